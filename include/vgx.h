@@ -1,0 +1,284 @@
+/*
+ * vgx.h -- C ABI of the MI355X VEGAS hot path (libvgx.so).
+ *
+ * The operations follow the thesis's statement of the problem:
+ *   - Monte Carlo integration with importance sampling and the VEGAS
+ *     adaptive separable grid (thesis Sec. "Monte Carlo integration",
+ *     "Importance sampling", "Adaptive Monte Carlo: VEGAS algorithm",
+ *     "Inverse transform method");
+ *   - PDF access in LHAPDF style, xf(x, Q^2) on a grid of knots with
+ *     subgrids, log-bicubic interpolation with a bilinear fallback (thesis
+ *     Sec. on LHAPDF and PDFFlow's design);
+ *   - the hadronic master formula sigma = sum_ab int dPhi L |M|^2 with the
+ *     pp -> t tbar sub-processes (thesis MadFlow chapter);
+ *   - a learned importance-sampling proposal trained with Adam (thesis
+ *     optimiser section); the coupling flow itself is not in the thesis
+ *     (Mueller et al. 2019, piecewise-linear couplings).
+ *
+ * General conventions
+ *   - Every pointer argument is named *_dev (device memory, caller-owned,
+ *     e.g. a torch tensor's storage) or *_host (host memory, caller-owned).
+ *     Contexts (vgx_vegas, vgx_pdf, vgx_flow) are library-owned and freed by
+ *     the matching *_destroy.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *     "async" only enqueue work on it; calls marked "sync" wait for it.
+ *   - Device arrays are structure-of-arrays: a [d][n] array holds dimension
+ *     j of sample i at j*n + i.
+ *   - Errors: a non-zero vgx_status; nothing is launched on VGX_EINVAL.
+ *     vgx_last_error() returns a thread-local message of the last failure.
+ *     No C++ exception crosses the ABI.
+ *   - The library runs on the device current at the call (hipSetDevice);
+ *     a context must be used on the device it was created on.
+ *   - Calls on one context are not thread-safe; distinct contexts are.
+ */
+#ifndef VGX_H
+#define VGX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The library is built with hidden visibility; everything declared here is
+ * exported. */
+#pragma GCC visibility push(default)
+
+typedef enum {
+  VGX_OK = 0,
+  VGX_EINVAL = 1,     /* invalid argument (sizes, pointers, kinds)          */
+  VGX_ENOMEM = 2,     /* device or pinned-host allocation failed            */
+  VGX_EDEVICE = 3,    /* a HIP runtime call failed                          */
+  VGX_ERANGE = 4,     /* PDF query outside the grid (outputs set to NaN)    */
+  VGX_ENUMERIC = 5,   /* non-finite iteration estimate (excluded)           */
+  VGX_EFALLBACK = 6,  /* flow worse than plain VEGAS or non-finite loss     */
+  VGX_ESTATE = 7      /* call not valid in the context's current state      */
+} vgx_status;
+
+/* Thread-local, NUL-terminated message describing the last error. */
+const char* vgx_last_error(void);
+
+/* Library version string (static storage). */
+const char* vgx_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Integrands                                                                */
+/* ------------------------------------------------------------------------ */
+enum {
+  VGX_GAUSS = 0,      /* prod_j N(x_j; c_j, s_j), normalised on R.
+                         params = [c_0..c_{d-1}, s_0..s_{d-1}]               */
+  VGX_GENZ_OSC = 1,   /* cos(2 pi w_1 + sum c_j x_j).  params = [w_1, c_0..] */
+  VGX_GENZ_PEAK = 2,  /* prod (c_j^-2 + (x_j - w_j)^2)^-1.
+                         params = [w_0..w_{d-1}, c_0..c_{d-1}]               */
+  VGX_TTBAR = 3       /* LO pp -> t tbar, d = 3, (tau, y, cos theta*) map.
+                         params = [sqrt_s, m_top, alpha_s, gev2_to_pb];
+                         needs a PDF context, evaluated at mu^2 = m_top^2    */
+};
+enum { VGX_F64 = 0, VGX_F32 = 1 };   /* integrand / output precision          */
+
+#define VGX_MAX_DIM 12
+#define VGX_MAX_BINS 256
+
+/* ------------------------------------------------------------------------ */
+/* PDF grids (LHAPDF-style, thesis PDF chapter)                              */
+/* ------------------------------------------------------------------------ */
+typedef struct vgx_pdf vgx_pdf;
+
+typedef struct {
+  int32_t n_x;              /* x knots, shared by all subgrids, >= 2        */
+  int32_t n_sub;            /* number of Q^2 subgrids, >= 1                  */
+  int32_t n_flav;           /* flavours, 1 .. 16                             */
+  const double* x_knots;    /* host [n_x], strictly ascending, > 0           */
+  const int32_t* nq_per_sub;/* host [n_sub], each >= 2                       */
+  const double* q2_knots;   /* host, subgrids concatenated, each strictly
+                               ascending; last knot of subgrid s equals the
+                               first knot of subgrid s+1                     */
+  const double* xf;         /* host, x*f node values, per subgrid the block
+                               [n_flav][n_q(s)][n_x], blocks concatenated    */
+} vgx_pdf_desc;
+
+/* Copy a grid to the device (sync).  The descriptor's host arrays may be
+ * freed after the call.  VGX_EINVAL on malformed knots. */
+vgx_status pdf_create(const vgx_pdf_desc* desc, void* stream, vgx_pdf** out);
+
+/* xf for every flavour at n points (async).
+ *   x_dev, q2_dev : device [n] FP64 query points.
+ *   out_dtype     : VGX_F64 or VGX_F32.
+ *   out_dev       : device [n_flav][n] of that type.
+ * Log-bicubic where the 4x4 stencil exists in both axes, bilinear
+ * otherwise; subgrid chosen with the upper one winning at a threshold.
+ * Queries outside the grid produce NaN in all flavours and are counted
+ * (see pdf_out_of_range).  n = 0 is a no-op. */
+vgx_status pdf_interp(const vgx_pdf* pdf, int64_t n, const double* x_dev, const double* q2_dev,
+                      int32_t out_dtype, void* out_dev, void* stream);
+
+/* Number of out-of-grid queries seen by pdf_interp since the last call of
+ * this function (sync on `stream`); resets the counter.  Returns VGX_ERANGE
+ * if the count is non-zero. */
+vgx_status pdf_out_of_range(vgx_pdf* pdf, void* stream, int64_t* count_host);
+
+/* Grid limits in x and Q^2. */
+vgx_status pdf_bounds(const vgx_pdf* pdf, double* xmin, double* xmax, double* q2min, double* q2max);
+
+void pdf_destroy(vgx_pdf* pdf);
+
+/* ------------------------------------------------------------------------ */
+/* VEGAS integration (thesis MC chapter)                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct vgx_vegas vgx_vegas;
+
+typedef struct {
+  int32_t kind;             /* VGX_GAUSS, VGX_GENZ_OSC, VGX_GENZ_PEAK, VGX_TTBAR */
+  int32_t dim;              /* 1 .. VGX_MAX_DIM (3 for VGX_TTBAR)               */
+  int32_t n_bins;           /* bins per dimension, 2 .. VGX_MAX_BINS            */
+  double alpha;             /* refinement damping exponent (e.g. 1.5)           */
+  uint64_t seed;            /* Philox key                                       */
+  uint32_t stream_id;       /* Philox stream (< 2^23)                           */
+  int32_t prec;             /* VGX_F64 or VGX_F32 integrand arithmetic          */
+  const double* params;     /* host, integrand parameters (see the kinds)       */
+  int32_t n_params;
+  const vgx_pdf* pdf;       /* VGX_TTBAR only; must outlive the context         */
+} vgx_vegas_cfg;
+
+typedef struct {
+  double mean;              /* E = S1/n                                          */
+  double var;               /* (S2/n - E^2)/(n-1), clamped at 0                  */
+  double s1, s2;            /* compensated sums of w = f J and w^2               */
+  int64_t n;
+} vgx_iter_result;
+
+/* Create a context with a uniform grid e[j][k] = k/N (sync). */
+vgx_status vegas_create(const vgx_vegas_cfg* cfg, void* stream, vgx_vegas** out);
+
+/* One iteration (sync): samples i = 0..n-1, uniforms from Philox with
+ * counter (i, iteration, stream_id, block) and key seed, mapped through the
+ * grid, w = f(x) J(u); accumulates the compensated sums and the per-bin
+ * histogram of w^2, appends (E, var) to the context's list of estimates
+ * (used by vegas_result) and stores the histogram for vegas_refine.
+ * VGX_ENUMERIC if the estimate is not finite (it is then excluded). */
+vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, vgx_iter_result* out_host);
+
+/* Same as vegas_iterate but async: the result stays on the device (read it
+ * with vegas_results).  Lets a caller queue many iterations back to back. */
+vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration);
+
+/* Refine the grid from the last iteration's histogram (async): Lepage's
+ * 3-point smoothing, damping r = ((1-p)/ln(1/p))^alpha, re-binning to equal
+ * shares of sum r.  A dimension with an all-zero histogram is unchanged. */
+vgx_status vegas_refine(vgx_vegas* v);
+
+/* Inverse-variance combination of the stored estimates and chi^2/dof
+ * (sync).  Non-finite estimates are skipped; a zero variance returns that
+ * estimate with sigma 0. */
+vgx_status vegas_result(vgx_vegas* v, double* mean, double* sigma, double* chi2_dof, int32_t* n_used);
+
+/* Copy up to cap stored per-iteration results to the host (sync). */
+vgx_status vegas_results(vgx_vegas* v, vgx_iter_result* out_host, int32_t cap, int32_t* count);
+
+/* Drop all stored estimates (the grid is kept). */
+vgx_status vegas_reset_results(vgx_vegas* v);
+
+/* Grid edges [dim][n_bins+1] and histogram [dim][n_bins] (sync copies). */
+vgx_status vegas_get_grid(vgx_vegas* v, double* edges_host);
+vgx_status vegas_set_grid(vgx_vegas* v, const double* edges_host);
+vgx_status vegas_get_hist(vgx_vegas* v, double* hist_host);
+
+/* Materialise samples first .. first+n-1 of an iteration (async):
+ * u_dev [dim][n] the Philox uniforms (the VEGAS unit-cube coordinates) and
+ * g_dev [n] = f(G(u)) J_G(u).  Either output may be NULL. */
+vgx_status vegas_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t iteration,
+                        double* u_dev, double* g_dev);
+
+/* Estimate from given unit-cube points y with proposal density q (sync):
+ * w = f(G(y)) J_G(y) exp(-logq).  y_dev [dim][n], logq_dev [n] (NULL means
+ * q = 1).  Appends the estimate like vegas_iterate; no histogram. */
+vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double* y_dev, const double* logq_dev,
+                                vgx_iter_result* out_host);
+
+/* Stream the context enqueues on. */
+void* vegas_stream(vgx_vegas* v);
+
+/* Kernel timing (for measurement): when enabled, HIP events on the
+ * context's stream bracket every fused sampling kernel; vegas_kernel_time
+ * (sync) returns the summed milliseconds and the number of launches since
+ * timing was enabled. */
+vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable);
+vgx_status vegas_kernel_time(vgx_vegas* v, double* ms_host, int64_t* launches_host);
+
+void vegas_destroy(vgx_vegas* v);
+
+/* ------------------------------------------------------------------------ */
+/* Batched integration: many contexts, one persistent launch per iteration    */
+/* ------------------------------------------------------------------------ */
+typedef struct vgx_batch vgx_batch;
+
+/* Bundle contexts (all on one device, non-TTBAR) into a batch.  The batch
+ * captures one iteration (persistent kernel + reductions + refinement) in
+ * a HIP graph on first use.  tile = samples per work item (0: autotuned),
+ * block = threads per workgroup (0: autotuned). */
+vgx_status batch_create(vgx_vegas* const* ctxs, int32_t count, const int64_t* n_samples_host,
+                        int32_t tile, int32_t block, void* stream, vgx_batch** out);
+
+/* One iteration of every integral (sync), refining every grid afterwards.
+ * out_host may be NULL; else [count] results. */
+vgx_status batch_iterate(vgx_batch* b, int32_t iteration, vgx_iter_result* out_host);
+
+/* Chosen tile / block after autotuning. */
+vgx_status batch_config(vgx_batch* b, int32_t* tile, int32_t* block);
+
+void batch_destroy(vgx_batch* b);
+
+/* ------------------------------------------------------------------------ */
+/* Coupling-flow proposal (neural importance sampling)                       */
+/* ------------------------------------------------------------------------ */
+typedef struct vgx_flow vgx_flow;
+
+/* Number of FP32 parameters of a flow.  Masks: layer l transforms the dims
+ * B_l = { j : bit k of j == (l even) }, k = (l/2) mod ceil(log2 dim),
+ * conditioned on the others A_l.  Per layer, in this order: W1 [H][|A|],
+ * b1 [H], W2 [H][H], b2 [H], W3 [|B| K][H], b3 [|B| K] (row-major).
+ * Supported: dim 2..VGX_MAX_DIM, n_bins = 32, hidden = 64, n_layers 1..8. */
+int64_t flow_num_params(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden);
+
+/* Create a flow with the given FP32 initial parameters (sync copy). */
+vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden,
+                       const float* params_host, int64_t n_params, void* stream, vgx_flow** out);
+
+/* Draw n points from the flow (async): u from Philox (counter (i,
+ * iteration, stream_id | 2^23, block), key seed), sampling direction
+ * (inverse piecewise-linear CDFs, layers L-1..0) -> y_dev [dim][n] and
+ * logq_dev [n] = ln q(y). */
+vgx_status flow_sample(vgx_flow* f, int64_t n, uint64_t seed, uint32_t stream_id, int32_t iteration,
+                       double* y_dev, double* logq_dev, void* stream);
+
+/* Density direction (async): y_dev [dim][n] -> u_dev [dim][n] (may be NULL),
+ * logq_dev [n]. */
+vgx_status flow_density(vgx_flow* f, int64_t n, const double* y_dev, double* u_dev, double* logq_dev,
+                        void* stream);
+
+/* Loss L = mean(g^2/q)/mean(g^2) over the batch (y_dev [dim][n] uniform
+ * points of the unit cube, g_dev [n]) and its gradient (sync).  grad_host
+ * [n_params] may be NULL. */
+vgx_status flow_loss_grad(vgx_flow* f, int64_t n, const double* y_dev, const double* g_dev,
+                          double* loss_host, float* grad_host);
+
+/* One training step: loss and gradient as above, then Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, learning rate lr) on the FP32 master weights.
+ * loss_host may be NULL (then async).  VGX_EFALLBACK if the loss is not
+ * finite (the weights are then left unchanged). */
+vgx_status flow_train_step(vgx_flow* f, int64_t n, const double* y_dev, const double* g_dev,
+                           float lr, double* loss_host);
+
+/* Adam alone on a given gradient (async; for tests): grad_dev [n_params]. */
+vgx_status flow_adam(vgx_flow* f, const float* grad_dev, float lr);
+
+vgx_status flow_get_params(vgx_flow* f, float* params_host, int64_t cap, int64_t* n_params);
+vgx_status flow_set_params(vgx_flow* f, const float* params_host, int64_t n_params);
+void flow_destroy(vgx_flow* f);
+
+#pragma GCC visibility pop
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VGX_H */

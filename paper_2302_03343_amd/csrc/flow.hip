@@ -1,0 +1,1211 @@
+// Coupling-flow proposal (neural importance sampling) on MFMA: sampling,
+// density, loss gradient and Adam.
+//
+// The thesis has no normalizing flow.  It gives the importance-sampling
+// estimator and its variance (MC chapter), the dense layer y = phi(W x + b)
+// and the activation table (deep-learning chapter), the training loop and
+// the Adam equations (optimiser section).  The coupling transform is the
+// piecewise-linear one of Mueller et al. (2019).  Per layer l the dims B_l
+// are transformed conditioned on the others A_l through a network
+// |A| -> 64 -> 64 -> |B| 32 (ReLU), softmax over 32 bins per B dim:
+//   density  direction: b = floor(32 z), z' = C_b + (32 z - b) Q_b,
+//   sampling direction: the inverse, b with C_b <= v < C_{b+1},
+//   log q += ln(32 Q_b) in both.
+// Loss: L = mean(g^2/q)/mean(g^2) on uniform points y of the VEGAS cube.
+//
+// MI355X design
+//   * one wave handles a tile of 32 samples; every matrix product of the
+//     networks runs on v_mfma_f32_32x32x16_bf16 in the transposed form
+//     (features x samples), BF16 operands, FP32 accumulation;
+//   * the D-layout of one product is fed to the next as the B operand
+//     without shuffles: 8 consecutive accumulator registers form one K=16
+//     step whose K order is a fixed permutation of the features, and the
+//     weights are packed once (after every Adam step) in that permuted
+//     order, so each A fragment is one 16-byte LDS read;
+//   * the 32 bin probabilities of a B dim for one sample sit in 2 lanes
+//     (l, l^32); softmax, cumulative sums and bin searches need one
+//     cross-lane exchange each;
+//   * training: a forward kernel (all layers, weights in LDS) saves each
+//     layer's input; per layer (last to first) a backward kernel recomputes
+//     the network, back-propagates to the layer input and writes BF16
+//     operand tiles, and a weight-gradient kernel reduces them with MFMA
+//     over the samples; one kernel reduces the per-workgroup partials in a
+//     fixed order and applies Adam to the FP32 master weights; log-
+//     densities and loss sums are FP64.
+#include "common.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <vector>
+
+namespace vgx {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int FH = 64;       // hidden width
+constexpr int FK = 32;       // bins
+constexpr int FL_MAX = 8;    // layers
+constexpr int FAB = 8;       // max |A|, |B|
+constexpr int FDM = VGX_MAX_DIM;
+constexpr int FBLOCK = 256;
+
+struct FlowLayerDesc {
+  int na, nb;
+  int a_idx[FAB], b_idx[FAB];
+  int p_off;     // first parameter of the layer in the flat master vector
+  int n_par;     // parameters of the layer
+  int fw_off;    // bf16 offset of the layer's forward pack [W1p | W2p | W3p]
+  int fw_len;
+  int bw_off;    // bf16 offset of the layer's backward pack [W3Tp | W2Tp | W1Tp]
+  int bw_len;
+  int bias_off;  // float offset of [b1 | b2 | b3]
+  int bias_len;
+};
+
+struct FlowDesc {
+  int d, L;
+  FlowLayerDesc l[FL_MAX];
+  int fw_total, bw_total, bias_total;  // sizes of the packed buffers
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x16 zero16() {
+  f32x16 z;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) z[v] = 0.0f;
+  return z;
+}
+
+// 8 consecutive accumulator registers as a B operand (K step half 0 or 1).
+__device__ __forceinline__ bf16x8 to_b(const f32x16& c, int half) {
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (__bf16)(half ? c[8 + e] : c[e]);
+  return r;
+}
+
+// row (feature / bin) held by register v of lane half h in a 32x32 D tile
+__device__ __forceinline__ int drow(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+__device__ __forceinline__ float xor32(float x) { return __shfl_xor(x, 32, 64); }
+
+// read / write z[j] for a runtime j without dynamic register indexing
+__device__ __forceinline__ float zget(const float (&z)[FDM], int j) {
+  float r = z[0];
+#pragma unroll
+  for (int k = 1; k < FDM; ++k) r = (k == j) ? z[k] : r;
+  return r;
+}
+__device__ __forceinline__ void zset(float (&z)[FDM], int j, float v) {
+#pragma unroll
+  for (int k = 0; k < FDM; ++k) z[k] = (k == j) ? v : z[k];
+}
+
+struct LayerLds {
+  const bf16x8* w1p;   // [2][32][2]
+  const bf16x8* w2p;   // [2][4][32][2]
+  const bf16x8* w3p;   // [nb][4][32][2]
+  const float* b1;
+  const float* b2;
+  const float* b3;
+};
+
+__device__ __forceinline__ LayerLds layer_lds(const unsigned short* fw, const float* bias, const FlowLayerDesc& L,
+                                              int fw_base, int bias_base) {
+  LayerLds r;
+  const unsigned short* p = fw + (L.fw_off - fw_base);
+  r.w1p = (const bf16x8*)p;
+  r.w2p = (const bf16x8*)(p + 1024);
+  r.w3p = (const bf16x8*)(p + 1024 + 4096);
+  const float* b = bias + (L.bias_off - bias_base);
+  r.b1 = b;
+  r.b2 = b + FH;
+  r.b3 = b + 2 * FH;
+  return r;
+}
+
+// Network forward of one layer for the wave's 32 samples (transposed form).
+template <int NBM>
+__device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, const LayerLds& W, f32x16 (&h1)[2],
+                                        f32x16 (&h2)[2], f32x16 (&lg)[NBM]) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  bf16x8 bz;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) bz[e] = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    h1[t] = mfma(W.w1p[(t * 32 + i) * 2 + h], bz, zero16());
+#pragma unroll
+    for (int v = 0; v < 16; ++v) h1[t][v] = fmaxf(h1[t][v] + W.b1[32 * t + drow(v, h)], 0.0f);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16 acc = zero16();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], to_b(h1[kk >> 1], kk & 1), acc);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v] + W.b2[32 * t + drow(v, h)], 0.0f);
+    h2[t] = acc;
+  }
+#pragma unroll
+  for (int t = 0; t < NBM; ++t) {
+    if (t < nb) {
+      f32x16 acc = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], to_b(h2[kk >> 1], kk & 1), acc);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] += W.b3[32 * t + drow(v, h)];
+      lg[t] = acc;
+    }
+  }
+}
+
+// in-place softmax over the 32 bins of one B dim (16 here, 16 in lane^32)
+__device__ __forceinline__ void softmax32(f32x16& q) {
+  float m = q[0];
+#pragma unroll
+  for (int v = 1; v < 16; ++v) m = fmaxf(m, q[v]);
+  m = fmaxf(m, xor32(m));
+  float s = 0.0f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    q[v] = expf(q[v] - m);
+    s += q[v];
+  }
+  s += xor32(s);
+  const float inv = 1.0f / s;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) q[v] *= inv;
+}
+
+// density direction for one B dim: returns z', sets the bin, alpha, Q_b
+__device__ __forceinline__ float cdf_fwd(const f32x16& q, float z, int& b, float& al, float& qb) {
+  const int h = (threadIdx.x >> 5) & 1;
+  const float t = z * (float)FK;
+  int bb = (int)floorf(t);
+  bb = bb < 0 ? 0 : (bb > FK - 1 ? FK - 1 : bb);
+  al = t - (float)bb;
+  float lt = 0.0f, qq = 0.0f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int k = drow(v, h);
+    lt += (k < bb) ? q[v] : 0.0f;
+    qq += (k == bb) ? q[v] : 0.0f;
+  }
+  lt += xor32(lt);
+  qq += xor32(qq);
+  b = bb;
+  qb = qq;
+  return lt + al * qq;
+}
+
+// sampling direction for one B dim: returns z, sets the bin and Q_b
+__device__ __forceinline__ float cdf_inv(const f32x16& q, float v, int& b, float& qb) {
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  float cs[4], ps[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) cs[g] = (q[4 * g] + q[4 * g + 1]) + (q[4 * g + 2] + q[4 * g + 3]);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) ps[g] = xor32(cs[g]);
+  // chunks c = 2g + h' hold bins 4c .. 4c+3; scan them in order
+  float acc = 0.0f, base = 0.0f;
+  int cstar = 7;
+  bool found = false;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const float sc = ((c & 1) == h) ? cs[c >> 1] : ps[c >> 1];
+    if (!found && (v < acc + sc || c == 7)) {
+      found = true;
+      cstar = c;
+      base = acc;
+    }
+    acc += sc;
+  }
+  // the owner of chunk c* locates the bin inside it
+  int bb = 4 * cstar + 3;
+  float cb = base, qq = 0.0f;
+  if ((cstar & 1) == h) {
+    const int g = cstar >> 1;
+    float run = base;
+    bool got = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float qr = q[4 * g + r];
+      if (!got && (v < run + qr || r == 3)) {
+        got = true;
+        bb = 4 * cstar + r;
+        cb = run;
+        qq = qr;
+      }
+      run += qr;
+    }
+  }
+  const int src = (lane & 31) + 32 * (cstar & 1);
+  bb = __shfl(bb, src, 64);
+  cb = __shfl(cb, src, 64);
+  qq = __shfl(qq, src, 64);
+  b = bb;
+  qb = qq;
+  float frac = (v - cb) / qq;
+  frac = frac < 0.0f ? 0.0f : (frac > 1.0f ? 1.0f : frac);
+  return ((float)bb + frac) * (1.0f / (float)FK);
+}
+
+// copy n 16-byte chunks global -> LDS (whole workgroup)
+__device__ __forceinline__ void copy16(void* dst, const void* src, int bytes) {
+  const int4* s = (const int4*)src;
+  int4* d = (int4*)dst;
+  for (int k = threadIdx.x; k < bytes / 16; k += blockDim.x) d[k] = s[k];
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernels: MODE 0 density (eval), 1 density (training), 2 sampling.
+// ---------------------------------------------------------------------------
+struct FwdArgs {
+  int64_t n;
+  const double* yin;    // density: [d][n]
+  const double* g;      // training: [n]
+  double* out;          // density: u [d][n] (nullable); sampling: y [d][n]
+  double* logq;         // [n]
+  float* zsave;         // training: [L][d][n]
+  double* rsave;        // training: [n]
+  double* partials;     // training: [grid][4]
+  uint32_t it, sid, k0, k1;  // sampling: Philox counter / key
+};
+
+template <int NBM, int MODE>
+__global__ __launch_bounds__(FBLOCK) void k_flow_fwd(const FlowDesc* __restrict__ Dp, FwdArgs a, const unsigned short* __restrict__ fw,
+                                                     const float* __restrict__ bias) {
+  extern __shared__ __align__(16) unsigned char flds[];
+  const FlowDesc& D = *Dp;
+  unsigned short* sfw = (unsigned short*)flds;
+  float* sb = (float*)(flds + D.fw_total * 2);
+  copy16(sfw, fw, D.fw_total * 2);
+  copy16(sb, bias, D.bias_total * 4);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+  const int wave = blockIdx.x * (FBLOCK / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (FBLOCK / 64);
+  const int64_t ntiles = (a.n + 31) / 32;
+  Comp sr, sg;
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    const int64_t i = t * 32 + s;
+    const bool valid = i < a.n;
+    float z[FDM];
+#pragma unroll
+    for (int j = 0; j < FDM; ++j) z[j] = 0.5f;
+    if (MODE == 2) {
+#pragma unroll
+      for (int bk = 0; bk < (FDM + 3) / 4; ++bk) {
+        if (4 * bk < D.d) {
+          const u32x4 w = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), a.it, (a.sid << 8) | (uint32_t)bk,
+                                        a.k0, a.k1);
+          const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (4 * bk + e < FDM) z[4 * bk + e] = (float)word_to_unit(ww[e]);
+        }
+      }
+    } else if (valid) {
+#pragma unroll
+      for (int j = 0; j < FDM; ++j)
+        if (j < D.d) z[j] = (float)a.yin[(int64_t)j * a.n + i];
+    }
+    double lq = 0.0;
+    for (int step = 0; step < D.L; ++step) {
+      const int l = (MODE == 2) ? D.L - 1 - step : step;
+      const FlowLayerDesc& L = D.l[l];
+      if (MODE == 1 && valid && h == 0) {
+#pragma unroll
+        for (int j = 0; j < FDM; ++j)
+          if (j < D.d) a.zsave[((int64_t)l * D.d + j) * a.n + i] = z[j];
+      }
+      float za[FAB];
+#pragma unroll
+      for (int e = 0; e < FAB; ++e) za[e] = (e < L.na) ? zget(z, L.a_idx[e]) : 0.0f;
+      const LayerLds W = layer_lds(sfw, sb, L, 0, 0);
+      f32x16 h1[2], h2[2], lg[NBM];
+      mlp_fwd<NBM>(za, L.na, L.nb, W, h1, h2, lg);
+#pragma unroll
+      for (int jb = 0; jb < NBM; ++jb) {
+        if (jb < L.nb) {
+          softmax32(lg[jb]);
+          const int j = L.b_idx[jb];
+          const float zj = zget(z, j);
+          int b;
+          float qb, al;
+          const float zn = (MODE == 2) ? cdf_inv(lg[jb], zj, b, qb) : cdf_fwd(lg[jb], zj, b, al, qb);
+          zset(z, j, zn);
+          lq += (double)logf((float)FK * qb);
+        }
+      }
+    }
+    if (valid && h == 0) {
+      a.logq[i] = lq;
+      if (a.out) {
+#pragma unroll
+        for (int j = 0; j < FDM; ++j)
+          if (j < D.d) a.out[(int64_t)j * a.n + i] = (double)z[j];
+      }
+      if (MODE == 1) {
+        const double gi = a.g[i];
+        const double r = gi * gi * exp(-lq);
+        a.rsave[i] = r;
+        sr.add(r);
+        sg.add(gi * gi);
+      }
+    }
+  }
+  if (MODE == 1) {
+    __shared__ double red[4][FBLOCK / 64];
+    const double v0 = wave_sum(sr.s), v1 = wave_sum(sr.c), v2 = wave_sum(sg.s), v3 = wave_sum(sg.c);
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wv] = v0; red[1][wv] = v1; red[2][wv] = v2; red[3][wv] = v3; }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      double acc = 0.0;
+      for (int k = 0; k < FBLOCK / 64; ++k) acc += red[threadIdx.x][k];
+      a.partials[blockIdx.x * 4 + threadIdx.x] = acc;
+    }
+  }
+}
+
+// loss L = sum r / sum g^2, scale = -1/sum g^2 (fixed-order reduction)
+__global__ __launch_bounds__(64) void k_flow_loss(const double* __restrict__ partials, int rows, double* __restrict__ out) {
+  __shared__ double sh[4];
+  if (threadIdx.x < 4) {
+    Comp c;
+    for (int r = 0; r < rows; ++r) c.add(partials[r * 4 + threadIdx.x]);
+    sh[threadIdx.x] = c.value();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double sr = sh[0] + sh[1], sg = sh[2] + sh[3];
+    const double L = sr / sg;
+    out[0] = L;
+    out[1] = -1.0 / sg;
+    out[2] = (isfinite(L) && sg > 0.0) ? 1.0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of one layer (data gradients + BF16 operand tiles for dW).
+// Scratch rows per 32-sample tile: [zA 32][h1 64][h2 64][dpre1 64][dpre2 64][dlogit 32 nb].
+// ---------------------------------------------------------------------------
+struct BwdArgs {
+  int64_t n;
+  int layer;
+  const float* zin;     // [d][n] input of this layer (saved by the forward)
+  const float* dzout;   // [d][n] gradient w.r.t. the layer output (null: zero)
+  float* dzin;          // [d][n] gradient w.r.t. the layer input
+  const double* rsave;  // [n]
+  const double* loss;   // [3]: L, scale, ok
+  unsigned short* scr;  // bf16 scratch
+  int srows;            // scratch rows per tile
+};
+
+__device__ __forceinline__ void put_tile(unsigned short* base, int row0, const f32x16& c, int s, int h) {
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const __bf16 x = (__bf16)c[v];
+    base[(row0 + drow(v, h)) * 32 + s] = *(const unsigned short*)&x;
+  }
+}
+
+template <int NBM>
+__global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict__ Dp, BwdArgs a, const unsigned short* __restrict__ fw,
+                                                     const unsigned short* __restrict__ bw,
+                                                     const float* __restrict__ bias) {
+  extern __shared__ __align__(16) unsigned char flds[];
+  const FlowDesc& D = *Dp;
+  const FlowLayerDesc& L = D.l[a.layer];
+  unsigned short* sfw = (unsigned short*)flds;
+  unsigned short* sbw = sfw + L.fw_len;
+  float* sb = (float*)(sbw + L.bw_len);
+  copy16(sfw, fw + L.fw_off, L.fw_len * 2);
+  copy16(sbw, bw + L.bw_off, L.bw_len * 2);
+  copy16(sb, bias + L.bias_off, L.bias_len * 4);
+  __syncthreads();
+  const LayerLds W = layer_lds(sfw, sb, L, L.fw_off, L.bias_off);
+  const bf16x8* w3t = (const bf16x8*)sbw;                         // [2][2nb][32][2]
+  const bf16x8* w2t = (const bf16x8*)(sbw + L.nb * 2048);         // [2][4][32][2]
+  const bf16x8* w1t = (const bf16x8*)(sbw + L.nb * 2048 + 4096);  // [1][4][32][2]
+  const double scale = a.loss[1];
+  const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+  const int wave = blockIdx.x * (FBLOCK / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (FBLOCK / 64);
+  const int64_t ntiles = (a.n + 31) / 32;
+  const int na = L.na, nb = L.nb;
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    const int64_t i = t * 32 + s;
+    const bool valid = i < a.n;
+    float z[FDM], gz[FDM];
+#pragma unroll
+    for (int j = 0; j < FDM; ++j) { z[j] = 0.5f; gz[j] = 0.0f; }
+    float dlq = 0.0f;
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < FDM; ++j) {
+        if (j < D.d) {
+          z[j] = a.zin[(int64_t)j * a.n + i];
+          if (a.dzout) gz[j] = a.dzout[(int64_t)j * a.n + i];
+        }
+      }
+      dlq = (float)(a.rsave[i] * scale);
+    }
+    float za[FAB];
+#pragma unroll
+    for (int e = 0; e < FAB; ++e) za[e] = (e < na) ? zget(z, L.a_idx[e]) : 0.0f;
+    f32x16 h1[2], h2[2], lg[NBM];
+    mlp_fwd<NBM>(za, na, nb, W, h1, h2, lg);
+    float dz[FDM];
+#pragma unroll
+    for (int j = 0; j < FDM; ++j) dz[j] = gz[j];
+    // bins, dQ and dlogit per transformed dim
+#pragma unroll
+    for (int jb = 0; jb < NBM; ++jb) {
+      if (jb < nb) {
+        softmax32(lg[jb]);
+        const int j = L.b_idx[jb];
+        int b;
+        float al, qb;
+        cdf_fwd(lg[jb], zget(z, j), b, al, qb);
+        const float g_out = zget(gz, j);
+        float dq[16];
+        float sdot = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int k = drow(v, h);
+          dq[v] = g_out * ((k < b) ? 1.0f : ((k == b) ? al : 0.0f)) + ((k == b) ? dlq / qb : 0.0f);
+          sdot += lg[jb][v] * dq[v];
+        }
+        sdot += xor32(sdot);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) lg[jb][v] = lg[jb][v] * (dq[v] - sdot);  // dlogit
+        zset(dz, j, g_out * (float)FK * qb);
+      }
+    }
+    // dh2 = W3^T dlogit, masked by relu'
+    f32x16 d2[2];
+#pragma unroll
+    for (int to = 0; to < 2; ++to) {
+      f32x16 acc = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 2 * NBM; ++kk)
+        if (kk < 2 * nb) acc = mfma(w3t[((to * 2 * nb + kk) * 32 + s) * 2 + h], to_b(lg[kk >> 1], kk & 1), acc);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = h2[to][v] > 0.0f ? acc[v] : 0.0f;
+      d2[to] = acc;
+    }
+    // dh1 = W2^T dpre2, masked
+    f32x16 d1[2];
+#pragma unroll
+    for (int to = 0; to < 2; ++to) {
+      f32x16 acc = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], to_b(d2[kk >> 1], kk & 1), acc);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = h1[to][v] > 0.0f ? acc[v] : 0.0f;
+      d1[to] = acc;
+    }
+    // dzA = W1^T dpre1: rows a = 4h + r in registers 0..3
+    f32x16 d0 = zero16();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d0 = mfma(w1t[(kk * 32 + s) * 2 + h], to_b(d1[kk >> 1], kk & 1), d0);
+    float dza[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float mine = d0[r], other = xor32(d0[r]);
+      dza[r] = h == 0 ? mine : other;
+      dza[4 + r] = h == 0 ? other : mine;
+    }
+#pragma unroll
+    for (int e = 0; e < FAB; ++e)
+      if (e < na) {
+        const int j = L.a_idx[e];
+        zset(dz, j, zget(dz, j) + dza[e]);
+      }
+    if (valid && h == 0) {
+#pragma unroll
+      for (int j = 0; j < FDM; ++j)
+        if (j < D.d) a.dzin[(int64_t)j * a.n + i] = dz[j];
+    }
+    // BF16 operand tiles for the weight gradients (invalid samples carry
+    // zero deltas, so they add nothing)
+    unsigned short* base = a.scr + (size_t)t * a.srows * 32;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 x = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
+      base[(8 * h + e) * 32 + s] = *(const unsigned short*)&x;
+    }
+    put_tile(base, 32, h1[0], s, h);
+    put_tile(base, 64, h1[1], s, h);
+    put_tile(base, 96, h2[0], s, h);
+    put_tile(base, 128, h2[1], s, h);
+    put_tile(base, 160, d1[0], s, h);
+    put_tile(base, 192, d1[1], s, h);
+    put_tile(base, 224, d2[0], s, h);
+    put_tile(base, 256, d2[1], s, h);
+#pragma unroll
+    for (int jb = 0; jb < NBM; ++jb)
+      if (jb < nb) put_tile(base, 288 + 32 * jb, lg[jb], s, h);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradients of one layer: dW3 = dlogit h2^T, dW2 = dpre2 h1^T,
+// dW1 = dpre1 zA^T (K = samples, MFMA), biases = row sums of the deltas.
+// Each workgroup writes its partial of the layer's parameter block.
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+  int64_t n;
+  int layer;
+  const unsigned short* scr;
+  int srows;
+  float* gpart;   // [grid][n_par] partials of this layer
+};
+
+__device__ __forceinline__ bf16x8 ld_frag(const unsigned short* base, int row, int kk, int h) {
+  return *(const bf16x8*)(base + row * 32 + 16 * kk + 8 * h);
+}
+
+__device__ __forceinline__ float frag_sum(const bf16x8& x) {
+  float s = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) s += (float)x[e];
+  return s;
+}
+
+template <int MT, int NT>
+__device__ __forceinline__ void wgrad_gemm(const unsigned short* scr, int srows, int64_t ntiles, int wave, int nwaves,
+                                           int arow0, int brow0, int mt, int nt, f32x16 (&acc)[MT][NT],
+                                           float (&bsum)[MT]) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    bsum[m] = 0.0f;
+#pragma unroll
+    for (int nn = 0; nn < NT; ++nn) acc[m][nn] = zero16();
+  }
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    const unsigned short* base = scr + (size_t)t * srows * 32;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      bf16x8 bf[NT];
+#pragma unroll
+      for (int nn = 0; nn < NT; ++nn)
+        if (nn < nt) bf[nn] = ld_frag(base, brow0 + 32 * nn + i, kk, h);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        if (m < mt) {
+          const bf16x8 af = ld_frag(base, arow0 + 32 * m + i, kk, h);
+          bsum[m] += frag_sum(af);
+#pragma unroll
+          for (int nn = 0; nn < NT; ++nn)
+            if (nn < nt) acc[m][nn] = mfma(af, bf[nn], acc[m][nn]);
+        }
+      }
+    }
+  }
+}
+
+// add a D tile (rows = output rows of W, cols = input columns) into the LDS
+// parameter block W[row][col] with row stride ld, columns < ncol only
+__device__ __forceinline__ void add_tile(float* blk, int ld, int row0, int col0, int ncol, const f32x16& c) {
+  const int lane = threadIdx.x & 63, j = lane & 31, h = lane >> 5;
+  if (col0 + j < ncol) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) atomicAdd(&blk[(row0 + drow(v, h)) * ld + col0 + j], c[v]);
+  }
+}
+
+template <int NBM>
+__global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restrict__ Dp, WgradArgs a) {
+  extern __shared__ __align__(16) unsigned char flds[];
+  const FlowLayerDesc& L = Dp->l[a.layer];
+  float* blk = (float*)flds;  // the layer's parameter block
+  for (int k = threadIdx.x; k < L.n_par; k += FBLOCK) blk[k] = 0.0f;
+  __syncthreads();
+  const int na = L.na, nb = L.nb;
+  const int oW1 = 0, ob1 = FH * na, oW2 = ob1 + FH, ob2 = oW2 + FH * FH, oW3 = ob2 + FH, ob3 = oW3 + nb * FK * FH;
+  const int wave = blockIdx.x * (FBLOCK / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (FBLOCK / 64);
+  const int64_t ntiles = (a.n + 31) / 32;
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  {  // dW3 [o][f], db3
+    f32x16 acc[NBM][2];
+    float bs[NBM];
+    wgrad_gemm<NBM, 2>(a.scr, a.srows, ntiles, wave, nwaves, 288, 96, nb, 2, acc, bs);
+#pragma unroll
+    for (int m = 0; m < NBM; ++m)
+      if (m < nb) {
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn) add_tile(blk + oW3, FH, 32 * m, 32 * nn, FH, acc[m][nn]);
+        const float tot = bs[m] + xor32(bs[m]);
+        if (h == 0) atomicAdd(&blk[ob3 + 32 * m + i], tot);
+      }
+  }
+  {  // dW2 [f][f'], db2
+    f32x16 acc[2][2];
+    float bs[2];
+    wgrad_gemm<2, 2>(a.scr, a.srows, ntiles, wave, nwaves, 224, 32, 2, 2, acc, bs);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+      for (int nn = 0; nn < 2; ++nn) add_tile(blk + oW2, FH, 32 * m, 32 * nn, FH, acc[m][nn]);
+      const float tot = bs[m] + xor32(bs[m]);
+      if (h == 0) atomicAdd(&blk[ob2 + 32 * m + i], tot);
+    }
+  }
+  {  // dW1 [f][a], db1
+    f32x16 acc[2][1];
+    float bs[2];
+    wgrad_gemm<2, 1>(a.scr, a.srows, ntiles, wave, nwaves, 160, 0, 2, 1, acc, bs);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      add_tile(blk + oW1, na, 32 * m, 0, na, acc[m][0]);
+      const float tot = bs[m] + xor32(bs[m]);
+      if (h == 0) atomicAdd(&blk[ob1 + 32 * m + i], tot);
+    }
+  }
+  __syncthreads();
+  float* out = a.gpart + (size_t)blockIdx.x * L.n_par;
+  for (int k = threadIdx.x; k < L.n_par; k += FBLOCK) out[k] = blk[k];
+}
+
+// ---------------------------------------------------------------------------
+// Gradient reduction (fixed order over workgroup partials) + Adam.
+// ---------------------------------------------------------------------------
+struct AdamArgs {
+  int64_t n_par;
+  int rows;              // workgroup partial rows per layer
+  const float* gpart;    // per layer: [rows][n_par_l] at offset p_off * rows
+  const float* grad_in;  // alternative: a full gradient (flow_adam)
+  float* grad_out;       // reduced gradient (nullable)
+  float* master;
+  float* m;
+  float* v;
+  const double* loss;    // [3]; ok flag at [2] (nullable = always ok)
+  float lr, beta1, beta2, eps;
+  int step;              // t >= 1
+  int do_adam;
+};
+
+__global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ Dp, AdamArgs a) {
+  const FlowDesc& D = *Dp;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.n_par) return;
+  float g;
+  if (a.grad_in) {
+    g = a.grad_in[p];
+  } else {
+    int l = 0;
+    while (l + 1 < D.L && p >= D.l[l + 1].p_off) ++l;
+    const int q = (int)(p - D.l[l].p_off);
+    const int np = D.l[l].n_par;
+    const float* base = a.gpart + (size_t)D.l[l].p_off * a.rows;
+    float acc = 0.0f, c = 0.0f;
+    for (int r = 0; r < a.rows; ++r) {  // compensated, fixed order
+      const float y = base[(size_t)r * np + q] - c;
+      const float t = acc + y;
+      c = (t - acc) - y;
+      acc = t;
+    }
+    g = acc;
+  }
+  if (a.grad_out) a.grad_out[p] = g;
+  if (!a.do_adam) return;
+  if (a.loss && a.loss[2] == 0.0) return;  // non-finite loss: leave the weights
+  const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * g;
+  const float v = a.beta2 * a.v[p] + (1.0f - a.beta2) * g * g;
+  a.m[p] = m;
+  a.v[p] = v;
+  const float mh = m / (1.0f - powf(a.beta1, (float)a.step));
+  const float vh = v / (1.0f - powf(a.beta2, (float)a.step));
+  a.master[p] -= a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+// master FP32 weights -> permuted BF16 packs and FP32 bias pack
+__global__ __launch_bounds__(256) void k_flow_pack(const float* __restrict__ master, const int* __restrict__ fw_src,
+                                                   int fw_total, const int* __restrict__ bw_src, int bw_total,
+                                                   const int* __restrict__ b_src, int b_total,
+                                                   unsigned short* __restrict__ fw, unsigned short* __restrict__ bw,
+                                                   float* __restrict__ bias) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < fw_total) {
+    const int s = fw_src[k];
+    const __bf16 x = (__bf16)(s >= 0 ? master[s] : 0.0f);
+    fw[k] = *(const unsigned short*)&x;
+  }
+  if (k < bw_total) {
+    const int s = bw_src[k];
+    const __bf16 x = (__bf16)(s >= 0 ? master[s] : 0.0f);
+    bw[k] = *(const unsigned short*)&x;
+  }
+  if (k < b_total) bias[k] = master[b_src[k]];
+}
+
+}  // namespace vgx
+
+using namespace vgx;
+
+struct vgx_flow {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int dim = 0, L = 0, n_bins = 0, hidden = 0;
+  int nbm = 1;            // template bound on |B|
+  int64_t n_par = 0;
+  FlowDesc D{};
+  FlowDesc* d_desc = nullptr;   // device copy read by the kernels
+  float* master = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  float* grad = nullptr;
+  unsigned short* fw = nullptr;
+  unsigned short* bw = nullptr;
+  float* bias = nullptr;
+  int* fw_src = nullptr;
+  int* bw_src = nullptr;
+  int* b_src = nullptr;
+  double* loss = nullptr;       // [3]
+  double* partials = nullptr;   // [max grid][4]
+  int step = 0;
+  // training scratch, grown on demand
+  int64_t cap_n = 0;
+  float* zsave = nullptr;       // [L][d][n]
+  double* rsave = nullptr;      // [n]
+  double* lqsave = nullptr;     // [n]
+  float* dz[2] = {nullptr, nullptr};  // [d][n]
+  unsigned short* scr = nullptr;
+  float* gpart = nullptr;       // [n_par * grid_w]
+  int grid_w = 0;
+  int srows = 0;
+  double* pinned = nullptr;
+};
+
+namespace {
+
+int n_bits(int d) {
+  int b = 0;
+  while ((1 << b) < d) ++b;
+  return b < 1 ? 1 : b;
+}
+
+vgx_status build_desc(int dim, int L, FlowDesc& D, std::vector<int>& fws, std::vector<int>& bws,
+                      std::vector<int>& bs, int64_t& n_par, int& nbm) {
+  D = FlowDesc{};
+  D.d = dim;
+  D.L = L;
+  const int nbit = n_bits(dim);
+  int p = 0;
+  nbm = 1;
+  fws.clear();
+  bws.clear();
+  bs.clear();
+  for (int l = 0; l < L; ++l) {
+    FlowLayerDesc& Ld = D.l[l];
+    const int k = (l / 2) % nbit;
+    const int par = (l % 2 == 0) ? 1 : 0;
+    Ld.na = Ld.nb = 0;
+    for (int j = 0; j < dim; ++j) {
+      if (((j >> k) & 1) == par) {
+        if (Ld.nb >= FAB) { set_error("flow: |B| > %d", FAB); return VGX_EINVAL; }
+        Ld.b_idx[Ld.nb++] = j;
+      } else {
+        if (Ld.na >= FAB) { set_error("flow: |A| > %d", FAB); return VGX_EINVAL; }
+        Ld.a_idx[Ld.na++] = j;
+      }
+    }
+    if (Ld.na == 0 || Ld.nb == 0) { set_error("flow: dimension too small for the masks"); return VGX_EINVAL; }
+    const int na = Ld.na, nb = Ld.nb;
+    while (nbm < nb) nbm *= 2;
+    const int oW1 = p, ob1 = oW1 + FH * na, oW2 = ob1 + FH, ob2 = oW2 + FH * FH, oW3 = ob2 + FH,
+              ob3 = oW3 + nb * FK * FH;
+    Ld.p_off = p;
+    Ld.n_par = FH * na + FH + FH * FH + FH + nb * FK * FH + nb * FK;
+    p += Ld.n_par;
+    // forward pack
+    Ld.fw_off = (int)fws.size();
+    for (int t = 0; t < 2; ++t)
+      for (int i = 0; i < 32; ++i)
+        for (int h = 0; h < 2; ++h)
+          for (int e = 0; e < 8; ++e) {
+            const int slot = 8 * h + e;
+            fws.push_back(slot < na ? oW1 + (32 * t + i) * na + slot : -1);
+          }
+    for (int t = 0; t < 2; ++t)
+      for (int kk = 0; kk < 4; ++kk)
+        for (int i = 0; i < 32; ++i)
+          for (int h = 0; h < 2; ++h)
+            for (int e = 0; e < 8; ++e) {
+              const int fin = 16 * kk + 8 * (e >> 2) + 4 * h + (e & 3);
+              fws.push_back(oW2 + (32 * t + i) * FH + fin);
+            }
+    for (int t = 0; t < nb; ++t)
+      for (int kk = 0; kk < 4; ++kk)
+        for (int i = 0; i < 32; ++i)
+          for (int h = 0; h < 2; ++h)
+            for (int e = 0; e < 8; ++e) {
+              const int fin = 16 * kk + 8 * (e >> 2) + 4 * h + (e & 3);
+              fws.push_back(oW3 + (32 * t + i) * FH + fin);
+            }
+    Ld.fw_len = (int)fws.size() - Ld.fw_off;
+    // backward pack: W3^T, W2^T, W1^T
+    Ld.bw_off = (int)bws.size();
+    for (int t = 0; t < 2; ++t)
+      for (int kk = 0; kk < 2 * nb; ++kk)
+        for (int i = 0; i < 32; ++i)
+          for (int h = 0; h < 2; ++h)
+            for (int e = 0; e < 8; ++e) {
+              const int o = 16 * kk + 8 * (e >> 2) + 4 * h + (e & 3);
+              bws.push_back(oW3 + o * FH + 32 * t + i);
+            }
+    for (int t = 0; t < 2; ++t)
+      for (int kk = 0; kk < 4; ++kk)
+        for (int i = 0; i < 32; ++i)
+          for (int h = 0; h < 2; ++h)
+            for (int e = 0; e < 8; ++e) {
+              const int f = 16 * kk + 8 * (e >> 2) + 4 * h + (e & 3);
+              bws.push_back(oW2 + f * FH + 32 * t + i);
+            }
+    for (int kk = 0; kk < 4; ++kk)
+      for (int i = 0; i < 32; ++i)
+        for (int h = 0; h < 2; ++h)
+          for (int e = 0; e < 8; ++e) {
+            const int f = 16 * kk + 8 * (e >> 2) + 4 * h + (e & 3);
+            bws.push_back(i < na ? oW1 + f * na + i : -1);
+          }
+    Ld.bw_len = (int)bws.size() - Ld.bw_off;
+    // biases
+    Ld.bias_off = (int)bs.size();
+    for (int f = 0; f < FH; ++f) bs.push_back(ob1 + f);
+    for (int f = 0; f < FH; ++f) bs.push_back(ob2 + f);
+    for (int o = 0; o < nb * FK; ++o) bs.push_back(ob3 + o);
+    Ld.bias_len = (int)bs.size() - Ld.bias_off;
+  }
+  D.fw_total = (int)fws.size();
+  D.bw_total = (int)bws.size();
+  D.bias_total = (int)bs.size();
+  n_par = p;
+  return VGX_OK;
+}
+
+size_t fwd_lds(const vgx_flow* f) { return (size_t)f->D.fw_total * 2 + (size_t)f->D.bias_total * 4; }
+
+vgx_status pack(vgx_flow* f) {
+  const int tot = f->D.fw_total > f->D.bw_total ? f->D.fw_total : f->D.bw_total;
+  hipLaunchKernelGGL(k_flow_pack, dim3((tot + 255) / 256), dim3(256), 0, f->stream, f->master, f->fw_src,
+                     f->D.fw_total, f->bw_src, f->D.bw_total, f->b_src, f->D.bias_total, f->fw, f->bw, f->bias);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+int fwd_grid(const vgx_flow* f, int64_t n) {
+  const int64_t tiles = (n + 31) / 32;
+  const int64_t waves_per_wg = FBLOCK / 64;
+  int64_t g = (tiles + waves_per_wg - 1) / waves_per_wg;
+  const int64_t cap = (int64_t)device_cus() * 2;
+  if (g > cap) g = cap;
+  return (int)(g < 1 ? 1 : g);
+}
+
+template <int MODE>
+vgx_status launch_fwd(vgx_flow* f, int grid, const FwdArgs& a, hipStream_t st) {
+  const size_t lds = fwd_lds(f);
+#define L_(NB)                                                                                        \
+  case NB:                                                                                            \
+    hipFuncSetAttribute((const void*)k_flow_fwd<NB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                        (int)lds);                                                                    \
+    hipLaunchKernelGGL((k_flow_fwd<NB, MODE>), dim3(grid), dim3(FBLOCK), lds, st, f->d_desc, a, f->fw, f->bias); \
+    break;
+  switch (f->nbm) { L_(1) L_(2) L_(4) L_(8) default: set_error("flow: bad |B| bound"); return VGX_EINVAL; }
+#undef L_
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+vgx_status ensure_train(vgx_flow* f, int64_t n) {
+  if (n <= f->cap_n) return VGX_OK;
+  hipFree(f->zsave); hipFree(f->rsave); hipFree(f->lqsave); hipFree(f->dz[0]); hipFree(f->dz[1]); hipFree(f->scr);
+  hipFree(f->gpart);
+  f->zsave = nullptr; f->rsave = nullptr; f->lqsave = nullptr; f->dz[0] = f->dz[1] = nullptr; f->scr = nullptr;
+  f->gpart = nullptr;
+  f->cap_n = 0;
+  const int64_t tiles = (n + 31) / 32;
+  f->srows = 32 + 4 * FH + FK * f->nbm;
+  f->grid_w = device_cus();
+  VGX_TRY(dev_alloc((void**)&f->zsave, sizeof(float) * (size_t)f->L * f->dim * n));
+  VGX_TRY(dev_alloc((void**)&f->rsave, sizeof(double) * (size_t)n));
+  VGX_TRY(dev_alloc((void**)&f->lqsave, sizeof(double) * (size_t)n));
+  VGX_TRY(dev_alloc((void**)&f->dz[0], sizeof(float) * (size_t)f->dim * n));
+  VGX_TRY(dev_alloc((void**)&f->dz[1], sizeof(float) * (size_t)f->dim * n));
+  VGX_TRY(dev_alloc((void**)&f->scr, sizeof(unsigned short) * (size_t)tiles * f->srows * 32));
+  VGX_TRY(dev_alloc((void**)&f->gpart, sizeof(float) * (size_t)f->n_par * f->grid_w));
+  // rows 16..31 of the zA block are never written and must read as zero
+  VGX_HIP(hipMemsetAsync(f->scr, 0, sizeof(unsigned short) * (size_t)tiles * f->srows * 32, f->stream));
+  f->cap_n = n;
+  return VGX_OK;
+}
+
+// forward (training) + loss + per-layer backward + weight gradients; leaves
+// per-workgroup partials in gpart and the loss on the device.
+vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const double* g) {
+  VGX_TRY(ensure_train(f, n));
+  const int grid = fwd_grid(f, n);
+  FwdArgs a{};
+  a.n = n;
+  a.yin = y;
+  a.g = g;
+  a.out = nullptr;
+  a.logq = f->lqsave;
+  a.zsave = f->zsave;
+  a.rsave = f->rsave;
+  a.partials = f->partials;
+  VGX_TRY(launch_fwd<1>(f, grid, a, f->stream));
+  hipLaunchKernelGGL(k_flow_loss, dim3(1), dim3(64), 0, f->stream, f->partials, grid, f->loss);
+  VGX_HIP(hipGetLastError());
+  const int wgrid = f->grid_w;
+  int cur = 0;
+  for (int l = f->L - 1; l >= 0; --l) {
+    const FlowLayerDesc& Ld = f->D.l[l];
+    BwdArgs b{};
+    b.n = n;
+    b.layer = l;
+    b.zin = f->zsave + (size_t)l * f->dim * n;
+    b.dzout = (l == f->L - 1) ? nullptr : f->dz[cur];
+    b.dzin = f->dz[cur ^ 1];
+    b.rsave = f->rsave;
+    b.loss = f->loss;
+    b.scr = f->scr;
+    b.srows = f->srows;
+    const size_t lds = (size_t)Ld.fw_len * 2 + (size_t)Ld.bw_len * 2 + (size_t)Ld.bias_len * 4;
+#define B_(NB)                                                                                        \
+  case NB:                                                                                            \
+    hipFuncSetAttribute((const void*)k_flow_bwd<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    hipLaunchKernelGGL((k_flow_bwd<NB>), dim3(grid), dim3(FBLOCK), lds, f->stream, f->d_desc, b, f->fw, f->bw, f->bias); \
+    break;
+    switch (f->nbm) { B_(1) B_(2) B_(4) B_(8) default: return VGX_EINVAL; }
+#undef B_
+    VGX_HIP(hipGetLastError());
+    WgradArgs w{};
+    w.n = n;
+    w.layer = l;
+    w.scr = f->scr;
+    w.srows = f->srows;
+    w.gpart = f->gpart + (size_t)Ld.p_off * wgrid;
+    const size_t wl = (size_t)Ld.n_par * 4;
+#define W_(NB)                                                                                        \
+  case NB:                                                                                            \
+    hipFuncSetAttribute((const void*)k_flow_wgrad<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wl); \
+    hipLaunchKernelGGL((k_flow_wgrad<NB>), dim3(wgrid), dim3(FBLOCK), wl, f->stream, f->d_desc, w); \
+    break;
+    switch (f->nbm) { W_(1) W_(2) W_(4) W_(8) default: return VGX_EINVAL; }
+#undef W_
+    VGX_HIP(hipGetLastError());
+    cur ^= 1;
+  }
+  return VGX_OK;
+}
+
+vgx_status reduce_adam(vgx_flow* f, const float* grad_in, float* grad_out, float lr, bool adam, const double* loss) {
+  AdamArgs a{};
+  a.n_par = f->n_par;
+  a.rows = f->grid_w;
+  a.gpart = f->gpart;
+  a.grad_in = grad_in;
+  a.grad_out = grad_out;
+  a.master = f->master;
+  a.m = f->m;
+  a.v = f->v;
+  a.loss = loss;
+  a.lr = lr;
+  a.beta1 = 0.9f;
+  a.beta2 = 0.999f;
+  a.eps = 1e-8f;
+  a.do_adam = adam ? 1 : 0;
+  if (adam) a.step = ++f->step;
+  hipLaunchKernelGGL(k_flow_adam, dim3((unsigned)((f->n_par + 255) / 256)), dim3(256), 0, f->stream, f->d_desc, a);
+  VGX_HIP(hipGetLastError());
+  if (adam) VGX_TRY(pack(f));
+  return VGX_OK;
+}
+
+}  // namespace
+
+extern "C" int64_t flow_num_params(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden) {
+  if (dim < 2 || dim > VGX_MAX_DIM || n_layers < 1 || n_layers > FL_MAX || n_bins != FK || hidden != FH) return -1;
+  FlowDesc D;
+  std::vector<int> a, b, c;
+  int64_t np = 0;
+  int nbm = 0;
+  if (build_desc(dim, n_layers, D, a, b, c, np, nbm) != VGX_OK) return -1;
+  return np;
+}
+
+extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden, const float* params,
+                                  int64_t n_params, void* stream, vgx_flow** out) {
+  VGX_CHECK(out, "flow_create: null out");
+  *out = nullptr;
+  VGX_CHECK(dim >= 2 && dim <= VGX_MAX_DIM, "flow_create: dim %d out of 2..%d", dim, VGX_MAX_DIM);
+  VGX_CHECK(n_layers >= 1 && n_layers <= FL_MAX, "flow_create: n_layers out of 1..%d", FL_MAX);
+  VGX_CHECK(n_bins == FK && hidden == FH, "flow_create: supported n_bins = %d, hidden = %d", FK, FH);
+  VGX_CHECK(params, "flow_create: null params");
+  vgx_flow* f = new vgx_flow();
+  hipGetDevice(&f->device);
+  f->stream = (hipStream_t)stream;
+  f->dim = dim;
+  f->L = n_layers;
+  f->n_bins = n_bins;
+  f->hidden = hidden;
+  std::vector<int> fws, bws, bs;
+  vgx_status s = build_desc(dim, n_layers, f->D, fws, bws, bs, f->n_par, f->nbm);
+  if (s != VGX_OK) { delete f; return s; }
+  if (n_params != f->n_par) {
+    delete f;
+    set_error("flow_create: expected %lld parameters, got %lld", (long long)f->n_par, (long long)n_params);
+    return VGX_EINVAL;
+  }
+  if (fwd_lds(f) > 160 * 1024) {
+    delete f;
+    set_error("flow_create: packed weights exceed LDS");
+    return VGX_EINVAL;
+  }
+  do {
+    if ((s = dev_alloc((void**)&f->master, sizeof(float) * f->n_par)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->m, sizeof(float) * f->n_par)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->v, sizeof(float) * f->n_par)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->grad, sizeof(float) * f->n_par)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->fw, 2 * (size_t)f->D.fw_total)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->bw, 2 * (size_t)f->D.bw_total)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->bias, 4 * (size_t)f->D.bias_total)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->fw_src, 4 * fws.size())) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->bw_src, 4 * bws.size())) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->b_src, 4 * bs.size())) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->loss, sizeof(double) * 4)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->d_desc, sizeof(FlowDesc))) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->partials, sizeof(double) * 4 * (size_t)device_cus() * 2)) != VGX_OK) break;
+    if ((s = host_alloc((void**)&f->pinned, sizeof(double) * 4)) != VGX_OK) break;
+  } while (0);
+  if (s != VGX_OK) { flow_destroy(f); return s; }
+  hipError_t e = hipMemcpyAsync(f->master, params, sizeof(float) * f->n_par, hipMemcpyHostToDevice, f->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(f->m, 0, sizeof(float) * f->n_par, f->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(f->v, 0, sizeof(float) * f->n_par, f->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f->fw_src, fws.data(), 4 * fws.size(), hipMemcpyHostToDevice, f->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f->bw_src, bws.data(), 4 * bws.size(), hipMemcpyHostToDevice, f->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f->b_src, bs.data(), 4 * bs.size(), hipMemcpyHostToDevice, f->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f->d_desc, &f->D, sizeof(FlowDesc), hipMemcpyHostToDevice, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);  // host vectors die at return
+  if (e != hipSuccess) { s = hip_fail(e, "flow_create copies", __FILE__, __LINE__); flow_destroy(f); return s; }
+  s = pack(f);
+  if (s == VGX_OK) {
+    e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) s = hip_fail(e, "flow_create pack", __FILE__, __LINE__);
+  }
+  if (s != VGX_OK) { flow_destroy(f); return s; }
+  *out = f;
+  return VGX_OK;
+}
+
+extern "C" vgx_status flow_sample(vgx_flow* f, int64_t n, uint64_t seed, uint32_t stream_id, int32_t iteration,
+                                  double* y, double* logq, void* stream) {
+  VGX_CHECK(f, "flow_sample: null flow");
+  VGX_CHECK(n >= 0 && stream_id < (1u << 23), "flow_sample: bad n or stream_id");
+  if (n == 0) return VGX_OK;
+  VGX_CHECK(y && logq, "flow_sample: null output");
+  FwdArgs a{};
+  a.n = n;
+  a.out = y;
+  a.logq = logq;
+  a.it = (uint32_t)iteration;
+  a.sid = stream_id | (1u << 23);
+  a.k0 = (uint32_t)seed;
+  a.k1 = (uint32_t)(seed >> 32);
+  return launch_fwd<2>(f, fwd_grid(f, n), a, (hipStream_t)stream);
+}
+
+extern "C" vgx_status flow_density(vgx_flow* f, int64_t n, const double* y, double* u, double* logq, void* stream) {
+  VGX_CHECK(f, "flow_density: null flow");
+  VGX_CHECK(n >= 0, "flow_density: n < 0");
+  if (n == 0) return VGX_OK;
+  VGX_CHECK(y && logq, "flow_density: null pointer");
+  FwdArgs a{};
+  a.n = n;
+  a.yin = y;
+  a.out = u;
+  a.logq = logq;
+  return launch_fwd<0>(f, fwd_grid(f, n), a, (hipStream_t)stream);
+}
+
+extern "C" vgx_status flow_loss_grad(vgx_flow* f, int64_t n, const double* y, const double* g, double* loss_host,
+                                     float* grad_host) {
+  VGX_CHECK(f, "flow_loss_grad: null flow");
+  VGX_CHECK(n >= 2 && y && g, "flow_loss_grad: need n >= 2 and data");
+  VGX_TRY(loss_grad_enqueue(f, n, y, g));
+  VGX_TRY(reduce_adam(f, nullptr, f->grad, 0.0f, false, nullptr));
+  VGX_HIP(hipMemcpyAsync(f->pinned, f->loss, sizeof(double) * 3, hipMemcpyDeviceToHost, f->stream));
+  if (grad_host) VGX_HIP(hipMemcpyAsync(grad_host, f->grad, sizeof(float) * f->n_par, hipMemcpyDeviceToHost, f->stream));
+  VGX_HIP(hipStreamSynchronize(f->stream));
+  if (loss_host) *loss_host = f->pinned[0];
+  return VGX_OK;
+}
+
+extern "C" vgx_status flow_train_step(vgx_flow* f, int64_t n, const double* y, const double* g, float lr,
+                                      double* loss_host) {
+  VGX_CHECK(f, "flow_train_step: null flow");
+  VGX_CHECK(n >= 2 && y && g, "flow_train_step: need n >= 2 and data");
+  VGX_CHECK(lr >= 0.0f, "flow_train_step: lr < 0");
+  VGX_TRY(loss_grad_enqueue(f, n, y, g));
+  VGX_TRY(reduce_adam(f, nullptr, f->grad, lr, true, f->loss));
+  if (!loss_host) return VGX_OK;
+  VGX_HIP(hipMemcpyAsync(f->pinned, f->loss, sizeof(double) * 3, hipMemcpyDeviceToHost, f->stream));
+  VGX_HIP(hipStreamSynchronize(f->stream));
+  *loss_host = f->pinned[0];
+  if (f->pinned[2] == 0.0) {
+    --f->step;  // the update was skipped on the device
+    set_error("flow_train_step: non-finite loss, weights unchanged");
+    return VGX_EFALLBACK;
+  }
+  return VGX_OK;
+}
+
+extern "C" vgx_status flow_adam(vgx_flow* f, const float* grad, float lr) {
+  VGX_CHECK(f && grad, "flow_adam: null argument");
+  return reduce_adam(f, grad, nullptr, lr, true, nullptr);
+}
+
+extern "C" vgx_status flow_get_params(vgx_flow* f, float* params, int64_t cap, int64_t* n) {
+  VGX_CHECK(f && n, "flow_get_params: null argument");
+  *n = f->n_par;
+  if (!params || cap < f->n_par) return VGX_OK;
+  VGX_HIP(hipMemcpyAsync(params, f->master, sizeof(float) * f->n_par, hipMemcpyDeviceToHost, f->stream));
+  VGX_HIP(hipStreamSynchronize(f->stream));
+  return VGX_OK;
+}
+
+extern "C" vgx_status flow_set_params(vgx_flow* f, const float* params, int64_t n) {
+  VGX_CHECK(f && params, "flow_set_params: null argument");
+  VGX_CHECK(n == f->n_par, "flow_set_params: expected %lld parameters", (long long)f->n_par);
+  VGX_HIP(hipMemcpyAsync(f->master, params, sizeof(float) * n, hipMemcpyHostToDevice, f->stream));
+  VGX_TRY(pack(f));
+  VGX_HIP(hipStreamSynchronize(f->stream));
+  return VGX_OK;
+}
+
+extern "C" void flow_destroy(vgx_flow* f) {
+  if (!f) return;
+  if (f->stream) hipStreamSynchronize(f->stream);
+  hipFree(f->master); hipFree(f->m); hipFree(f->v); hipFree(f->grad);
+  hipFree(f->fw); hipFree(f->bw); hipFree(f->bias);
+  hipFree(f->fw_src); hipFree(f->bw_src); hipFree(f->b_src);
+  hipFree(f->loss); hipFree(f->partials); hipFree(f->d_desc);
+  hipFree(f->zsave); hipFree(f->rsave); hipFree(f->lqsave); hipFree(f->dz[0]); hipFree(f->dz[1]); hipFree(f->scr); hipFree(f->gpart);
+  if (f->pinned) hipHostFree(f->pinned);
+  delete f;
+}

@@ -1,0 +1,303 @@
+// Log-bicubic PDF interpolation on subgrids (LHAPDF-style), one query per
+// thread, FP64 arithmetic, FP64 or FP32 output.
+//
+// Thesis: PDF chapter, LHAPDF paragraphs (knots in (x, Q^2), subgrids split
+// at quark-mass thresholds, cubic Hermite in (log x, log Q) on 4 neighbouring
+// knots, bilinear where the 4-knot stencil is unavailable) and PDFFlow's
+// Subgrid design.  The Hermite node slopes are the average of the two
+// adjacent secants (LHAPDF6's rule, Buckley et al. 2015).
+//
+// Kernel design (MI355X): the cubic Hermite with secant slopes is linear in
+// the four node values, so for a query the 4x4 stencil reduces to 16
+// weights w_rk = q_r c_k computed once and shared by all flavours; node
+// values are stored [iq][ix][flav] so that one stencil row (4 consecutive x
+// knots) is one contiguous 4*n_flav run.  Knots are staged in LDS for the
+// binary searches; outputs are written structure-of-arrays, coalesced.
+#include "pdf_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+
+namespace vgx {
+
+struct PdfKernelArgs {
+  int n_x, n_sub, n_flav;
+  int nq[VGX_MAX_SUB];
+  int q_off[VGX_MAX_SUB + 1];
+  double q2_lo[VGX_MAX_SUB], q2_hi[VGX_MAX_SUB];
+};
+
+// Weights (cm, c0, c1, c2) of the nodes k-1, k, k+1, k+2 such that
+// sum c * F equals the cubic Hermite between k and k+1 at fraction t with
+// node slopes the average of adjacent secants.  rm = h_k/h_{k-1},
+// rp = h_k/h_{k+1} with h the knot spacings.
+__device__ __forceinline__ void hermite_weights(double t, double rm, double rp, double (&c)[4]) {
+  const double t2 = t * t, t3 = t2 * t;
+  const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+  const double h10 = t3 - 2.0 * t2 + t;
+  const double h01 = -2.0 * t3 + 3.0 * t2;
+  const double h11 = t3 - t2;
+  // d0 = (F1 - F0)/2 + rm (F0 - Fm)/2,  d1 = rp (F2 - F1)/2 + (F1 - F0)/2
+  c[0] = -0.5 * h10 * rm;
+  c[1] = h00 - 0.5 * h10 + 0.5 * h10 * rm - 0.5 * h11;
+  c[2] = h01 + 0.5 * h10 - 0.5 * h11 * rp + 0.5 * h11;
+  c[3] = 0.5 * h11 * rp;
+}
+
+// first index i in [lo, hi) with key < a[i+1], i.e. a[i] <= key < a[i+1],
+// clamped to hi - 1 (so the top knot maps to the last cell).
+__device__ __forceinline__ int find_cell(const double* a, int n, double key) {
+  int lo = 0, hi = n - 1;  // answer in [0, n-2]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= key) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// NF > 0: compile-time flavour count; NF == 0: runtime count (<= VGX_MAX_FLAV).
+// ValT: node-value type read from memory (FP64 grid, or its FP32 copy for
+// FP32 outputs); arithmetic is FP64 in both cases.
+template <typename OutT, typename ValT, int NF>
+__global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, const double* __restrict__ qx,
+                                                     const double* __restrict__ qq2,
+                                                     const double* __restrict__ kx, const double* __restrict__ klx,
+                                                     const double* __restrict__ kq2, const double* __restrict__ klq2,
+                                                     const ValT* __restrict__ vals, OutT* __restrict__ out,
+                                                     unsigned long long* __restrict__ oor) {
+  constexpr int NFM = NF > 0 ? NF : VGX_MAX_FLAV;
+  extern __shared__ double lds[];
+  double* sx = lds;                 // [n_x]
+  double* slx = sx + g.n_x;         // [n_x]
+  const int nqt = g.q_off[g.n_sub];
+  double* sq2 = slx + g.n_x;        // [nqt]
+  double* slq2 = sq2 + nqt;         // [nqt]
+  for (int k = threadIdx.x; k < g.n_x; k += blockDim.x) { sx[k] = kx[k]; slx[k] = klx[k]; }
+  for (int k = threadIdx.x; k < nqt; k += blockDim.x) { sq2[k] = kq2[k]; slq2[k] = klq2[k]; }
+  __syncthreads();
+
+  const int nf = NF > 0 ? NF : g.n_flav;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double x = qx[q];
+    const double q2 = qq2[q];
+    int s = -1;
+    for (int k = 0; k < g.n_sub; ++k) {
+      const bool last = (k == g.n_sub - 1);
+      if (q2 >= g.q2_lo[k] && (q2 < g.q2_hi[k] || (last && q2 <= g.q2_hi[k]))) s = k;
+    }
+    if (s < 0 || !(x >= sx[0] && x <= sx[g.n_x - 1])) {
+      for (int f = 0; f < nf; ++f) out[(int64_t)f * n + q] = (OutT)NAN;
+      atomicAdd(oor, 1ull);
+      continue;
+    }
+    const int nq = g.nq[s];
+    const double* lq = slq2 + g.q_off[s];
+    const int i = find_cell(sx, g.n_x, x);
+    const int j = find_cell(sq2 + g.q_off[s], nq, q2);
+    const double a = log(x), b = log(q2);
+    const ValT* V = vals + (int64_t)g.q_off[s] * g.n_x * nf;  // [iq][ix][f] of subgrid s
+    double acc[NFM];
+#pragma unroll
+    for (int f = 0; f < NFM; ++f) acc[f] = 0.0;
+    if (i >= 1 && i <= g.n_x - 3 && j >= 1 && j <= nq - 3) {
+      const double ha = slx[i + 1] - slx[i];
+      const double hb = lq[j + 1] - lq[j];
+      double cx[4], cq[4];
+      hermite_weights((a - slx[i]) / ha, ha / (slx[i] - slx[i - 1]), ha / (slx[i + 2] - slx[i + 1]), cx);
+      hermite_weights((b - lq[j]) / hb, hb / (lq[j] - lq[j - 1]), hb / (lq[j + 2] - lq[j + 1]), cq);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const ValT* row = V + ((int64_t)(j - 1 + r) * g.n_x + (i - 1)) * nf;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double w = cq[r] * cx[k];
+          const ValT* node = row + k * nf;
+#pragma unroll
+          for (int f = 0; f < NFM; ++f)
+            if (f < nf) acc[f] = fma(w, (double)node[f], acc[f]);
+        }
+      }
+    } else {
+      const double ta = (a - slx[i]) / (slx[i + 1] - slx[i]);
+      const double tb = (b - lq[j]) / (lq[j + 1] - lq[j]);
+      const double w[4] = {(1.0 - ta) * (1.0 - tb), ta * (1.0 - tb), (1.0 - ta) * tb, ta * tb};
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const ValT* row = V + ((int64_t)(j + r) * g.n_x + i) * nf;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const ValT* node = row + k * nf;
+#pragma unroll
+          for (int f = 0; f < NFM; ++f)
+            if (f < nf) acc[f] = fma(w[2 * r + k], (double)node[f], acc[f]);
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NFM; ++f)
+      if (f < nf) out[(int64_t)f * n + q] = (OutT)acc[f];
+  }
+}
+
+}  // namespace vgx
+
+using namespace vgx;
+
+extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** out) {
+  VGX_CHECK(d && out, "pdf_create: null argument");
+  *out = nullptr;
+  VGX_CHECK(d->n_x >= 2 && d->n_sub >= 1 && d->n_sub <= VGX_MAX_SUB && d->n_flav >= 1 &&
+                d->n_flav <= VGX_MAX_FLAV,
+            "pdf_create: bad sizes n_x=%d n_sub=%d n_flav=%d", d->n_x, d->n_sub, d->n_flav);
+  VGX_CHECK(d->x_knots && d->nq_per_sub && d->q2_knots && d->xf, "pdf_create: null array");
+  for (int k = 0; k < d->n_x; ++k) {
+    VGX_CHECK(d->x_knots[k] > 0.0 && (k == 0 || d->x_knots[k] > d->x_knots[k - 1]),
+              "pdf_create: x knots must be positive and strictly ascending");
+  }
+  vgx_pdf* p = new vgx_pdf();
+  p->n_x = d->n_x;
+  p->n_sub = d->n_sub;
+  p->n_flav = d->n_flav;
+  int tot = 0;
+  for (int s = 0; s < d->n_sub; ++s) {
+    if (d->nq_per_sub[s] < 2) { delete p; set_error("pdf_create: subgrid %d has < 2 knots", s); return VGX_EINVAL; }
+    p->nq[s] = d->nq_per_sub[s];
+    p->q_off[s] = tot;
+    tot += d->nq_per_sub[s];
+  }
+  p->q_off[d->n_sub] = tot;
+  for (int s = 0; s < d->n_sub; ++s) {
+    const double* q = d->q2_knots + p->q_off[s];
+    for (int k = 0; k < p->nq[s]; ++k) {
+      if (!(q[k] > 0.0) || (k > 0 && !(q[k] > q[k - 1]))) {
+        delete p; set_error("pdf_create: Q^2 knots of subgrid %d must be positive, strictly ascending", s);
+        return VGX_EINVAL;
+      }
+    }
+    if (s > 0 && q[0] != d->q2_knots[p->q_off[s] - 1]) {
+      delete p; set_error("pdf_create: subgrid %d must start at the previous subgrid's last knot", s);
+      return VGX_EINVAL;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipGetDevice(&p->device);
+  const size_t nvals = (size_t)tot * p->n_x * p->n_flav;
+  p->h_x = (double*)malloc(sizeof(double) * p->n_x);
+  p->h_q2 = (double*)malloc(sizeof(double) * tot);
+  double* lx = (double*)malloc(sizeof(double) * p->n_x);
+  double* lq = (double*)malloc(sizeof(double) * tot);
+  double* v = (double*)malloc(sizeof(double) * nvals);
+  float* v32 = (float*)malloc(sizeof(float) * nvals);
+  if (!p->h_x || !p->h_q2 || !lx || !lq || !v || !v32) {
+    free(lx); free(lq); free(v); free(v32); pdf_destroy(p);
+    set_error("pdf_create: host allocation failed");
+    return VGX_ENOMEM;
+  }
+  for (int k = 0; k < p->n_x; ++k) { p->h_x[k] = d->x_knots[k]; lx[k] = log(d->x_knots[k]); }
+  for (int k = 0; k < tot; ++k) { p->h_q2[k] = d->q2_knots[k]; lq[k] = log(d->q2_knots[k]); }
+  // re-layout [sub][flav][iq][ix] -> [iq_total][ix][flav]
+  size_t src = 0;
+  for (int s = 0; s < p->n_sub; ++s)
+    for (int f = 0; f < p->n_flav; ++f)
+      for (int iq = 0; iq < p->nq[s]; ++iq)
+        for (int ix = 0; ix < p->n_x; ++ix, ++src) {
+          const size_t dst = ((size_t)(p->q_off[s] + iq) * p->n_x + ix) * p->n_flav + f;
+          v[dst] = d->xf[src];
+          v32[dst] = (float)d->xf[src];
+        }
+  vgx_status st_ = VGX_OK;
+  do {
+    if ((st_ = dev_alloc((void**)&p->x, sizeof(double) * p->n_x)) != VGX_OK) break;
+    if ((st_ = dev_alloc((void**)&p->lx, sizeof(double) * p->n_x)) != VGX_OK) break;
+    if ((st_ = dev_alloc((void**)&p->q2, sizeof(double) * tot)) != VGX_OK) break;
+    if ((st_ = dev_alloc((void**)&p->lq2, sizeof(double) * tot)) != VGX_OK) break;
+    if ((st_ = dev_alloc((void**)&p->v64, sizeof(double) * nvals)) != VGX_OK) break;
+    if ((st_ = dev_alloc((void**)&p->v32, sizeof(float) * nvals)) != VGX_OK) break;
+    if ((st_ = dev_alloc((void**)&p->oor, sizeof(unsigned long long))) != VGX_OK) break;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(p->x, p->h_x, sizeof(double) * p->n_x, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->lx, lx, sizeof(double) * p->n_x, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->q2, p->h_q2, sizeof(double) * tot, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->lq2, lq, sizeof(double) * tot, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->v64, v, sizeof(double) * nvals, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->v32, v32, sizeof(float) * nvals, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(p->oor, 0, sizeof(unsigned long long), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) st_ = hip_fail(e, "pdf_create copies", __FILE__, __LINE__);
+  } while (0);
+  free(lx); free(lq); free(v); free(v32);
+  if (st_ != VGX_OK) { pdf_destroy(p); return st_; }
+  *out = p;
+  return VGX_OK;
+}
+
+extern "C" vgx_status pdf_interp(const vgx_pdf* p, int64_t n, const double* x_dev, const double* q2_dev,
+                                 int32_t out_dtype, void* out_dev, void* stream) {
+  VGX_CHECK(p, "pdf_interp: null context");
+  VGX_CHECK(n >= 0, "pdf_interp: n < 0");
+  VGX_CHECK(out_dtype == VGX_F64 || out_dtype == VGX_F32, "pdf_interp: bad out_dtype %d", out_dtype);
+  if (n == 0) return VGX_OK;
+  VGX_CHECK(x_dev && q2_dev && out_dev, "pdf_interp: null device pointer");
+  PdfKernelArgs g{};
+  g.n_x = p->n_x; g.n_sub = p->n_sub; g.n_flav = p->n_flav;
+  for (int s = 0; s < p->n_sub; ++s) {
+    g.nq[s] = p->nq[s];
+    g.q_off[s] = p->q_off[s];
+    g.q2_lo[s] = p->h_q2[p->q_off[s]];
+    g.q2_hi[s] = p->h_q2[p->q_off[s] + p->nq[s] - 1];
+  }
+  g.q_off[p->n_sub] = p->q_off[p->n_sub];
+  const int block = 256;
+  const int64_t want = (n + block - 1) / block;
+  const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
+  const size_t lds = sizeof(double) * (2 * (size_t)p->n_x + 2 * (size_t)p->q_off[p->n_sub]);
+  hipStream_t st = (hipStream_t)stream;
+  const bool f11 = p->n_flav == 11;
+  if (out_dtype == VGX_F64) {
+    if (f11)
+      hipLaunchKernelGGL((k_pdf_interp<double, double, 11>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
+    else
+      hipLaunchKernelGGL((k_pdf_interp<double, double, 0>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
+  } else {
+    if (f11)
+      hipLaunchKernelGGL((k_pdf_interp<float, float, 11>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
+    else
+      hipLaunchKernelGGL((k_pdf_interp<float, float, 0>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
+  }
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+extern "C" vgx_status pdf_out_of_range(vgx_pdf* p, void* stream, int64_t* count) {
+  VGX_CHECK(p && count, "pdf_out_of_range: null argument");
+  unsigned long long c = 0;
+  hipStream_t st = (hipStream_t)stream;
+  VGX_HIP(hipMemcpyAsync(&c, p->oor, sizeof(c), hipMemcpyDeviceToHost, st));
+  VGX_HIP(hipStreamSynchronize(st));
+  VGX_HIP(hipMemsetAsync(p->oor, 0, sizeof(c), st));
+  VGX_HIP(hipStreamSynchronize(st));
+  *count = (int64_t)c;
+  return c ? VGX_ERANGE : VGX_OK;
+}
+
+extern "C" vgx_status pdf_bounds(const vgx_pdf* p, double* xmin, double* xmax, double* q2min, double* q2max) {
+  VGX_CHECK(p, "pdf_bounds: null context");
+  if (xmin) *xmin = p->h_x[0];
+  if (xmax) *xmax = p->h_x[p->n_x - 1];
+  if (q2min) *q2min = p->h_q2[0];
+  if (q2max) *q2max = p->h_q2[p->q_off[p->n_sub] - 1];
+  return VGX_OK;
+}
+
+extern "C" void pdf_destroy(vgx_pdf* p) {
+  if (!p) return;
+  hipFree(p->x); hipFree(p->lx); hipFree(p->q2); hipFree(p->lq2);
+  hipFree(p->v64); hipFree(p->v32); hipFree(p->oor);
+  free(p->h_x); free(p->h_q2);
+  delete p;
+}

@@ -1,0 +1,26 @@
+// Internal layout of a PDF grid on the device (shared by pdf.hip and the
+// fused t tbar integrand).
+#pragma once
+
+#include "common.h"
+
+#define VGX_MAX_SUB 8
+#define VGX_MAX_FLAV 16
+
+struct vgx_pdf {
+  int device = 0;
+  int n_x = 0, n_sub = 0, n_flav = 0;
+  int nq[VGX_MAX_SUB] = {0};
+  int q_off[VGX_MAX_SUB + 1] = {0};   // knot offset of each subgrid
+  // host copies (knots only; values stay on the device)
+  double* h_x = nullptr;              // [n_x]
+  double* h_q2 = nullptr;             // [q_off[n_sub]]
+  // device arrays
+  double* x = nullptr;                // [n_x]            x knots
+  double* lx = nullptr;               // [n_x]            ln x knots
+  double* q2 = nullptr;               // [total q]        Q^2 knots
+  double* lq2 = nullptr;              // [total q]        ln Q^2 knots
+  double* v64 = nullptr;              // [total q][n_x][n_flav]  node values (FP64)
+  float* v32 = nullptr;               // same, FP32 copy
+  unsigned long long* oor = nullptr;  // out-of-range counter
+};

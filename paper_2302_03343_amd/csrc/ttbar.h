@@ -1,0 +1,200 @@
+// Fused LO pp -> t tbar integrand (FP32 arithmetic, kinematics set up in
+// FP64) with the log-bicubic PDF lookup served from LDS.
+//
+// Thesis: master formula sigma = sum_ab int dPhi_n L(x1, x2) |M|^2 (MadFlow
+// chapter), factorisation sigma = sum_ij int dx1 dx2 f_i f_j sigma_ij (PDF
+// chapter), sub-processes q qbar -> t tbar and g g -> t tbar (pp -> t tbar
+// example), two-body phase space (phase-space section).  Matrix elements:
+// the spin/colour-averaged LO forms (Combridge 1979; Ellis-Stirling-Webber
+// Ch. 10) with tau_{1,2} = (1 -/+ beta cos)/2, rho = 4 m^2/s_hat:
+//   |M|^2_qq = g^4 (4/9)(tau1^2 + tau2^2 + rho/2)
+//   |M|^2_gg = g^4 (1/(6 tau1 tau2) - 3/8)(tau1^2 + tau2^2 + rho - rho^2/(4 tau1 tau2)).
+// Map of the unit cube: tau = tau0^(1-x1), y = (x2 - 1/2) ln(1/tau),
+// cos = 2 x3 - 1, so that
+//   F = [J_tau/tau] J_y J_c * L * beta/(32 pi s_hat) * (hbar c)^2
+//     = 2 L0 l_tau beta/(32 pi s tau) * (lum_gg |M|^2_gg + lum_qq |M|^2_qq) * conv,
+// with L0 = ln(1/tau0), l_tau = ln(1/tau) = (1 - x1) L0 and the luminosities
+// built from xf (f(x) = xf/x gives the 1/tau of dx1 dx2 = dtau dy).
+//
+// Rounding-safe forms (exact identities, no cancellation in FP32):
+//   rho = exp(-x1 L0), beta^2 = -expm1(-x1 L0),
+//   1 - beta cos = (1 - beta) + 2 beta (1 - x3),  1 + beta cos = (1 - beta) + 2 beta x3,
+//   1 - beta = rho/(1 + beta),  ln x_{1,2} = +/- y - l_tau/2  (no log needed).
+//
+// PDF lookup at the fixed scale mu^2 = m_t^2: the four Q^2 rows j-1..j+2
+// around mu^2 (two rows if the Q stencil is incomplete) are staged in LDS as
+// FP32 [ix][row][flav]; per event and per x the cubic Hermite (secant
+// slopes) in ln x and then in ln Q^2 is evaluated for all 11 flavours, as a
+// 4x4 weighted sum w_rk = q_r c_k of the stencil (same linear function as
+// the Hermite-with-slopes formula).  Bilinear where the stencil is
+// incomplete.  Flavour order: -5..-1, g, 1..5.
+#pragma once
+
+#include "common.h"
+#include "pdf_internal.h"
+
+namespace vgx {
+
+constexpr int TT_NF = 11;
+constexpr int TT_MAX_NX = 256;
+
+struct TTbarConst {
+  // kinematics (FP64, set on the host from sqrt_s, m_t, alpha_s, conv)
+  double L0;        // ln(1/tau0)
+  float pref;       // 2 conv / (32 pi s)
+  float g4;         // (4 pi alpha_s)^2
+  // PDF staging
+  const float* v32; // device [iq][ix][flav] FP32 grid
+  const double* lx; // device ln x knots
+  const double* lq2;// device ln Q^2 knots (all subgrids)
+  int n_x;
+  int row0;         // global index of the first staged Q^2 row
+  int n_rows;       // 4 (bicubic in Q) or 2 (bilinear in Q)
+  int j_local;      // cell index of mu^2 inside its subgrid
+  int nq_sub;       // knots in that subgrid
+  int q_off;        // global knot offset of the subgrid
+  double lmu2;      // ln mu^2
+};
+
+// LDS footprint in floats.
+__host__ __device__ inline int ttbar_lds_floats(int n_x) { return n_x * 4 * TT_NF + 2 * n_x + 8; }
+
+struct TTbar {
+  static constexpr bool kStage = true;
+  TTbarConst c;
+  float* F;     // LDS [n_x][n_rows][11]
+  float* sa;    // LDS ln x knots [n_x]
+  float* sinv;  // LDS 1/(a_{i+1} - a_i) [n_x]
+  float* qw;    // LDS Q-direction weights [4]
+
+  __device__ void stage(float* lds) {
+    F = lds;
+    sa = F + c.n_x * 4 * TT_NF;
+    sinv = sa + c.n_x;
+    qw = sinv + c.n_x;
+    const int nr = c.n_rows;
+    const int tot = c.n_x * nr * TT_NF;
+    for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+      const int f = k % TT_NF;
+      const int r = (k / TT_NF) % nr;
+      const int ix = k / (TT_NF * nr);
+      F[k] = c.v32[((size_t)(c.row0 + r) * c.n_x + ix) * TT_NF + f];
+    }
+    for (int k = threadIdx.x; k < c.n_x; k += blockDim.x) {
+      sa[k] = (float)c.lx[k];
+      sinv[k] = k + 1 < c.n_x ? (float)(1.0 / (c.lx[k + 1] - c.lx[k])) : 0.0f;
+    }
+    if (threadIdx.x == 0) {
+      // weights of the Q rows at mu^2 (FP64 setup, FP32 storage)
+      const double* lq = c.lq2 + c.q_off;
+      const int j = c.j_local;
+      const double hb = lq[j + 1] - lq[j];
+      const double t = (c.lmu2 - lq[j]) / hb;
+      if (c.n_rows == 4) {
+        const double rm = hb / (lq[j] - lq[j - 1]), rp = hb / (lq[j + 2] - lq[j + 1]);
+        const double t2 = t * t, t3 = t2 * t;
+        const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+        qw[0] = (float)(-0.5 * h10 * rm);
+        qw[1] = (float)(h00 - 0.5 * h10 + 0.5 * h10 * rm - 0.5 * h11);
+        qw[2] = (float)(h01 + 0.5 * h10 - 0.5 * h11 * rp + 0.5 * h11);
+        qw[3] = (float)(0.5 * h11 * rp);
+      } else {
+        qw[0] = (float)(1.0 - t);
+        qw[1] = (float)t;
+        qw[2] = 0.0f;
+        qw[3] = 0.0f;
+      }
+    }
+  }
+
+  // xf of all flavours at ln x = a (a <= 0).
+  __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
+    const int nx = c.n_x;
+    // cell: sa[i] <= a < sa[i+1], clamped to [0, nx-2]
+    int lo = 0, hi = nx - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sa[mid] <= a) lo = mid; else hi = mid;
+    }
+    const int i = lo;
+    const float t = (a - sa[i]) * sinv[i];
+#pragma unroll
+    for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
+    const int nr = c.n_rows;
+    if (nr == 4 && i >= 1 && i <= nx - 3) {
+      const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
+      const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
+      const float t2 = t * t, t3 = t2 * t;
+      const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
+      const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
+      float cx[4];
+      cx[0] = -0.5f * h10 * rm;
+      cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
+      cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
+      cx[3] = 0.5f * h11 * rp;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float* node = F + (size_t)(i - 1 + k) * 4 * TT_NF;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float w = cx[k] * qw[r];
+#pragma unroll
+          for (int f = 0; f < TT_NF; ++f) xf[f] = fmaf(w, node[r * TT_NF + f], xf[f]);
+        }
+      }
+    } else {
+      // bilinear on rows (j, j+1): staged rows 1, 2 when 4 rows, 0, 1 when 2
+      const int r0 = nr == 4 ? 1 : 0;
+      float tb = qw[1];
+      if (nr == 4) {
+        // linear weight in ln Q^2 for the bilinear fallback
+        const double* lq = c.lq2 + c.q_off;
+        tb = (float)((c.lmu2 - lq[c.j_local]) / (lq[c.j_local + 1] - lq[c.j_local]));
+      }
+      const float w00 = (1.f - t) * (1.f - tb), w01 = t * (1.f - tb), w10 = (1.f - t) * tb, w11 = t * tb;
+      const float* n0 = F + (size_t)i * nr * TT_NF;
+      const float* n1 = F + (size_t)(i + 1) * nr * TT_NF;
+#pragma unroll
+      for (int f = 0; f < TT_NF; ++f) {
+        float v = w00 * n0[r0 * TT_NF + f];
+        v = fmaf(w01, n1[r0 * TT_NF + f], v);
+        v = fmaf(w10, n0[(r0 + 1) * TT_NF + f], v);
+        v = fmaf(w11, n1[(r0 + 1) * TT_NF + f], v);
+        xf[f] = v;
+      }
+    }
+  }
+
+  __device__ __forceinline__ double eval(const double (&x)[3]) const {
+    // kinematics in FP64 (a handful of operations), then FP32
+    const double v = x[0] * c.L0;                  // u1 L0
+    const double ltau = (1.0 - x[0]) * c.L0;       // ln(1/tau)
+    const double y = (x[1] - 0.5) * ltau;
+    const float a1 = (float)(y - 0.5 * ltau);      // ln x1
+    const float a2 = (float)(-y - 0.5 * ltau);     // ln x2
+    const float w3 = (float)(1.0 - x[2]);          // 1 - u3
+    const float u3 = (float)x[2];
+    const float vf = (float)v;
+    const float rho = expf(-vf);
+    const float beta = sqrtf(-expm1f(-vf));
+    const float omb = rho / (1.f + beta);          // 1 - beta
+    const float tau1 = 0.5f * (omb + 2.f * beta * w3);
+    const float tau2 = 0.5f * (omb + 2.f * beta * u3);
+    const float t12 = tau1 * tau2;
+    const float ss = fmaf(tau1, tau1, tau2 * tau2);
+    const float m_qq = c.g4 * (4.f / 9.f) * fmaf(0.5f, rho, ss);
+    const float m_gg = c.g4 * (1.f / (6.f * t12) - 0.375f) * (ss + rho - rho * rho / (4.f * t12));
+    float f1[TT_NF], f2[TT_NF];
+    pdf_at(a1, f1);
+    pdf_at(a2, f2);
+    const float lum_gg = f1[5] * f2[5];
+    float lum_qq = 0.f;
+#pragma unroll
+    for (int q = 6; q < 11; ++q) lum_qq = fmaf(f1[q], f2[10 - q], fmaf(f1[10 - q], f2[q], lum_qq));
+    const float inv_tau = expf((float)ltau);
+    const float jac = (float)(c.L0 * ltau);
+    return (double)(c.pref * jac * beta * inv_tau * fmaf(lum_gg, m_gg, lum_qq * m_qq));
+  }
+};
+
+}  // namespace vgx

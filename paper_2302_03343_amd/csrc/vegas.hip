@@ -1,0 +1,662 @@
+// VEGAS adaptive importance sampling on the GPU: Philox uniforms -> grid map
+// with Jacobian -> fused integrand -> compensated sums and per-bin
+// histograms -> fixed-order reduction -> estimate and combination -> grid
+// refinement.
+//
+// Thesis: importance-sampling estimator E_N = (1/N) sum f/p and its variance
+// (MC chapter, importance-sampling equations); VEGAS (Sec. "Adaptive Monte
+// Carlo: VEGAS algorithm"): separable grid, fixed bin count, adaptive
+// widths, inverse-variance combination of iterations and the chi^2/dof
+// check; sampling by the inverse-transform method (Sec. "Inverse transform
+// method").  The refinement (smoothing, damping, re-binning) is Lepage's
+// (1978), which the thesis cites but does not print.
+//
+// MI355X design
+//   * one fused kernel per iteration, grid-stride over 64-bit sample indices,
+//     no per-sample buffers: uniforms are regenerated from the counter;
+//   * the grid edges (d x (N+1) FP64) and the per-workgroup histogram
+//     (d x N FP64, LDS atomics) live in LDS; integrand tables (t tbar PDF
+//     rows) are staged there too;
+//   * S1, S2 are FP64 sums compensated per 16-sample chunk (Neumaier), wave
+//     reduced with cross-lane shuffles and written as per-workgroup partials;
+//     a second kernel reduces the partials in a fixed order (no float
+//     atomics across workgroups), computes E and var(E), and updates the
+//     inverse-variance combination, all on the device;
+//   * refinement runs as one workgroup per dimension.
+#include "common.h"
+#include "integrands.h"
+#include "pdf_internal.h"
+#include "ttbar.h"
+#include "vegas_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+
+namespace vgx {
+
+constexpr int BLOCK = 256;
+constexpr int CHUNK = 16;
+
+struct VegasArgs {
+  int64_t n;
+  const double* edges;
+  int nb;
+  int pstride;   // doubles per workgroup partial row
+};
+
+// ---------------------------------------------------------------------------
+// Sample sources
+// ---------------------------------------------------------------------------
+template <int D>
+struct PhiloxSrc {
+  uint32_t it, sid, k0, k1;
+  int64_t first;
+  __device__ __forceinline__ double get(int64_t i, double (&u)[D]) const {
+    philox_uniforms<D>((uint64_t)(first + i), it, sid, k0, k1, u);
+    return 1.0;
+  }
+};
+
+template <int D>
+struct PointsSrc {
+  const double* y;     // [D][n]
+  const double* logq;  // [n] or null
+  int64_t n;
+  __device__ __forceinline__ double get(int64_t i, double (&u)[D]) const {
+#pragma unroll
+    for (int j = 0; j < D; ++j) u[j] = y[(int64_t)j * n + i];
+    return logq ? exp(-logq[i]) : 1.0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Fused iteration kernel.
+// LDS: edges [D][nb+1] | histogram [D][nb] (HIST) | integrand staging.
+// Partial row per workgroup: [S1.s, S1.c, S2.s, S2.c, hist[D][nb]].
+// ---------------------------------------------------------------------------
+template <int D, class F, class Src, bool HIST>
+__global__ __launch_bounds__(BLOCK) void k_vegas_iter(VegasArgs a, F f, Src src, double* __restrict__ partials) {
+  extern __shared__ double lds[];
+  const int nb = a.nb;
+  double* se = lds;
+  double* sh = se + D * (nb + 1);
+  float* extra = (float*)(sh + (HIST ? D * nb : 0));
+  for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
+  if (HIST)
+    for (int k = threadIdx.x; k < D * nb; k += BLOCK) sh[k] = 0.0;
+  F ff = f;
+  if constexpr (F::kStage) ff.stage(extra);
+  __syncthreads();
+
+  Comp c1, c2;
+  double p1 = 0.0, p2 = 0.0;
+  int cnt = 0;
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += stride) {
+    double u[D], x[D];
+    int idx[D];
+    const double ws = src.get(i, u);
+    const double jac = grid_map<D>(u, se, nb, x, idx);
+    const double w = ff.eval(x) * jac * ws;
+    const double w2 = w * w;
+    p1 += w;
+    p2 += w2;
+    if (++cnt == CHUNK) {
+      c1.add(p1);
+      c2.add(p2);
+      p1 = p2 = 0.0;
+      cnt = 0;
+    }
+    if (HIST) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) atomicAdd(&sh[j * nb + idx[j]], w2);
+    }
+  }
+  c1.add(p1);
+  c2.add(p2);
+
+  __shared__ double red[4][BLOCK / 64];
+  const double v0 = wave_sum(c1.s), v1 = wave_sum(c1.c), v2 = wave_sum(c2.s), v3 = wave_sum(c2.c);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { red[0][wv] = v0; red[1][wv] = v1; red[2][wv] = v2; red[3][wv] = v3; }
+  __syncthreads();
+  double* row = partials + (size_t)blockIdx.x * a.pstride;
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[threadIdx.x][k];
+    row[threadIdx.x] = s;
+  }
+  if (HIST)
+    for (int k = threadIdx.x; k < D * nb; k += BLOCK) row[4 + k] = sh[k];
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of the partial rows.  Workgroup b owns columns
+// 64b .. 64b+63; its 16 waves sum the rows r = wave, wave+16, ... with
+// compensation and are combined in wave order.  Workgroup 0 then turns
+// (S1, S2, n) into the iteration record and updates the combination.
+// ---------------------------------------------------------------------------
+constexpr int RBLOCK = 1024;
+constexpr int RGROUPS = RBLOCK / 64;
+
+__global__ __launch_bounds__(RBLOCK) void k_reduce(const double* __restrict__ partials, int rows, int pstride,
+                                                   int ncols, double* __restrict__ hist_out, int64_t n,
+                                                   IterRecord* __restrict__ rec, int k_rec, Combined* __restrict__ comb) {
+  __shared__ double ss[RGROUPS][64], sc[RGROUPS][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  Comp acc;
+  if (col < ncols)
+    for (int r = grp; r < rows; r += RGROUPS) acc.add(partials[(size_t)r * pstride + col]);
+  ss[grp][lane] = acc.s;
+  sc[grp][lane] = acc.c;
+  __syncthreads();
+  if (grp == 0) {
+    Comp t;
+    for (int g = 0; g < RGROUPS; ++g) { t.add(ss[g][lane]); t.add(sc[g][lane]); }
+    ss[0][lane] = t.value();
+    if (col >= 4 && col < ncols) hist_out[col - 4] = t.value();
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    finalize_record(ss[0][0] + ss[0][1], ss[0][2] + ss[0][3], n, rec, k_rec, comb);
+}
+
+__global__ __launch_bounds__(64) void k_refine(double* __restrict__ edges, const double* __restrict__ hist, int nb,
+                                               double alpha) {
+  refine_dim(edges + (size_t)blockIdx.x * (nb + 1), hist + (size_t)blockIdx.x * nb, nb, alpha);
+}
+
+// ---------------------------------------------------------------------------
+// Materialise samples: u [D][n] and g = f(G(u)) J(u).
+// ---------------------------------------------------------------------------
+template <int D, class F>
+__global__ __launch_bounds__(BLOCK) void k_vegas_sample(VegasArgs a, F f, PhiloxSrc<D> src, double* __restrict__ u_out,
+                                                        double* __restrict__ g_out) {
+  extern __shared__ double lds[];
+  const int nb = a.nb;
+  double* se = lds;
+  float* extra = (float*)(se + D * (nb + 1));
+  for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
+  F ff = f;
+  if constexpr (F::kStage) ff.stage(extra);
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += stride) {
+    double u[D], x[D];
+    int idx[D];
+    src.get(i, u);
+    const double jac = grid_map<D>(u, se, nb, x, idx);
+    if (u_out) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) u_out[(int64_t)j * a.n + i] = u[j];
+    }
+    if (g_out) g_out[i] = ff.eval(x) * jac;
+  }
+}
+
+}  // namespace vgx
+
+using namespace vgx;
+
+namespace {
+
+size_t extra_lds_bytes(const vgx_vegas* v) {
+  return v->kind == VGX_TTBAR ? sizeof(float) * (size_t)ttbar_lds_floats(v->tt.n_x) : 0;
+}
+
+int grid_for(const vgx_vegas* v, int64_t n) {
+  const int64_t want = (n + BLOCK - 1) / BLOCK;
+  return (int)(want < v->max_wg ? (want > 0 ? want : 1) : v->max_wg);
+}
+
+// Build the device-side integrand parameters from the user's parameters.
+vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
+  const int d = c->dim;
+  double* p = v->prm.p;
+  switch (c->kind) {
+    case VGX_GAUSS: {
+      VGX_CHECK(c->n_params >= 2 * d, "GAUSS needs 2*dim params");
+      double norm = 1.0;
+      for (int j = 0; j < d; ++j) {
+        const double s = c->params[d + j];
+        VGX_CHECK(s > 0.0, "GAUSS sigma must be > 0");
+        p[j] = c->params[j];
+        p[d + j] = 1.0 / (s * sqrt(2.0));
+        norm *= 1.0 / (s * sqrt(2.0 * M_PI));
+      }
+      p[2 * d] = norm;
+      return VGX_OK;
+    }
+    case VGX_GENZ_OSC:
+      VGX_CHECK(c->n_params >= 1 + d, "GENZ_OSC needs 1+dim params");
+      p[0] = 2.0 * M_PI * c->params[0];
+      for (int j = 0; j < d; ++j) p[1 + j] = c->params[1 + j];
+      return VGX_OK;
+    case VGX_GENZ_PEAK:
+      VGX_CHECK(c->n_params >= 2 * d, "GENZ_PEAK needs 2*dim params");
+      for (int j = 0; j < d; ++j) {
+        const double cj = c->params[d + j];
+        VGX_CHECK(cj != 0.0, "GENZ_PEAK c must be non-zero");
+        p[j] = c->params[j];
+        p[d + j] = 1.0 / (cj * cj);
+      }
+      return VGX_OK;
+    case VGX_TTBAR: {
+      VGX_CHECK(d == 3, "TTBAR needs dim 3");
+      VGX_CHECK(c->n_params >= 4, "TTBAR needs [sqrt_s, m_top, alpha_s, gev2_to_pb]");
+      VGX_CHECK(c->pdf, "TTBAR needs a PDF context");
+      const vgx_pdf* pdf = c->pdf;
+      VGX_CHECK(pdf->n_flav == TT_NF, "TTBAR needs an 11-flavour PDF (order -5..-1, g, 1..5)");
+      VGX_CHECK(pdf->n_x <= TT_MAX_NX, "TTBAR supports at most %d x knots", TT_MAX_NX);
+      const double rs = c->params[0], mt = c->params[1], as = c->params[2], conv = c->params[3];
+      VGX_CHECK(rs > 2.0 * mt && mt > 0.0 && as > 0.0, "TTBAR: need sqrt_s > 2 m_top > 0");
+      const double s = rs * rs;
+      const double tau0 = 4.0 * mt * mt / s;
+      VGX_CHECK(tau0 >= pdf->h_x[0], "TTBAR: tau0 below the PDF x range");
+      const double mu2 = mt * mt;
+      int sub = -1;
+      for (int k = 0; k < pdf->n_sub; ++k) {
+        const double lo = pdf->h_q2[pdf->q_off[k]], hi = pdf->h_q2[pdf->q_off[k] + pdf->nq[k] - 1];
+        const bool last = k == pdf->n_sub - 1;
+        if (mu2 >= lo && (mu2 < hi || (last && mu2 <= hi))) sub = k;
+      }
+      VGX_CHECK(sub >= 0, "TTBAR: mu^2 = m_top^2 outside the PDF Q^2 range");
+      const double* q = pdf->h_q2 + pdf->q_off[sub];
+      const int nq = pdf->nq[sub];
+      int j = 0;
+      while (j < nq - 2 && q[j + 1] <= mu2) ++j;
+      TTbarConst& t = v->tt;
+      t.L0 = log(1.0 / tau0);
+      t.pref = (float)(2.0 * conv / (32.0 * M_PI * s));
+      t.g4 = (float)((4.0 * M_PI * as) * (4.0 * M_PI * as));
+      t.v32 = pdf->v32;
+      t.lx = pdf->lx;
+      t.lq2 = pdf->lq2;
+      t.n_x = pdf->n_x;
+      t.j_local = j;
+      t.nq_sub = nq;
+      t.q_off = pdf->q_off[sub];
+      t.lmu2 = log(mu2);
+      if (j >= 1 && j <= nq - 3) { t.n_rows = 4; t.row0 = pdf->q_off[sub] + j - 1; }
+      else { t.n_rows = 2; t.row0 = pdf->q_off[sub] + j; }
+      return VGX_OK;
+    }
+    default:
+      set_error("unknown integrand kind %d", c->kind);
+      return VGX_EINVAL;
+  }
+}
+
+// Launch helpers dispatching on (kind, prec, D).
+template <int D, class F, class Src, bool HIST>
+vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
+  VegasArgs a{n, v->edges, v->nb, v->pstride};
+  const int grid = grid_for(v, n);
+  const size_t lds = sizeof(double) * ((size_t)D * (v->nb + 1) + (HIST ? (size_t)D * v->nb : 0)) + extra_lds_bytes(v);
+  hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
+                     v->partials);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+template <int D, class Src, bool HIST>
+vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
+  if (v->kind == VGX_TTBAR) {
+    if constexpr (D == 3) {
+      TTbar f{};
+      f.c = v->tt;
+      return launch_iter_f<3, TTbar, Src, HIST>(v, n, f, src);
+    }
+    set_error("TTBAR needs dim 3");
+    return VGX_EINVAL;
+  }
+#define VGX_LAUNCH_KIND(T)                                                     \
+  do {                                                                         \
+    if (v->prec == VGX_F64) {                                                  \
+      T<D, double> f{};                                                        \
+      f.prm = v->prm;                                                          \
+      return launch_iter_f<D, T<D, double>, Src, HIST>(v, n, f, src);          \
+    } else {                                                                   \
+      T<D, float> f{};                                                         \
+      f.prm = v->prm;                                                          \
+      return launch_iter_f<D, T<D, float>, Src, HIST>(v, n, f, src);           \
+    }                                                                          \
+  } while (0)
+  switch (v->kind) {
+    case VGX_GAUSS: VGX_LAUNCH_KIND(Gauss);
+    case VGX_GENZ_OSC: VGX_LAUNCH_KIND(GenzOsc);
+    case VGX_GENZ_PEAK: VGX_LAUNCH_KIND(GenzPeak);
+  }
+#undef VGX_LAUNCH_KIND
+  set_error("unknown kind");
+  return VGX_EINVAL;
+}
+
+template <int D, class F>
+vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, const F& f, double* u, double* g) {
+  VegasArgs a{n, v->edges, v->nb, v->pstride};
+  PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
+  const int grid = grid_for(v, n);
+  const size_t lds = sizeof(double) * (size_t)D * (v->nb + 1) + extra_lds_bytes(v);
+  hipLaunchKernelGGL((k_vegas_sample<D, F>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src, u, g);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+template <int D>
+vgx_status launch_sample_d(vgx_vegas* v, int64_t first, int64_t n, int32_t it, double* u, double* g) {
+  if (v->kind == VGX_TTBAR) {
+    if constexpr (D == 3) {
+      TTbar f{};
+      f.c = v->tt;
+      return launch_sample_f<3, TTbar>(v, first, n, it, f, u, g);
+    }
+    set_error("TTBAR needs dim 3");
+    return VGX_EINVAL;
+  }
+#define VGX_SAMPLE_KIND(T)                                                     \
+  do {                                                                         \
+    if (v->prec == VGX_F64) {                                                  \
+      T<D, double> f{};                                                        \
+      f.prm = v->prm;                                                          \
+      return launch_sample_f<D, T<D, double>>(v, first, n, it, f, u, g);       \
+    } else {                                                                   \
+      T<D, float> f{};                                                         \
+      f.prm = v->prm;                                                          \
+      return launch_sample_f<D, T<D, float>>(v, first, n, it, f, u, g);        \
+    }                                                                          \
+  } while (0)
+  switch (v->kind) {
+    case VGX_GAUSS: VGX_SAMPLE_KIND(Gauss);
+    case VGX_GENZ_OSC: VGX_SAMPLE_KIND(GenzOsc);
+    case VGX_GENZ_PEAK: VGX_SAMPLE_KIND(GenzPeak);
+  }
+#undef VGX_SAMPLE_KIND
+  set_error("unknown kind");
+  return VGX_EINVAL;
+}
+
+#define VGX_DIM_SWITCH(d, CALL)                                                 \
+  switch (d) {                                                                 \
+    case 1: return CALL(1); case 2: return CALL(2); case 3: return CALL(3);    \
+    case 4: return CALL(4); case 5: return CALL(5); case 6: return CALL(6);    \
+    case 7: return CALL(7); case 8: return CALL(8); case 9: return CALL(9);    \
+    case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12); \
+  }
+
+vgx_status timed_begin(vgx_vegas* v) {
+  if (v->timing) VGX_HIP(hipEventRecord(v->ev[0], v->stream));
+  return VGX_OK;
+}
+
+vgx_status timed_end(vgx_vegas* v) {
+  if (!v->timing) return VGX_OK;
+  VGX_HIP(hipEventRecord(v->ev[1], v->stream));
+  VGX_HIP(hipEventSynchronize(v->ev[1]));
+  float ms = 0.f;
+  VGX_HIP(hipEventElapsedTime(&ms, v->ev[0], v->ev[1]));
+  v->t_ms += ms;
+  v->t_launches += 1;
+  return VGX_OK;
+}
+
+vgx_status launch_philox_iter(vgx_vegas* v, int64_t n, int32_t it) {
+#define CALL(D) launch_iter_d<D, PhiloxSrc<D>, true>(v, n, PhiloxSrc<D>{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), 0})
+  VGX_DIM_SWITCH(v->dim, CALL)
+#undef CALL
+  set_error("bad dim");
+  return VGX_EINVAL;
+}
+
+vgx_status launch_points_iter(vgx_vegas* v, int64_t n, const double* y, const double* logq) {
+#define CALL(D) launch_iter_d<D, PointsSrc<D>, false>(v, n, PointsSrc<D>{y, logq, n})
+  VGX_DIM_SWITCH(v->dim, CALL)
+#undef CALL
+  set_error("bad dim");
+  return VGX_EINVAL;
+}
+
+vgx_status launch_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t it, double* u, double* g) {
+#define CALL(D) launch_sample_d<D>(v, first, n, it, u, g)
+  VGX_DIM_SWITCH(v->dim, CALL)
+#undef CALL
+  set_error("bad dim");
+  return VGX_EINVAL;
+}
+
+vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n) {
+  const int blocks = (ncols + 63) / 64;
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(RBLOCK), 0, v->stream, v->partials, rows, v->pstride, ncols,
+                     v->hist, n, v->rec, v->n_rec, v->comb);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out) {
+  IterRecord* h = (IterRecord*)v->pinned;
+  VGX_HIP(hipMemcpyAsync(h, v->rec + k, sizeof(IterRecord), hipMemcpyDeviceToHost, v->stream));
+  VGX_HIP(hipStreamSynchronize(v->stream));
+  if (out) {
+    out->mean = h->mean;
+    out->var = h->var;
+    out->s1 = h->s1;
+    out->s2 = h->s2;
+    out->n = h->n;
+  }
+  if (!h->finite) {
+    set_error("non-finite iteration estimate (mean=%g var=%g); excluded from the combination", h->mean, h->var);
+    return VGX_ENUMERIC;
+  }
+  return VGX_OK;
+}
+
+}  // namespace
+
+extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_vegas** out) {
+  VGX_CHECK(c && out, "vegas_create: null argument");
+  *out = nullptr;
+  VGX_CHECK(c->dim >= 1 && c->dim <= VGX_MAX_DIM, "vegas_create: dim %d out of 1..%d", c->dim, VGX_MAX_DIM);
+  VGX_CHECK(c->n_bins >= 2 && c->n_bins <= VGX_MAX_BINS, "vegas_create: n_bins %d out of 2..%d", c->n_bins,
+            VGX_MAX_BINS);
+  VGX_CHECK(c->prec == VGX_F64 || c->prec == VGX_F32, "vegas_create: bad prec");
+  VGX_CHECK(c->alpha >= 0.0 && c->alpha < 100.0, "vegas_create: bad alpha");
+  VGX_CHECK(c->stream_id < (1u << 23), "vegas_create: stream_id must be < 2^23");
+  VGX_CHECK(c->n_params <= MAX_PARAMS && (c->n_params == 0 || c->params), "vegas_create: bad params");
+  vgx_vegas* v = new vgx_vegas();
+  hipGetDevice(&v->device);
+  v->stream = (hipStream_t)stream;
+  v->kind = c->kind;
+  v->dim = c->dim;
+  v->nb = c->n_bins;
+  v->prec = c->prec;
+  v->alpha = c->alpha;
+  v->seed = c->seed;
+  v->stream_id = c->stream_id;
+  vgx_status s = prepare_params(v, c);
+  if (s != VGX_OK) { delete v; return s; }
+  v->max_wg = device_cus() * (c->kind == VGX_TTBAR ? 4 : 8);
+  v->pstride = 4 + v->dim * v->nb;
+  const size_t ne = (size_t)v->dim * (v->nb + 1);
+  do {
+    if ((s = dev_alloc((void**)&v->edges, sizeof(double) * ne)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&v->hist, sizeof(double) * v->dim * v->nb)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&v->partials, sizeof(double) * (size_t)v->max_wg * v->pstride)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&v->rec, sizeof(IterRecord) * MAX_RECORDS)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&v->comb, sizeof(Combined))) != VGX_OK) break;
+    if ((s = host_alloc(&v->pinned, sizeof(IterRecord) * MAX_RECORDS + sizeof(Combined) + sizeof(double) * ne)) != VGX_OK) break;
+  } while (0);
+  if (s != VGX_OK) { vegas_destroy(v); return s; }
+  double* h = (double*)v->pinned;
+  for (int j = 0; j < v->dim; ++j)
+    for (int k = 0; k <= v->nb; ++k) h[j * (v->nb + 1) + k] = (double)k / (double)v->nb;
+  hipError_t e = hipMemcpyAsync(v->edges, h, sizeof(double) * ne, hipMemcpyHostToDevice, v->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(v->hist, 0, sizeof(double) * v->dim * v->nb, v->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(v->comb, 0, sizeof(Combined), v->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(v->stream);
+  if (e != hipSuccess) { s = hip_fail(e, "vegas_create init", __FILE__, __LINE__); vegas_destroy(v); return s; }
+  *out = v;
+  return VGX_OK;
+}
+
+static vgx_status iterate_enqueue(vgx_vegas* v, int64_t n, int32_t iteration) {
+  VGX_CHECK(v, "vegas_iterate: null context");
+  VGX_CHECK(n >= 2, "vegas_iterate: need n >= 2 samples");
+  if (v->n_rec >= MAX_RECORDS) { set_error("vegas_iterate: more than %d stored estimates", MAX_RECORDS); return VGX_ESTATE; }
+  VGX_TRY(timed_begin(v));
+  VGX_TRY(launch_philox_iter(v, n, iteration));
+  VGX_TRY(timed_end(v));
+  VGX_TRY(launch_reduce(v, grid_for(v, n), v->pstride, n));
+  v->have_hist = true;
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, vgx_iter_result* out) {
+  VGX_TRY(iterate_enqueue(v, n, iteration));
+  const int k = v->n_rec++;
+  return read_record(v, k, out);
+}
+
+extern "C" vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration) {
+  VGX_TRY(iterate_enqueue(v, n, iteration));
+  v->n_rec++;
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_refine(vgx_vegas* v) {
+  VGX_CHECK(v, "vegas_refine: null context");
+  if (!v->have_hist) { set_error("vegas_refine: no histogram (run vegas_iterate first)"); return VGX_ESTATE; }
+  hipLaunchKernelGGL(k_refine, dim3(v->dim), dim3(64), 0, v->stream, v->edges, v->hist, v->nb, v->alpha);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_result(vgx_vegas* v, double* mean, double* sigma, double* chi2, int32_t* n_used) {
+  VGX_CHECK(v, "vegas_result: null context");
+  Combined* h = (Combined*)((char*)v->pinned + sizeof(IterRecord) * MAX_RECORDS);
+  if (v->n_rec == 0) {
+    if (mean) *mean = 0.0;
+    if (sigma) *sigma = 0.0;
+    if (chi2) *chi2 = 0.0;
+    if (n_used) *n_used = 0;
+    return VGX_OK;
+  }
+  VGX_HIP(hipMemcpyAsync(h, v->comb, sizeof(Combined), hipMemcpyDeviceToHost, v->stream));
+  VGX_HIP(hipStreamSynchronize(v->stream));
+  if (mean) *mean = h->mean;
+  if (sigma) *sigma = h->sigma;
+  if (chi2) *chi2 = h->chi2_dof;
+  if (n_used) *n_used = h->n_used;
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_results(vgx_vegas* v, vgx_iter_result* out, int32_t cap, int32_t* count) {
+  VGX_CHECK(v && count && (cap == 0 || out), "vegas_results: bad argument");
+  const int m = v->n_rec < cap ? v->n_rec : cap;
+  IterRecord* h = (IterRecord*)v->pinned;
+  if (m > 0) {
+    VGX_HIP(hipMemcpyAsync(h, v->rec, sizeof(IterRecord) * m, hipMemcpyDeviceToHost, v->stream));
+    VGX_HIP(hipStreamSynchronize(v->stream));
+  }
+  for (int k = 0; k < m; ++k) {
+    out[k].mean = h[k].mean;
+    out[k].var = h[k].var;
+    out[k].s1 = h[k].s1;
+    out[k].s2 = h[k].s2;
+    out[k].n = h[k].n;
+  }
+  *count = v->n_rec;
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_reset_results(vgx_vegas* v) {
+  VGX_CHECK(v, "vegas_reset_results: null context");
+  v->n_rec = 0;
+  VGX_HIP(hipMemsetAsync(v->comb, 0, sizeof(Combined), v->stream));
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_get_grid(vgx_vegas* v, double* edges) {
+  VGX_CHECK(v && edges, "vegas_get_grid: null argument");
+  VGX_HIP(hipMemcpyAsync(edges, v->edges, sizeof(double) * v->dim * (v->nb + 1), hipMemcpyDeviceToHost, v->stream));
+  VGX_HIP(hipStreamSynchronize(v->stream));
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_set_grid(vgx_vegas* v, const double* edges) {
+  VGX_CHECK(v && edges, "vegas_set_grid: null argument");
+  for (int j = 0; j < v->dim; ++j) {
+    const double* e = edges + (size_t)j * (v->nb + 1);
+    VGX_CHECK(e[0] == 0.0 && e[v->nb] == 1.0, "vegas_set_grid: edges of dim %d must span [0, 1]", j);
+    for (int k = 0; k < v->nb; ++k) VGX_CHECK(e[k + 1] > e[k], "vegas_set_grid: edges of dim %d not increasing", j);
+  }
+  const size_t bytes = sizeof(double) * v->dim * (v->nb + 1);
+  double* h = (double*)((char*)v->pinned + sizeof(IterRecord) * MAX_RECORDS + sizeof(Combined));
+  VGX_HIP(hipStreamSynchronize(v->stream));
+  memcpy(h, edges, bytes);
+  VGX_HIP(hipMemcpyAsync(v->edges, h, bytes, hipMemcpyHostToDevice, v->stream));
+  VGX_HIP(hipStreamSynchronize(v->stream));
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_get_hist(vgx_vegas* v, double* hist) {
+  VGX_CHECK(v && hist, "vegas_get_hist: null argument");
+  VGX_HIP(hipMemcpyAsync(hist, v->hist, sizeof(double) * v->dim * v->nb, hipMemcpyDeviceToHost, v->stream));
+  VGX_HIP(hipStreamSynchronize(v->stream));
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t iteration, double* u, double* g) {
+  VGX_CHECK(v, "vegas_sample: null context");
+  VGX_CHECK(n >= 0 && first >= 0, "vegas_sample: negative range");
+  if (n == 0 || (!u && !g)) return VGX_OK;
+  return launch_sample(v, first, n, iteration, u, g);
+}
+
+extern "C" vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double* y, const double* logq,
+                                           vgx_iter_result* out) {
+  VGX_CHECK(v, "vegas_iterate_points: null context");
+  VGX_CHECK(n >= 2 && y, "vegas_iterate_points: need n >= 2 and points");
+  if (v->n_rec >= MAX_RECORDS) { set_error("vegas_iterate_points: too many stored estimates"); return VGX_ESTATE; }
+  VGX_TRY(timed_begin(v));
+  VGX_TRY(launch_points_iter(v, n, y, logq));
+  VGX_TRY(timed_end(v));
+  VGX_TRY(launch_reduce(v, grid_for(v, n), 4, n));
+  const int k = v->n_rec++;
+  return read_record(v, k, out);
+}
+
+extern "C" void* vegas_stream(vgx_vegas* v) { return v ? (void*)v->stream : nullptr; }
+
+extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
+  VGX_CHECK(v, "vegas_set_timing: null context");
+  if (enable && !v->ev[0]) {
+    VGX_HIP(hipEventCreate(&v->ev[0]));
+    VGX_HIP(hipEventCreate(&v->ev[1]));
+  }
+  v->timing = enable != 0;
+  v->t_ms = 0.0;
+  v->t_launches = 0;
+  return VGX_OK;
+}
+
+extern "C" vgx_status vegas_kernel_time(vgx_vegas* v, double* ms, int64_t* launches) {
+  VGX_CHECK(v && ms && launches, "vegas_kernel_time: null argument");
+  *ms = v->t_ms;
+  *launches = v->t_launches;
+  return VGX_OK;
+}
+
+extern "C" void vegas_destroy(vgx_vegas* v) {
+  if (!v) return;
+  if (v->stream) hipStreamSynchronize(v->stream);
+  hipFree(v->edges);
+  hipFree(v->hist);
+  hipFree(v->partials);
+  hipFree(v->rec);
+  hipFree(v->comb);
+  if (v->pinned) hipHostFree(v->pinned);
+  if (v->ev[0]) hipEventDestroy(v->ev[0]);
+  if (v->ev[1]) hipEventDestroy(v->ev[1]);
+  delete v;
+}

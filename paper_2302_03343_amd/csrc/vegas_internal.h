@@ -1,0 +1,195 @@
+// Pieces of the VEGAS path shared by the single-integral kernels
+// (vegas.hip) and the batched persistent kernel (batch.hip): the grid map,
+// the per-iteration record and its inverse-variance combination, Lepage's
+// refinement of one dimension, and the context structure.
+#pragma once
+
+#include "common.h"
+#include "integrands.h"
+#include "ttbar.h"
+
+namespace vgx {
+
+struct IterRecord {
+  double mean, var, s1, s2;
+  int64_t n;
+  int32_t finite;
+  int32_t pad;
+};
+
+struct Combined {
+  double mean, sigma, chi2_dof;
+  int32_t n_used;
+  int32_t pad;
+};
+
+constexpr int MAX_RECORDS = 4096;
+
+// Grid map (inverse transform through the piecewise-constant density of the
+// bins): i = min(floor(u N), N-1), delta = u N - i,
+// x = e_i + delta (e_{i+1} - e_i), J = prod_j N (e_{i+1} - e_i).
+template <int D>
+__device__ __forceinline__ double grid_map(const double (&u)[D], const double* se, int nb, double (&x)[D],
+                                           int (&idx)[D]) {
+  double jac = 1.0;
+  const double dnb = (double)nb;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double t = u[j] * dnb;
+    int i = (int)t;
+    i = i < nb - 1 ? i : nb - 1;
+    i = i > 0 ? i : 0;  // points given by the caller may sit on or outside the cube's faces
+    const double delta = t - (double)i;
+    const double lo = se[j * (nb + 1) + i];
+    const double w = se[j * (nb + 1) + i + 1] - lo;
+    x[j] = fma(delta, w, lo);
+    jac *= dnb * w;
+    idx[j] = i;
+  }
+  return jac;
+}
+
+// Estimate of one iteration from its compensated sums, stored as record
+// k_rec, then the inverse-variance combination of the finite records
+// 0..k_rec with chi^2/dof:  E = S1/n, var(E) = max(S2/n - E^2, 0)/(n-1);
+// E_bar = S^2 sum E_i/S_i^2, 1/S^2 = sum 1/S_i^2,
+// chi^2/dof = sum (E_i - E_bar)^2/S_i^2/(M-1).  A zero variance makes that
+// estimate exact (sigma 0).  Single-thread device code.
+__device__ inline void finalize_record(double s1, double s2, int64_t n, IterRecord* rec, int k_rec, Combined* comb) {
+  IterRecord r;
+  r.s1 = s1;
+  r.s2 = s2;
+  r.n = n;
+  r.mean = s1 / (double)n;
+  const double m2 = s2 / (double)n - r.mean * r.mean;
+  r.var = n > 1 ? (m2 > 0.0 ? m2 : 0.0) / (double)(n - 1) : 0.0;
+  r.finite = isfinite(r.mean) && isfinite(r.var);
+  r.pad = 0;
+  rec[k_rec] = r;
+  Combined c{0.0, 0.0, 0.0, 0, 0};
+  int zero_var = -1;
+  int used = 0;
+  for (int k = 0; k <= k_rec; ++k) {
+    if (!rec[k].finite) continue;
+    ++used;
+    if (rec[k].var == 0.0 && zero_var < 0) zero_var = k;
+  }
+  if (zero_var >= 0) {
+    c.mean = rec[zero_var].mean;
+  } else if (used > 0) {
+    Comp wsum, msum;
+    for (int k = 0; k <= k_rec; ++k) {
+      if (!rec[k].finite) continue;
+      wsum.add(1.0 / rec[k].var);
+      msum.add(rec[k].mean / rec[k].var);
+    }
+    c.mean = msum.value() / wsum.value();
+    c.sigma = sqrt(1.0 / wsum.value());
+    if (used > 1) {
+      Comp chi;
+      for (int k = 0; k <= k_rec; ++k) {
+        if (!rec[k].finite) continue;
+        const double dd = rec[k].mean - c.mean;
+        chi.add(dd * dd / rec[k].var);
+      }
+      c.chi2_dof = chi.value() / (double)(used - 1);
+    }
+  }
+  c.n_used = used;
+  *comb = c;
+}
+
+// Lepage's refinement of one dimension, by one 64-thread workgroup:
+// 3-point smoothing of the accumulated (f J)^2 per bin, normalisation to
+// p_i, damping r_i = ((1 - p_i)/ln(1/p_i))^alpha, re-binning to equal shares
+// of sum r with r spread uniformly inside each old bin.  A dimension whose
+// histogram is all zero is left unchanged.
+__device__ inline void refine_dim(double* __restrict__ ej, const double* __restrict__ hj, int nb, double alpha) {
+  __shared__ double d[VGX_MAX_BINS], r[VGX_MAX_BINS], cum[VGX_MAX_BINS + 1], e[VGX_MAX_BINS + 1];
+  __shared__ double tot_d, tot_sm;
+  for (int i = threadIdx.x; i < nb; i += 64) d[i] = hj[i];
+  for (int i = threadIdx.x; i <= nb; i += 64) e[i] = ej[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += d[i];
+    tot_d = s;
+  }
+  __syncthreads();
+  if (!(tot_d > 0.0)) return;  // uniform decision: every thread returns
+  for (int i = threadIdx.x; i < nb; i += 64) {
+    double sm;
+    if (nb == 1) sm = d[0];
+    else if (i == 0) sm = 0.5 * (d[0] + d[1]);
+    else if (i == nb - 1) sm = 0.5 * (d[nb - 2] + d[nb - 1]);
+    else sm = (d[i - 1] + d[i] + d[i + 1]) / 3.0;
+    r[i] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += r[i];
+    tot_sm = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += 64) {
+    const double p = r[i] / tot_sm;
+    double v;
+    if (p <= 0.0) v = 0.0;
+    else if (p >= 1.0) v = 1.0;
+    else v = pow((1.0 - p) / log(1.0 / p), alpha);
+    r[i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    cum[0] = 0.0;
+    for (int i = 0; i < nb; ++i) { s += r[i]; cum[i + 1] = s; }
+  }
+  __syncthreads();
+  const double step = cum[nb] / (double)nb;
+  for (int k = 1 + threadIdx.x; k < nb; k += 64) {
+    const double target = (double)k * step;
+    // smallest i in [0, nb-1) with cum[i+1] >= target, else nb-1
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cum[mid + 1] >= target) hi = mid; else lo = mid + 1;
+    }
+    const int i = lo;
+    double frac = 0.0;
+    if (r[i] > 0.0) {
+      frac = (target - cum[i]) / r[i];
+      frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+    }
+    ej[k] = e[i] + frac * (e[i + 1] - e[i]);
+  }
+}
+
+}  // namespace vgx
+
+struct vgx_vegas {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int kind = 0, dim = 0, nb = 0, prec = 0;
+  double alpha = 1.5;
+  uint64_t seed = 0;
+  uint32_t stream_id = 0;
+  vgx::IntegrandParams prm{};
+  vgx::TTbarConst tt{};
+  int max_wg = 0;
+  int pstride = 0;
+  double* edges = nullptr;          // [dim][nb+1]
+  double* hist = nullptr;           // [dim][nb]
+  double* partials = nullptr;       // [max_wg][pstride]
+  vgx::IterRecord* rec = nullptr;   // [MAX_RECORDS]
+  vgx::Combined* comb = nullptr;
+  void* pinned = nullptr;           // host readback (IterRecord + Combined + grid)
+  int n_rec = 0;
+  bool have_hist = false;
+  // kernel timing
+  bool timing = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double t_ms = 0.0;
+  int64_t t_launches = 0;
+};

@@ -1,0 +1,404 @@
+"""ctypes binding of libvgx.so (the C ABI in include/vgx.h).
+
+Argument marshalling only: every function below has the name of the C entry
+point it calls, converts torch tensors to device pointers and numpy arrays to
+host pointers, passes the current HIP stream, and raises VgxError on a
+non-zero status.  No arithmetic of the method happens here.  Importing this
+module fails loudly if the compiled library is missing; there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libvgx.so")
+
+VGX_OK, VGX_EINVAL, VGX_ENOMEM, VGX_EDEVICE, VGX_ERANGE, VGX_ENUMERIC, VGX_EFALLBACK, VGX_ESTATE = range(8)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ERANGE", 5: "ENUMERIC",
+                6: "EFALLBACK", 7: "ESTATE"}
+GAUSS, GENZ_OSC, GENZ_PEAK, TTBAR = 0, 1, 2, 3
+F64, F32 = 0, 1
+MAX_DIM, MAX_BINS = 12, 256
+
+
+class VgxError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libvgx.so not found at {LIB_PATH}; build it with `python -m paper_2302_03343_amd.build` "
+        "(the HIP path has no CPU fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+_vp = C.c_void_p
+_i32, _i64, _u32, _u64, _f32, _f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float, C.c_double
+
+
+class IterResult(C.Structure):
+    _fields_ = [("mean", _f64), ("var", _f64), ("s1", _f64), ("s2", _f64), ("n", _i64)]
+
+    def as_dict(self):
+        return dict(mean=self.mean, var=self.var, s1=self.s1, s2=self.s2, n=self.n)
+
+
+class VegasCfg(C.Structure):
+    _fields_ = [("kind", _i32), ("dim", _i32), ("n_bins", _i32), ("alpha", _f64), ("seed", _u64),
+                ("stream_id", _u32), ("prec", _i32), ("params", C.POINTER(_f64)), ("n_params", _i32),
+                ("pdf", _vp)]
+
+
+class PdfDesc(C.Structure):
+    _fields_ = [("n_x", _i32), ("n_sub", _i32), ("n_flav", _i32), ("x_knots", C.POINTER(_f64)),
+                ("nq_per_sub", C.POINTER(_i32)), ("q2_knots", C.POINTER(_f64)), ("xf", C.POINTER(_f64))]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_S = C.c_int  # vgx_status
+_c = {}
+for _name, _res, _args in [
+    ("vgx_last_error", C.c_char_p, []),
+    ("vgx_version", C.c_char_p, []),
+    ("pdf_create", _S, [C.POINTER(PdfDesc), _vp, C.POINTER(_vp)]),
+    ("pdf_interp", _S, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
+    ("pdf_out_of_range", _S, [_vp, _vp, C.POINTER(_i64)]),
+    ("pdf_bounds", _S, [_vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64)]),
+    ("pdf_destroy", None, [_vp]),
+    ("vegas_create", _S, [C.POINTER(VegasCfg), _vp, C.POINTER(_vp)]),
+    ("vegas_iterate", _S, [_vp, _i64, _i32, C.POINTER(IterResult)]),
+    ("vegas_iterate_async", _S, [_vp, _i64, _i32]),
+    ("vegas_refine", _S, [_vp]),
+    ("vegas_result", _S, [_vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_i32)]),
+    ("vegas_results", _S, [_vp, C.POINTER(IterResult), _i32, C.POINTER(_i32)]),
+    ("vegas_reset_results", _S, [_vp]),
+    ("vegas_get_grid", _S, [_vp, C.POINTER(_f64)]),
+    ("vegas_set_grid", _S, [_vp, C.POINTER(_f64)]),
+    ("vegas_get_hist", _S, [_vp, C.POINTER(_f64)]),
+    ("vegas_sample", _S, [_vp, _i64, _i64, _i32, _vp, _vp]),
+    ("vegas_iterate_points", _S, [_vp, _i64, _vp, _vp, C.POINTER(IterResult)]),
+    ("vegas_stream", _vp, [_vp]),
+    ("vegas_set_timing", _S, [_vp, _i32]),
+    ("vegas_kernel_time", _S, [_vp, C.POINTER(_f64), C.POINTER(_i64)]),
+    ("vegas_destroy", None, [_vp]),
+]:
+    _c[_name] = _sig(_name, _res, *_args)
+
+
+def _optional(name, res, *args):
+    if hasattr(_lib, name):
+        _c[name] = _sig(name, res, *args)
+
+
+_optional("batch_create", _S, C.POINTER(_vp), _i32, C.POINTER(_i64), _i32, _i32, _vp, C.POINTER(_vp))
+_optional("batch_iterate", _S, _vp, _i32, C.POINTER(IterResult))
+_optional("batch_config", _S, _vp, C.POINTER(_i32), C.POINTER(_i32))
+_optional("batch_destroy", None, _vp)
+_optional("flow_num_params", _i64, _i32, _i32, _i32, _i32)
+_optional("flow_create", _S, _i32, _i32, _i32, _i32, C.POINTER(_f32), _i64, _vp, C.POINTER(_vp))
+_optional("flow_sample", _S, _vp, _i64, _u64, _u32, _i32, _vp, _vp, _vp)
+_optional("flow_density", _S, _vp, _i64, _vp, _vp, _vp, _vp)
+_optional("flow_loss_grad", _S, _vp, _i64, _vp, _vp, C.POINTER(_f64), C.POINTER(_f32))
+_optional("flow_train_step", _S, _vp, _i64, _vp, _vp, _f32, C.POINTER(_f64))
+_optional("flow_adam", _S, _vp, _vp, _f32)
+_optional("flow_get_params", _S, _vp, C.POINTER(_f32), _i64, C.POINTER(_i64))
+_optional("flow_set_params", _S, _vp, C.POINTER(_f32), _i64)
+_optional("flow_destroy", None, _vp)
+
+EXPORTED = sorted(_c)
+
+
+def _check(st, where):
+    if st != VGX_OK:
+        msg = _c["vgx_last_error"]().decode(errors="replace")
+        raise VgxError(st, where, msg)
+
+
+def last_error():
+    return _c["vgx_last_error"]().decode(errors="replace")
+
+
+def version():
+    return _c["vgx_version"]().decode()
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+# ---------------------------------------------------------------------------
+# PDF
+# ---------------------------------------------------------------------------
+def pdf_create(x_knots, q2_knots, xf, stream=None):
+    """x_knots (n_x,), q2_knots list of per-subgrid arrays, xf list of
+    (n_flav, n_q[s], n_x) arrays (host, FP64).  Returns an opaque handle."""
+    x = np.ascontiguousarray(x_knots, dtype=np.float64)
+    nq = np.ascontiguousarray([len(q) for q in q2_knots], dtype=np.int32)
+    q2 = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.float64) for q in q2_knots]))
+    vals = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.float64).ravel() for v in xf]))
+    n_flav = int(np.asarray(xf[0]).shape[0])
+    d = PdfDesc(len(x), len(nq), n_flav, _hptr(x, _f64), _hptr(nq, _i32), _hptr(q2, _f64), _hptr(vals, _f64))
+    h = _vp()
+    _check(_c["pdf_create"](C.byref(d), _stream(stream), C.byref(h)), "pdf_create")
+    return h
+
+
+def pdf_interp(pdf, x, q2, out, out_dtype=None, stream=None):
+    import torch
+    n = x.numel()
+    if out_dtype is None:
+        out_dtype = F64 if out.dtype == torch.float64 else F32
+    want = torch.float64 if out_dtype == F64 else torch.float32
+    _check(_c["pdf_interp"](pdf, n, _dptr(x, torch.float64, n, "x"), _dptr(q2, torch.float64, n, "q2"), out_dtype,
+                            _dptr(out, want, None, "out"), _stream(stream)), "pdf_interp")
+    return out
+
+
+def pdf_out_of_range(pdf, stream=None):
+    c = _i64()
+    st = _c["pdf_out_of_range"](pdf, _stream(stream), C.byref(c))
+    if st not in (VGX_OK, VGX_ERANGE):
+        _check(st, "pdf_out_of_range")
+    return int(c.value)
+
+
+def pdf_bounds(pdf):
+    v = [_f64() for _ in range(4)]
+    _check(_c["pdf_bounds"](pdf, *[C.byref(t) for t in v]), "pdf_bounds")
+    return tuple(t.value for t in v)
+
+
+def pdf_destroy(pdf):
+    _c["pdf_destroy"](pdf)
+
+
+# ---------------------------------------------------------------------------
+# VEGAS
+# ---------------------------------------------------------------------------
+def vegas_create(kind, dim, n_bins, alpha, seed, stream_id=0, prec=F64, params=(), pdf=None, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    cfg = VegasCfg(kind, dim, n_bins, alpha, seed, stream_id, prec, _hptr(p, _f64) if p.size else None, p.size,
+                   pdf)
+    h = _vp()
+    _check(_c["vegas_create"](C.byref(cfg), _stream(stream), C.byref(h)), "vegas_create")
+    return h
+
+
+def vegas_iterate(v, n, iteration, allow_numeric=False):
+    r = IterResult()
+    st = _c["vegas_iterate"](v, n, iteration, C.byref(r))
+    if not (allow_numeric and st == VGX_ENUMERIC):
+        _check(st, "vegas_iterate")
+    return r.as_dict()
+
+
+def vegas_iterate_async(v, n, iteration):
+    _check(_c["vegas_iterate_async"](v, n, iteration), "vegas_iterate_async")
+
+
+def vegas_refine(v):
+    _check(_c["vegas_refine"](v), "vegas_refine")
+
+
+def vegas_result(v):
+    m, s, c, k = _f64(), _f64(), _f64(), _i32()
+    _check(_c["vegas_result"](v, C.byref(m), C.byref(s), C.byref(c), C.byref(k)), "vegas_result")
+    return dict(mean=m.value, sigma=s.value, chi2_dof=c.value, n_used=k.value)
+
+
+def vegas_results(v, cap=4096):
+    arr = (IterResult * cap)()
+    cnt = _i32()
+    _check(_c["vegas_results"](v, arr, cap, C.byref(cnt)), "vegas_results")
+    return [arr[k].as_dict() for k in range(min(cnt.value, cap))]
+
+
+def vegas_reset_results(v):
+    _check(_c["vegas_reset_results"](v), "vegas_reset_results")
+
+
+def vegas_get_grid(v, dim, n_bins):
+    e = np.empty((dim, n_bins + 1), dtype=np.float64)
+    _check(_c["vegas_get_grid"](v, _hptr(e, _f64)), "vegas_get_grid")
+    return e
+
+
+def vegas_set_grid(v, edges):
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    _check(_c["vegas_set_grid"](v, _hptr(e, _f64)), "vegas_set_grid")
+
+
+def vegas_get_hist(v, dim, n_bins):
+    h = np.empty((dim, n_bins), dtype=np.float64)
+    _check(_c["vegas_get_hist"](v, _hptr(h, _f64)), "vegas_get_hist")
+    return h
+
+
+def vegas_sample(v, first, n, iteration, u=None, g=None):
+    import torch
+    _check(_c["vegas_sample"](v, first, n, iteration, _dptr(u, torch.float64, None, "u"),
+                              _dptr(g, torch.float64, n if g is not None else None, "g")), "vegas_sample")
+
+
+def vegas_iterate_points(v, y, logq=None, allow_numeric=False):
+    import torch
+    n = y.shape[-1]
+    r = IterResult()
+    st = _c["vegas_iterate_points"](v, n, _dptr(y, torch.float64, None, "y"),
+                                    _dptr(logq, torch.float64, n if logq is not None else None, "logq"),
+                                    C.byref(r))
+    if not (allow_numeric and st == VGX_ENUMERIC):
+        _check(st, "vegas_iterate_points")
+    return r.as_dict()
+
+
+def vegas_stream(v):
+    return _c["vegas_stream"](v)
+
+
+def vegas_set_timing(v, enable=True):
+    _check(_c["vegas_set_timing"](v, 1 if enable else 0), "vegas_set_timing")
+
+
+def vegas_kernel_time(v):
+    ms, k = _f64(), _i64()
+    _check(_c["vegas_kernel_time"](v, C.byref(ms), C.byref(k)), "vegas_kernel_time")
+    return ms.value, k.value
+
+
+def vegas_destroy(v):
+    _c["vegas_destroy"](v)
+
+
+# ---------------------------------------------------------------------------
+# Batched integration
+# ---------------------------------------------------------------------------
+def batch_create(ctxs, n_samples, tile=0, block=0, stream=None):
+    arr = (_vp * len(ctxs))(*[c.value if isinstance(c, _vp) else c for c in ctxs])
+    ns = np.ascontiguousarray(n_samples, dtype=np.int64)
+    h = _vp()
+    _check(_c["batch_create"](arr, len(ctxs), _hptr(ns, _i64), tile, block, _stream(stream), C.byref(h)),
+           "batch_create")
+    return h
+
+
+def batch_iterate(b, iteration, count):
+    arr = (IterResult * count)()
+    _check(_c["batch_iterate"](b, iteration, arr), "batch_iterate")
+    return [arr[k].as_dict() for k in range(count)]
+
+
+def batch_config(b):
+    t, bl = _i32(), _i32()
+    _check(_c["batch_config"](b, C.byref(t), C.byref(bl)), "batch_config")
+    return t.value, bl.value
+
+
+def batch_destroy(b):
+    _c["batch_destroy"](b)
+
+
+# ---------------------------------------------------------------------------
+# Flow
+# ---------------------------------------------------------------------------
+def flow_num_params(dim, n_layers=4, n_bins=32, hidden=64):
+    return int(_c["flow_num_params"](dim, n_layers, n_bins, hidden))
+
+
+def flow_create(dim, params, n_layers=4, n_bins=32, hidden=64, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    h = _vp()
+    _check(_c["flow_create"](dim, n_layers, n_bins, hidden, _hptr(p, _f32), p.size, _stream(stream), C.byref(h)),
+           "flow_create")
+    return h
+
+
+def flow_sample(f, n, seed, stream_id, iteration, y, logq, stream=None):
+    import torch
+    _check(_c["flow_sample"](f, n, seed, stream_id, iteration, _dptr(y, torch.float64, None, "y"),
+                             _dptr(logq, torch.float64, n, "logq"), _stream(stream)), "flow_sample")
+
+
+def flow_density(f, y, logq, u=None, stream=None):
+    import torch
+    n = y.shape[-1]
+    _check(_c["flow_density"](f, n, _dptr(y, torch.float64, None, "y"), _dptr(u, torch.float64, None, "u"),
+                              _dptr(logq, torch.float64, n, "logq"), _stream(stream)), "flow_density")
+
+
+def flow_loss_grad(f, y, g, n_params=None):
+    import torch
+    n = y.shape[-1]
+    loss = _f64()
+    grad = np.empty(n_params, dtype=np.float32) if n_params else None
+    _check(_c["flow_loss_grad"](f, n, _dptr(y, torch.float64, None, "y"), _dptr(g, torch.float64, n, "g"),
+                                C.byref(loss), _hptr(grad, _f32) if grad is not None else None), "flow_loss_grad")
+    return loss.value, grad
+
+
+def flow_train_step(f, y, g, lr, sync=True, allow_fallback=False):
+    import torch
+    n = y.shape[-1]
+    loss = _f64()
+    st = _c["flow_train_step"](f, n, _dptr(y, torch.float64, None, "y"), _dptr(g, torch.float64, n, "g"), lr,
+                               C.byref(loss) if sync else None)
+    if not (allow_fallback and st == VGX_EFALLBACK):
+        _check(st, "flow_train_step")
+    return loss.value if sync else None
+
+
+def flow_adam(f, grad, lr):
+    import torch
+    _check(_c["flow_adam"](f, _dptr(grad, torch.float32, None, "grad"), lr), "flow_adam")
+
+
+def flow_get_params(f, n_params):
+    p = np.empty(n_params, dtype=np.float32)
+    n = _i64()
+    _check(_c["flow_get_params"](f, _hptr(p, _f32), n_params, C.byref(n)), "flow_get_params")
+    return p[:n.value]
+
+
+def flow_set_params(f, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_c["flow_set_params"](f, _hptr(p, _f32), p.size), "flow_set_params")
+
+
+def flow_destroy(f):
+    _c["flow_destroy"](f)

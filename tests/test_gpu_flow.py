@@ -1,0 +1,297 @@
+"""GPU coupling flow (MFMA, BF16 operands, FP32 accumulation) vs the oracle.
+
+The oracle evaluates the same network in FP64 with the kernel's BF16 weights
+(biases stay FP32 on both sides); the remaining difference is the BF16
+rounding of the activations that feed each matrix product (relative 2^-9).
+Derived bars (BF16 mode): per-sample |d log q| <= 2e-2 and |d y| <= 2e-3;
+the loss to 1e-2 relative; gradients to 3e-2 in relative L2 norm per weight
+tensor.  A bin decision flips where a sample lies within the activation
+error of a bin edge (density direction) or of a cumulative knot (sampling
+direction); there log q jumps, so the per-sample bars are asserted for
+samples whose oracle-side margin exceeds 1e-3 (ten times the activation
+error of a cumulative value) and for >= 90% of all samples.  Output-layer
+weights are drawn with a scale that gives logits of O(1) spread, as in a
+flow part-way through training; much larger logits make log q so steep
+that the comparison (and g/q itself) is dominated by bin-edge effects.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import flow as of
+from oracle.integrands import gauss, gauss_integral
+from oracle.philox import sample_uniforms
+from synth import he_init_segments
+
+pytestmark = pytest.mark.gpu
+
+L, K, H = 4, 32, 64
+
+
+def bf16(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def weights_bf16(theta, dim):
+    """Round the W segments (not the biases) to BF16, as the kernels do."""
+    th = np.array(theta, dtype=np.float32, copy=True)
+    off = 0
+    for sh in of.layer_shapes(dim, L, K, H):
+        sz = sh["sizes"]
+        for k, size in enumerate(sz):
+            if k in (0, 2, 4):
+                th[off:off + size] = bf16(th[off:off + size])
+            off += size
+    return th.astype(np.float64)
+
+
+def random_theta(dim, seed, out_scale=0.1):
+    rng = np.random.default_rng(seed)
+    th = he_init_segments(of.init_segments(dim, L, K, H), seed)
+    off = 0
+    for sh in of.layer_shapes(dim, L, K, H):
+        sz = sh["sizes"]
+        o3 = off + sum(sz[:4])
+        th[o3:o3 + sz[4] + sz[5]] = rng.normal(0, out_scale, sz[4] + sz[5]).astype(np.float32)
+        # non-zero hidden biases exercise the bias path
+        th[off + sz[0]:off + sz[0] + sz[1]] = rng.normal(0, 0.1, sz[1]).astype(np.float32)
+        off += sum(sz)
+    return th
+
+
+def margins(theta, pts, dim, direction):
+    """Oracle-side distance of every sample to the nearest decision boundary
+    over all layers (bin edges in z for the density direction, cumulative
+    knots for the sampling direction)."""
+    layers = of.unpack(theta, dim, L, K, H)
+    z = np.array(pts, dtype=np.float64, copy=True)
+    n = z.shape[0]
+    marg = np.full(n, np.inf)
+    seq = layers if direction == "density" else list(reversed(layers))
+    for p in seq:
+        A, B = p["A"], p["B"]
+        Q = of._mlp(p, z[:, A], K)["Q"]
+        cum = np.concatenate([np.zeros((n, len(B), 1)), np.cumsum(Q, axis=2)], axis=2)
+        for jb, j in enumerate(B):
+            if direction == "density":
+                t = K * z[:, j]
+                marg = np.minimum(marg, np.abs(t - np.round(t)) / K)
+                b = np.minimum(np.floor(t).astype(int), K - 1)
+                z[:, j] = cum[np.arange(n), jb, b] + (t - b) * Q[np.arange(n), jb, b]
+            else:
+                v = z[:, j]
+                marg = np.minimum(marg, np.min(np.abs(cum[:, jb, 1:K] - v[:, None]), axis=1))
+                b = np.minimum(np.sum(cum[:, jb, 1:K] <= v[:, None], axis=1), K - 1)
+                z[:, j] = (b + (v - cum[np.arange(n), jb, b]) / Q[np.arange(n), jb, b]) / K
+    return marg
+
+
+def make_flow(vgx, dim, theta):
+    return vgx.flow_create(dim, theta, L, K, H)
+
+
+@pytest.mark.parametrize("dim,count", [(3, 29760), (8, 51200), (2, None), (12, None)])
+def test_parameter_count_matches_oracle(vgx, dim, count):
+    n = vgx.flow_num_params(dim, L, K, H)
+    assert n == of.n_params(dim, L, K, H)
+    if count:
+        assert n == count
+
+
+@pytest.mark.parametrize("dim", [3, 8])
+def test_identity_initialisation(vgx, dim):
+    import torch
+    print(f"flow identity dim={dim}", flush=True)
+    th = he_init_segments(of.init_segments(dim, L, K, H), 0)
+    f = make_flow(vgx, dim, th)
+    try:
+        n = 4099
+        y = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(f, n, 5, 1, 0, y, lq)
+        torch.cuda.synchronize()
+        u = sample_uniforms(5, 1 | (1 << 23), 0, np.arange(n, dtype=np.uint64), dim)
+        assert np.max(np.abs(y.cpu().numpy().T - u)) < 2e-7
+        assert np.all(lq.cpu().numpy() == 0.0)
+    finally:
+        vgx.flow_destroy(f)
+
+
+@pytest.mark.parametrize("dim", [3, 8])
+def test_sampling_direction_matches_oracle(vgx, dim):
+    import torch
+    print(f"flow sample parity dim={dim}", flush=True)
+    th = random_theta(dim, 10 + dim)
+    thb = weights_bf16(th, dim)
+    f = make_flow(vgx, dim, th)
+    try:
+        n = 20000 + 17
+        y = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(f, n, 7, 3, 2, y, lq)
+        u = sample_uniforms(7, 3 | (1 << 23), 2, np.arange(n, dtype=np.uint64), dim)
+        yr, lqr = of.sample(thb, u, dim, L, K, H)
+        dy = np.max(np.abs(y.cpu().numpy().T - yr), axis=1)
+        dl = np.abs(lq.cpu().numpy() - lqr)
+        m = margins(thb, u, dim, "sampling")
+        safe = m > 1e-3
+        print(f"  median |dlogq| {np.median(dl):.2e}, p90 {np.percentile(dl, 90):.2e}, safe frac {safe.mean():.2f}")
+        assert np.all(dl[safe] <= 2e-2) and np.all(dy[safe] <= 2e-3)
+        assert np.mean((dl <= 2e-2) & (dy <= 2e-3)) >= 0.9
+    finally:
+        vgx.flow_destroy(f)
+
+
+@pytest.mark.parametrize("dim", [3, 8])
+def test_density_direction_matches_oracle_and_inverts_sampling(vgx, dim):
+    import torch
+    print(f"flow density parity dim={dim}", flush=True)
+    th = random_theta(dim, 20 + dim)
+    thb = weights_bf16(th, dim)
+    f = make_flow(vgx, dim, th)
+    try:
+        n = 20000
+        rng = np.random.default_rng(dim)
+        yy = rng.uniform(size=(n, dim))
+        yt = torch.tensor(yy.T.copy(), device="cuda")
+        u = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_density(f, yt, lq, u=u)
+        ur, lqr = of.density(thb, yy, dim, L, K, H)
+        du = np.max(np.abs(u.cpu().numpy().T - ur), axis=1)
+        dl = np.abs(lq.cpu().numpy() - lqr)
+        safe = margins(thb, yy, dim, "density") > 1e-3
+        print(f"  median |dlogq| {np.median(dl):.2e}, p90 {np.percentile(dl, 90):.2e}, safe frac {safe.mean():.2f}")
+        assert np.all(dl[safe] <= 2e-2) and np.all(du[safe] <= 2e-3)
+        assert np.mean((dl <= 2e-2) & (du <= 2e-3)) >= 0.9
+        # GPU self-consistency: density(sample(u)) returns u and the same log q
+        y2 = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq2 = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(f, n, 1, 0, 0, y2, lq2)
+        u2 = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq3 = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_density(f, y2, lq3, u=u2)
+        uref = sample_uniforms(1, 1 << 23, 0, np.arange(n, dtype=np.uint64), dim)
+        back = np.max(np.abs(u2.cpu().numpy().T - uref), axis=1)
+        same = np.abs(lq3.cpu().numpy() - lq2.cpu().numpy())
+        assert np.mean((back < 1e-4) & (same < 1e-4)) > 0.99
+    finally:
+        vgx.flow_destroy(f)
+
+
+@pytest.mark.parametrize("dim", [3, 8])
+def test_loss_and_gradient_match_oracle(vgx, dim):
+    import torch
+    print(f"flow gradient parity dim={dim}", flush=True)
+    th = random_theta(dim, 30 + dim, out_scale=0.05)
+    thb = weights_bf16(th, dim)
+    f = make_flow(vgx, dim, th)
+    try:
+        n = 8192 + 5
+        rng = np.random.default_rng(100 + dim)
+        yy = rng.uniform(size=(n, dim))
+        g = gauss(yy, 0.5, 0.25) + 0.05
+        P = vgx.flow_num_params(dim, L, K, H)
+        loss, grad = vgx.flow_loss_grad(f, torch.tensor(yy.T.copy(), device="cuda"), torch.tensor(g, device="cuda"), P)
+        lr, gr, _ = of.loss_and_grad(thb, yy, g, dim, L, K, H)
+        assert loss == pytest.approx(lr, rel=1e-2)
+        cos = float(np.dot(grad, gr) / (np.linalg.norm(grad) * np.linalg.norm(gr)))
+        assert cos > 0.995
+        off = 0
+        for sh in of.layer_shapes(dim, L, K, H):
+            for k, size in enumerate(sh["sizes"]):
+                a, b = grad[off:off + size].astype(np.float64), gr[off:off + size]
+                nb = np.linalg.norm(b)
+                if nb > 1e-3 * np.linalg.norm(gr):
+                    assert np.linalg.norm(a - b) <= 3e-2 * nb, f"segment {k} at {off}"
+                off += size
+    finally:
+        vgx.flow_destroy(f)
+
+
+def test_adam_matches_oracle(vgx):
+    import torch
+    dim = 3
+    th = random_theta(dim, 1)
+    f = make_flow(vgx, dim, th)
+    try:
+        P = th.size
+        rng = np.random.default_rng(0)
+        m = np.zeros(P)
+        v = np.zeros(P)
+        ref = th.astype(np.float64)
+        for t in range(1, 4):
+            gr = rng.normal(0, 1e-2, P).astype(np.float32)
+            vgx.flow_adam(f, torch.tensor(gr, device="cuda"), 1e-3)
+            ref, m, v = of.adam_step(ref, m, v, gr.astype(np.float64), t, 1e-3)
+        got = vgx.flow_get_params(f, P)
+        assert np.allclose(got, ref, rtol=1e-6, atol=1e-7)
+    finally:
+        vgx.flow_destroy(f)
+
+
+def test_flow_weights_are_unbiased(vgx):
+    """E[f/q] over flow samples equals the integral for any weights: the
+    sampler's reported log q is its true density."""
+    import torch
+    dim = 3
+    th = random_theta(dim, 40, out_scale=0.1)
+    f = make_flow(vgx, dim, th)
+    c, s = 0.45, 0.15
+    v = vgx.vegas_create(vgx.GAUSS, dim, 50, 1.5, 0, 0, vgx.F64, np.concatenate([np.full(dim, c), np.full(dim, s)]))
+    try:
+        n = 2_000_000
+        y = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(f, n, 11, 0, 0, y, lq)
+        r = vgx.vegas_iterate_points(v, y, lq)
+        I = gauss_integral(dim, c, s)
+        assert abs(r["mean"] - I) < 4 * math.sqrt(r["var"])
+    finally:
+        vgx.vegas_destroy(v)
+        vgx.flow_destroy(f)
+
+
+def test_training_reduces_variance(vgx):
+    import torch
+    dim = 3
+    print("flow training 60 steps", flush=True)
+    th = he_init_segments(of.init_segments(dim, L, K, H), 2)
+    f = make_flow(vgx, dim, th)
+    c, s = 0.3, 0.1
+    prm = np.concatenate([np.full(dim, c), np.full(dim, s)])
+    v = vgx.vegas_create(vgx.GAUSS, dim, 50, 1.5, 3, 0, vgx.F64, prm)
+    try:
+        n = 16384
+        yb = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        gb = torch.empty(n, dtype=torch.float64, device="cuda")
+        losses = []
+        for step in range(60):
+            vgx.vegas_sample(v, 0, n, step, u=yb, g=gb)   # uniform grid: g = f
+            losses.append(vgx.flow_train_step(f, yb, gb, 5e-3))
+        assert np.mean(losses[-5:]) < 0.5 * np.mean(losses[:3])
+        m = 400_000
+        y = torch.empty((dim, m), dtype=torch.float64, device="cuda")
+        lq = torch.empty(m, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(f, m, 4, 0, 0, y, lq)
+        rf = vgx.vegas_iterate_points(v, y, lq)
+        yu = torch.rand((dim, m), dtype=torch.float64, device="cuda")
+        ru = vgx.vegas_iterate_points(v, yu, None)
+        I = gauss_integral(dim, c, s)
+        assert abs(rf["mean"] - I) < 4 * math.sqrt(rf["var"])
+        assert rf["var"] < 0.3 * ru["var"]
+    finally:
+        vgx.vegas_destroy(v)
+        vgx.flow_destroy(f)
+
+
+def test_bad_arguments(vgx):
+    with pytest.raises(vgx.VgxError):
+        vgx.flow_create(3, np.zeros(10, dtype=np.float32))
+    with pytest.raises(vgx.VgxError):
+        vgx.flow_create(1, np.zeros(10, dtype=np.float32))
+    assert vgx.flow_num_params(13, L, K, H) == -1
