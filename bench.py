@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--events", type=int, default=None, help="events per iteration (default 1e7)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-flow", action="store_true", help="skip the flow comparison")
+    ap.add_argument("--extras", action="store_true",
+                    help="also measure the other workloads (PDF interpolation alone, plain Gaussian VEGAS, "
+                         "batched integrals) as extra fields")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run a plain 2 GiB device copy (reference for scaling HBM counters) and exit")
     return ap.parse_args()
 
 
@@ -93,8 +98,190 @@ def time_to_precision_vegas(vgx, pdf, params, n_iter_events, target=1e-4, max_it
         vgx.vegas_destroy(v)
 
 
+def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch, lr, n_flow, seed, target=1e-4,
+                  max_batches=40):
+    """Flow-proposal pipeline until sigma/mean <= target: VEGAS warm-up
+    iterations (kept in the combination), training of the coupling flow on
+    uniform points of the adapted VEGAS cube with g = f(G(u)) J(u), then
+    batches drawn from the flow (weights f/q) until the target is reached.
+    Wall time includes everything from the first launch."""
+    import torch
+    from synth import he_init_segments
+    prec = vgx.F32 if kind == vgx.TTBAR else vgx.F64
+    v = vgx.vegas_create(kind, dim, 50, 1.5, seed, 0, prec, params, pdf=pdf)
+    init = he_init_segments(vgx.flow_param_layout(dim), seed)
+    f = vgx.flow_create(dim, init)
+    try:
+        u = torch.empty((dim, batch), dtype=torch.float64, device="cuda")
+        g = torch.empty(batch, dtype=torch.float64, device="cuda")
+        y = torch.empty((dim, n_flow), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n_flow, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last_vegas = None
+        for it in range(warm_iters):
+            last_vegas = vgx.vegas_iterate(v, n_iter, it)
+            vgx.vegas_refine(v)
+        t_warm = time.perf_counter()
+        losses = []
+        for s in range(steps):
+            vgx.vegas_sample(v, 0, batch, 10_000 + s, u=u, g=g)
+            sync = (s == 0 or s == steps - 1)
+            l = vgx.flow_train_step(f, u, g, lr, sync=sync)
+            if sync:
+                losses.append(l)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter()
+        k = 0
+        res = vgx.vegas_result(v)
+        last_flow = None
+        while res["sigma"] > target * abs(res["mean"]) and k < max_batches:
+            vgx.flow_sample(f, n_flow, seed, 5, k, y, lq)
+            last_flow = vgx.vegas_iterate_points(v, y, lq)
+            res = vgx.vegas_result(v)
+            k += 1
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        out = dict(seconds=t_end - t0, seconds_excluding_training=(t_end - t0) - (t_train - t_warm),
+                   training_seconds=t_train - t_warm, warmup_iterations=warm_iters, train_steps=steps,
+                   train_batch=batch, flow_batches=k, flow_batch_events=n_flow, mean=res["mean"], sigma=res["sigma"],
+                   reached=bool(res["sigma"] <= target * abs(res["mean"])), loss_first=losses[0],
+                   loss_last=losses[-1])
+        if last_vegas and last_flow:
+            # relative variance per sample of the weights (n var(E) / E^2)
+            out["rel_var_per_sample_vegas"] = last_vegas["var"] * last_vegas["n"] / last_vegas["mean"] ** 2
+            out["rel_var_per_sample_flow"] = last_flow["var"] * last_flow["n"] / last_flow["mean"] ** 2
+        # sampling cost per event of each sampler
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        vgx.flow_sample(f, n_flow, seed, 6, 0, y, lq)
+        vgx.vegas_iterate_points(v, y, lq)
+        e1.record()
+        e1.synchronize()
+        out["flow_ns_per_event"] = e0.elapsed_time(e1) * 1e6 / n_flow
+        return out
+    finally:
+        vgx.flow_destroy(f)
+        vgx.vegas_destroy(v)
+
+
+def copy_reference():
+    """A plain device-to-device copy of a known size; its FETCH_SIZE and
+    WRITE_SIZE readings scale the counters of the measured kernels."""
+    import torch
+    n = 1 << 28  # 2 GiB of FP64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_bytes": n * 8}), flush=True)
+
+
+def cuda_timed(fn, reps=5):
+    """Median milliseconds of fn() between HIP events on the current stream."""
+    import torch
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def extra_pdf(vgx, pdf):
+    """PDF interpolation alone: 1e8 log-uniform queries, FP64 and FP32 outputs."""
+    import torch
+    from synth import C1, pdf_queries
+    n = C1["n_queries"]
+    x, q2 = pdf_queries(n)
+    xt, qt = torch.from_numpy(x).cuda(), torch.from_numpy(q2).cuda()
+    del x, q2
+    out = {}
+    for name, dt, obytes in (("f64", torch.float64, 88), ("f32", torch.float32, 44)):
+        res = torch.empty((11, n), dtype=dt, device="cuda")
+        vgx.pdf_interp(pdf, xt, qt, res)
+        ms = cuda_timed(lambda: vgx.pdf_interp(pdf, xt, qt, res))
+        byt = n * (16 + obytes)
+        out[name] = {"queries_per_s": n / (ms * 1e-3), "ms": ms, "algorithmic_GBps": byt / (ms * 1e-3) / 1e9,
+                     "frac_of_8TBps": byt / (ms * 1e-3) / 8e12, "bytes_per_query": 16 + obytes}
+        del res
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_gauss(vgx):
+    """Plain VEGAS on the d=4 Gaussian: the small configuration (10 x 1e5)
+    and a chip-filling 1e9 samples per iteration."""
+    import numpy as np
+    from synth import C0
+    prm = np.concatenate([np.full(4, C0["centre"]), np.full(4, C0["sigma"])])
+    out = {}
+    v = vgx.vegas_create(vgx.GAUSS, 4, C0["n_bins"], C0["alpha"], C0["seed"], 0, vgx.F64, prm)
+    try:
+        t0 = time.perf_counter()
+        for it in range(C0["iterations"]):
+            vgx.vegas_iterate(v, C0["n_per_iter"], it)
+            vgx.vegas_refine(v)
+        dt = time.perf_counter() - t0
+        r = vgx.vegas_result(v)
+        out["small"] = {"events_per_s": C0["iterations"] * C0["n_per_iter"] / dt, "ms_total": dt * 1e3,
+                        "mean": r["mean"], "sigma": r["sigma"]}
+        n = C0["n_per_iter_large"]
+        vgx.vegas_set_timing(v, True)
+        t0 = time.perf_counter()
+        for it in range(3):
+            vgx.vegas_iterate(v, n, 100 + it)
+            vgx.vegas_refine(v)
+        dt = time.perf_counter() - t0
+        ms, k = vgx.vegas_kernel_time(v)
+        kern = ms / k * 1e-3
+        flops = 65.0 * n / kern
+        out["large"] = {"events_per_s": 3 * n / dt, "kernel_ms": kern * 1e3, "fp64_flops_per_sample": 65,
+                        "achieved_TFLOPs": flops / 1e12, "frac_of_fp64_peak": flops / 78.6e12}
+    finally:
+        vgx.vegas_destroy(v)
+    return out
+
+
+def extra_batch(vgx):
+    """64 integrals, d 2..12, 1e4..1e7 samples, 10 iterations in one graph each."""
+    import torch
+    from synth import C3, batch_specs
+    specs = batch_specs()
+    ctxs = [vgx.vegas_create(s.kind, s.dim, C3["n_bins"], C3["alpha"], C3["seed"], s.stream, vgx.F32, s.params)
+            for s in specs]
+    try:
+        t0 = time.perf_counter()
+        b = vgx.batch_create(ctxs, [s.n for s in specs], 0, 0)
+        t_create = time.perf_counter() - t0
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for it in range(C3["iterations"]):
+                vgx.batch_iterate(b, it, len(specs))
+            dt = time.perf_counter() - t0
+            tile, block = vgx.batch_config(b)
+        finally:
+            vgx.batch_destroy(b)
+        tot = sum(s.n for s in specs) * C3["iterations"]
+        return {"events_per_s": tot / dt, "ms_per_iteration": dt / C3["iterations"] * 1e3,
+                "events_per_iteration": tot // C3["iterations"], "autotuned_tile": tile, "autotuned_block": block,
+                "create_and_autotune_ms": t_create * 1e3}
+    finally:
+        for c in ctxs:
+            vgx.vegas_destroy(c)
+
+
 def main():
     args = parse()
+    if args.copy_reference:
+        copy_reference()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -170,7 +357,17 @@ def main():
         },
     }
     if not args.no_flow:
-        out["time_to_1e-4"] = {"vegas": time_to_precision_vegas(vgx, pdf, params, n)}
+        from synth import C4
+        tv = time_to_precision_vegas(vgx, pdf, params, n)
+        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, n, warm_iters=2, steps=C4["steps"], batch=C4["batch"],
+                           lr=C4["lr"], n_flow=n, seed=1000 + C2["seed"])
+        tv["ns_per_event"] = ms_per_step * 1e6 / n
+        out["time_to_1e-4"] = {"vegas": tv, "flow": tf,
+                               "flow_faster_including_training": tf["seconds"] < tv["seconds"],
+                               "flow_faster_excluding_training": tf["seconds_excluding_training"] < tv["seconds"]}
+    if args.extras:
+        out["extras"] = {"pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
+                         "batched_64": extra_batch(vgx)}
     if not args.no_cpu:
         n_cpu = 300_000
         eps, secs = cpu_baseline(grid, n_cpu)

@@ -240,6 +240,14 @@ typedef struct vgx_flow vgx_flow;
  * Supported: dim 2..VGX_MAX_DIM, n_bins = 32, hidden = 64, n_layers 1..8. */
 int64_t flow_num_params(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden);
 
+/* Parameter segments of a flow, in the flat order (host-only, no device
+ * work): for each segment its kind (0 = hidden weight matrix, 1 = hidden
+ * bias, 2 = output-layer weight or bias, which an identity initialisation
+ * sets to zero), its fan-in and its size.  At most cap segments are
+ * written; *n_seg receives the total (6 per layer). */
+vgx_status flow_param_layout(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden, int32_t* kind_host,
+                             int32_t* fan_in_host, int64_t* size_host, int32_t cap, int32_t* n_seg);
+
 /* Create a flow with the given FP32 initial parameters (sync copy). */
 vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden,
                        const float* params_host, int64_t n_params, void* stream, vgx_flow** out);

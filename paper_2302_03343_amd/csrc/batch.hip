@@ -281,7 +281,11 @@ vgx_status autotune(vgx_batch* b, int fixed_tile, int fixed_block) {
   const int tiles[] = {2048, 4096, 8192, 16384, 32768};
   const int blocks[] = {128, 256};
   int best_t = fixed_tile > 0 ? fixed_tile : 8192, best_b = fixed_block > 0 ? fixed_block : 256;
-  if (fixed_tile > 0 && fixed_block > 0) return VGX_OK;
+  if (fixed_tile > 0 && fixed_block > 0) {
+    layout(b, fixed_tile);
+    b->block = fixed_block;
+    return VGX_OK;
+  }
   hipEvent_t e0, e1;
   VGX_HIP(hipEventCreate(&e0));
   VGX_HIP(hipEventCreate(&e1));

@@ -1049,6 +1049,33 @@ extern "C" int64_t flow_num_params(int32_t dim, int32_t n_layers, int32_t n_bins
   return np;
 }
 
+extern "C" vgx_status flow_param_layout(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden,
+                                       int32_t* kind, int32_t* fan_in, int64_t* size, int32_t cap, int32_t* n_seg) {
+  VGX_CHECK(n_seg, "flow_param_layout: null n_seg");
+  VGX_CHECK(dim >= 2 && dim <= VGX_MAX_DIM && n_layers >= 1 && n_layers <= FL_MAX && n_bins == FK && hidden == FH,
+            "flow_param_layout: unsupported shape");
+  FlowDesc D;
+  std::vector<int> a, b, c;
+  int64_t np = 0;
+  int nbm = 0;
+  VGX_TRY(build_desc(dim, n_layers, D, a, b, c, np, nbm));
+  *n_seg = 6 * n_layers;
+  int k = 0;
+  for (int l = 0; l < n_layers; ++l) {
+    const int na = D.l[l].na, nb = D.l[l].nb;
+    const int32_t kd[6] = {0, 1, 0, 1, 2, 2};
+    const int32_t fi[6] = {na, na, FH, FH, FH, FH};
+    const int64_t sz[6] = {(int64_t)FH * na, FH, (int64_t)FH * FH, FH, (int64_t)nb * FK * FH, (int64_t)nb * FK};
+    for (int q = 0; q < 6; ++q, ++k) {
+      if (k >= cap) continue;
+      if (kind) kind[k] = kd[q];
+      if (fan_in) fan_in[k] = fi[q];
+      if (size) size[k] = sz[q];
+    }
+  }
+  return VGX_OK;
+}
+
 extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden, const float* params,
                                   int64_t n_params, void* stream, vgx_flow** out) {
   VGX_CHECK(out, "flow_create: null out");

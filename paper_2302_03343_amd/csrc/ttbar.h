@@ -23,7 +23,8 @@
 //
 // PDF lookup at the fixed scale mu^2 = m_t^2: the four Q^2 rows j-1..j+2
 // around mu^2 (two rows if the Q stencil is incomplete) are staged in LDS as
-// FP32 [ix][row][flav]; per event and per x the cubic Hermite (secant
+// FP32 [ix][flav][row] (one 16-byte read per node and flavour); per event
+// and per x the cubic Hermite (secant
 // slopes) in ln x and then in ln Q^2 is evaluated for all 11 flavours, as a
 // 4x4 weighted sum w_rk = q_r c_k of the stencil (same linear function as
 // the Hermite-with-slopes formula).  Bilinear where the stencil is
@@ -56,29 +57,32 @@ struct TTbarConst {
   double lmu2;      // ln mu^2
 };
 
-// LDS footprint in floats.
-__host__ __device__ inline int ttbar_lds_floats(int n_x) { return n_x * 4 * TT_NF + 2 * n_x + 8; }
+// LDS footprint in floats: node values [n_x][11][4 rows] (16-byte aligned
+// float4 per node and flavour), ln x knots, inverse spacings, Q weights and
+// the cell-guess constants.
+__host__ __device__ inline int ttbar_lds_floats(int n_x) { return n_x * 4 * TT_NF + 2 * n_x + 16; }
 
 struct TTbar {
   static constexpr bool kStage = true;
   TTbarConst c;
-  float* F;     // LDS [n_x][n_rows][11]
-  float* sa;    // LDS ln x knots [n_x]
-  float* sinv;  // LDS 1/(a_{i+1} - a_i) [n_x]
-  float* qw;    // LDS Q-direction weights [4]
+  const float4* F;  // LDS [n_x][11] float4: the (up to) four Q^2 rows of one node and flavour
+  float* sa;        // LDS ln x knots [n_x]
+  float* sinv;      // LDS 1/(a_{i+1} - a_i) [n_x]
+  float* qw;        // LDS [0..3] Q-row Hermite weights, [4] bilinear t_b, [5] a_0, [6] 1/da, [7] uniform flag
 
   __device__ void stage(float* lds) {
-    F = lds;
-    sa = F + c.n_x * 4 * TT_NF;
+    float* Fs = lds;
+    F = (const float4*)lds;
+    sa = Fs + c.n_x * 4 * TT_NF;
     sinv = sa + c.n_x;
     qw = sinv + c.n_x;
     const int nr = c.n_rows;
-    const int tot = c.n_x * nr * TT_NF;
+    const int tot = c.n_x * TT_NF * 4;
     for (int k = threadIdx.x; k < tot; k += blockDim.x) {
-      const int f = k % TT_NF;
-      const int r = (k / TT_NF) % nr;
-      const int ix = k / (TT_NF * nr);
-      F[k] = c.v32[((size_t)(c.row0 + r) * c.n_x + ix) * TT_NF + f];
+      const int r = k & 3;
+      const int f = (k >> 2) % TT_NF;
+      const int ix = (k >> 2) / TT_NF;
+      Fs[k] = r < nr ? c.v32[((size_t)(c.row0 + r) * c.n_x + ix) * TT_NF + f] : 0.0f;
     }
     for (int k = threadIdx.x; k < c.n_x; k += blockDim.x) {
       sa[k] = (float)c.lx[k];
@@ -104,24 +108,45 @@ struct TTbar {
         qw[2] = 0.0f;
         qw[3] = 0.0f;
       }
+      qw[4] = (float)t;  // linear weight in ln Q^2 for the bilinear fallback
+      // cell guess for knots uniform in ln x (checked here; else binary search)
+      const int n = c.n_x;
+      const double a0 = c.lx[0], da = (c.lx[n - 1] - c.lx[0]) / (n - 1);
+      bool uni = true;
+      for (int k = 0; k < n; ++k)
+        if (fabs(c.lx[k] - (a0 + k * da)) > 1e-3 * da) uni = false;
+      qw[5] = (float)a0;
+      qw[6] = (float)(1.0 / da);
+      qw[7] = uni ? 1.0f : 0.0f;
     }
   }
 
-  // xf of all flavours at ln x = a (a <= 0).
-  __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
+  // cell i with sa[i] <= a < sa[i+1], clamped to [0, n_x - 2]
+  __device__ __forceinline__ int cell(float a) const {
     const int nx = c.n_x;
-    // cell: sa[i] <= a < sa[i+1], clamped to [0, nx-2]
+    if (qw[7] != 0.0f) {
+      // guess from the uniform spacing, then settle on the stored knots
+      // (the same cell as a binary search over sa)
+      int i = (int)((a - qw[5]) * qw[6]);
+      i = i < 0 ? 0 : (i > nx - 2 ? nx - 2 : i);
+      while (i > 0 && a < sa[i]) --i;
+      while (i < nx - 2 && a >= sa[i + 1]) ++i;
+      return i;
+    }
     int lo = 0, hi = nx - 1;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (sa[mid] <= a) lo = mid; else hi = mid;
     }
-    const int i = lo;
+    return lo;
+  }
+
+  // xf of all flavours at ln x = a (a <= 0).
+  __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
+    const int nx = c.n_x;
+    const int i = cell(a);
     const float t = (a - sa[i]) * sinv[i];
-#pragma unroll
-    for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
-    const int nr = c.n_rows;
-    if (nr == 4 && i >= 1 && i <= nx - 3) {
+    if (c.n_rows == 4 && i >= 1 && i <= nx - 3) {
       const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
       const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
       const float t2 = t * t, t3 = t2 * t;
@@ -132,34 +157,35 @@ struct TTbar {
       cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
       cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
       cx[3] = 0.5f * h11 * rp;
+      const float q0 = qw[0], q1 = qw[1], q2 = qw[2], q3 = qw[3];
+#pragma unroll
+      for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float* node = F + (size_t)(i - 1 + k) * 4 * TT_NF;
+        const float w0 = cx[k] * q0, w1 = cx[k] * q1, w2 = cx[k] * q2, w3 = cx[k] * q3;
+        const float4* node = F + (size_t)(i - 1 + k) * TT_NF;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float w = cx[k] * qw[r];
-#pragma unroll
-          for (int f = 0; f < TT_NF; ++f) xf[f] = fmaf(w, node[r * TT_NF + f], xf[f]);
+        for (int f = 0; f < TT_NF; ++f) {
+          const float4 v = node[f];
+          xf[f] = fmaf(w0, v.x, fmaf(w1, v.y, fmaf(w2, v.z, fmaf(w3, v.w, xf[f]))));
         }
       }
     } else {
-      // bilinear on rows (j, j+1): staged rows 1, 2 when 4 rows, 0, 1 when 2
-      const int r0 = nr == 4 ? 1 : 0;
-      float tb = qw[1];
-      if (nr == 4) {
-        // linear weight in ln Q^2 for the bilinear fallback
-        const double* lq = c.lq2 + c.q_off;
-        tb = (float)((c.lmu2 - lq[c.j_local]) / (lq[c.j_local + 1] - lq[c.j_local]));
-      }
+      // bilinear on rows (j, j+1): staged rows 1, 2 of four, or 0, 1 of two
+      const float tb = qw[4];
       const float w00 = (1.f - t) * (1.f - tb), w01 = t * (1.f - tb), w10 = (1.f - t) * tb, w11 = t * tb;
-      const float* n0 = F + (size_t)i * nr * TT_NF;
-      const float* n1 = F + (size_t)(i + 1) * nr * TT_NF;
+      const float4* n0 = F + (size_t)i * TT_NF;
+      const float4* n1 = F + (size_t)(i + 1) * TT_NF;
+      const bool four = c.n_rows == 4;
 #pragma unroll
       for (int f = 0; f < TT_NF; ++f) {
-        float v = w00 * n0[r0 * TT_NF + f];
-        v = fmaf(w01, n1[r0 * TT_NF + f], v);
-        v = fmaf(w10, n0[(r0 + 1) * TT_NF + f], v);
-        v = fmaf(w11, n1[(r0 + 1) * TT_NF + f], v);
+        const float4 a0 = n0[f], a1 = n1[f];
+        const float lo0 = four ? a0.y : a0.x, hi0 = four ? a0.z : a0.y;
+        const float lo1 = four ? a1.y : a1.x, hi1 = four ? a1.z : a1.y;
+        float v = w00 * lo0;
+        v = fmaf(w01, lo1, v);
+        v = fmaf(w10, hi0, v);
+        v = fmaf(w11, hi1, v);
         xf[f] = v;
       }
     }

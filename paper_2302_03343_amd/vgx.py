@@ -103,6 +103,8 @@ _optional("batch_iterate", _S, _vp, _i32, C.POINTER(IterResult))
 _optional("batch_config", _S, _vp, C.POINTER(_i32), C.POINTER(_i32))
 _optional("batch_destroy", None, _vp)
 _optional("flow_num_params", _i64, _i32, _i32, _i32, _i32)
+_optional("flow_param_layout", _S, _i32, _i32, _i32, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i64), _i32,
+          C.POINTER(_i32))
 _optional("flow_create", _S, _i32, _i32, _i32, _i32, C.POINTER(_f32), _i64, _vp, C.POINTER(_vp))
 _optional("flow_sample", _S, _vp, _i64, _u64, _u32, _i32, _vp, _vp, _vp)
 _optional("flow_density", _S, _vp, _i64, _vp, _vp, _vp, _vp)
@@ -339,6 +341,20 @@ def batch_destroy(b):
 # ---------------------------------------------------------------------------
 def flow_num_params(dim, n_layers=4, n_bins=32, hidden=64):
     return int(_c["flow_num_params"](dim, n_layers, n_bins, hidden))
+
+
+def flow_param_layout(dim, n_layers=4, n_bins=32, hidden=64):
+    """[(kind, fan_in, size)] per parameter segment; kind "w", "b" or "z"
+    (output layer), in the flat parameter order."""
+    cap = 6 * n_layers
+    kind = np.zeros(cap, dtype=np.int32)
+    fan = np.zeros(cap, dtype=np.int32)
+    size = np.zeros(cap, dtype=np.int64)
+    n = _i32()
+    _check(_c["flow_param_layout"](dim, n_layers, n_bins, hidden, _hptr(kind, _i32), _hptr(fan, _i32),
+                                   _hptr(size, _i64), cap, C.byref(n)), "flow_param_layout")
+    names = {0: "w", 1: "b", 2: "z"}
+    return [(names[int(kind[k])], int(fan[k]), int(size[k])) for k in range(n.value)]
 
 
 def flow_create(dim, params, n_layers=4, n_bins=32, hidden=64, stream=None):

@@ -48,3 +48,13 @@ def test_binding_has_the_same_names():
             continue
         assert hasattr(vgx, n), n
     assert vgx.version().startswith("vgx")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvgx.so not built")
+@pytest.mark.parametrize("dim", [2, 3, 5, 8, 12])
+def test_flow_layout_matches_oracle_on_host(dim):
+    # host-only entry point: segment list equals the oracle's reading of the masks
+    import paper_2302_03343_amd.vgx as vgx
+    from oracle import flow
+    assert vgx.flow_param_layout(dim) == flow.init_segments(dim, 4, 32, 64)
+    assert vgx.flow_num_params(dim, 4, 32, 64) == flow.n_params(dim, 4, 32, 64)
