@@ -248,6 +248,31 @@ def extra_gauss(vgx):
     return out
 
 
+def extra_ttbar_contracted(vgx, pdf, params, n):
+    """The same t tbar iteration with the Q^2 direction of the PDF stencil
+    contracted once per workgroup at the fixed scale (mode 1)."""
+    import numpy as np
+    from synth import C2
+    p = np.concatenate([params, [1.0]])
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], C2["seed"], 0, vgx.F32, p, pdf=pdf)
+    try:
+        for it in range(3):
+            vgx.vegas_iterate(v, n, it)
+            vgx.vegas_refine(v)
+        vgx.vegas_set_timing(v, True)
+        t0 = time.perf_counter()
+        k = 10
+        for it in range(k):
+            vgx.vegas_iterate(v, n, 3 + it)
+            vgx.vegas_refine(v)
+        dt = time.perf_counter() - t0
+        ms, launches = vgx.vegas_kernel_time(v)
+        r = vgx.vegas_result(v)
+        return {"events_per_s": n * k / dt, "kernel_ms": ms / launches, "mean_pb": r["mean"], "sigma_pb": r["sigma"]}
+    finally:
+        vgx.vegas_destroy(v)
+
+
 def extra_batch(vgx):
     """64 integrals, d 2..12, 1e4..1e7 samples, 10 iterations in one graph each."""
     import torch
@@ -366,7 +391,8 @@ def main():
                                "flow_faster_including_training": tf["seconds"] < tv["seconds"],
                                "flow_faster_excluding_training": tf["seconds_excluding_training"] < tv["seconds"]}
     if args.extras:
-        out["extras"] = {"pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
+        out["extras"] = {"ttbar_fixed_scale_contraction": extra_ttbar_contracted(vgx, pdf, params, n),
+                         "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
                          "batched_64": extra_batch(vgx)}
     if not args.no_cpu:
         n_cpu = 300_000

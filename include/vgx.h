@@ -71,8 +71,14 @@ enum {
   VGX_GENZ_PEAK = 2,  /* prod (c_j^-2 + (x_j - w_j)^2)^-1.
                          params = [w_0..w_{d-1}, c_0..c_{d-1}]               */
   VGX_TTBAR = 3       /* LO pp -> t tbar, d = 3, (tau, y, cos theta*) map.
-                         params = [sqrt_s, m_top, alpha_s, gev2_to_pb];
-                         needs a PDF context, evaluated at mu^2 = m_top^2    */
+                         params = [sqrt_s, m_top, alpha_s, gev2_to_pb(, mode)];
+                         needs a PDF context, evaluated at mu^2 = m_top^2.
+                         mode 0 (default): the full log-bicubic stencil in
+                         (ln x, ln Q^2) per event; mode 1: the Q^2 direction,
+                         identical for every event at the fixed scale, is
+                         contracted once per workgroup and each event does
+                         the ln x direction only (same interpolant, FP32
+                         rounding differs)                                    */
 };
 enum { VGX_F64 = 0, VGX_F32 = 1 };   /* integrand / output precision          */
 

@@ -45,7 +45,8 @@ struct TTbarConst {
   float pref;       // 2 conv / (32 pi s)
   float g4;         // (4 pi alpha_s)^2
   // PDF staging
-  const float* v32; // device [iq][ix][flav] FP32 grid
+  const float* v32; // device [iq][ix][fstride] FP32 grid
+  int fstride;
   const double* lx; // device ln x knots
   const double* lq2;// device ln Q^2 knots (all subgrids)
   int n_x;
@@ -55,6 +56,7 @@ struct TTbarConst {
   int nq_sub;       // knots in that subgrid
   int q_off;        // global knot offset of the subgrid
   double lmu2;      // ln mu^2
+  int contract;     // 1: Q^2 direction contracted once per workgroup
 };
 
 // LDS footprint in floats: node values [n_x][11][4 rows] (16-byte aligned
@@ -82,7 +84,7 @@ struct TTbar {
       const int r = k & 3;
       const int f = (k >> 2) % TT_NF;
       const int ix = (k >> 2) / TT_NF;
-      Fs[k] = r < nr ? c.v32[((size_t)(c.row0 + r) * c.n_x + ix) * TT_NF + f] : 0.0f;
+      Fs[k] = r < nr ? c.v32[((size_t)(c.row0 + r) * c.n_x + ix) * c.fstride + f] : 0.0f;
     }
     for (int k = threadIdx.x; k < c.n_x; k += blockDim.x) {
       sa[k] = (float)c.lx[k];
@@ -119,6 +121,35 @@ struct TTbar {
       qw[6] = (float)(1.0 / da);
       qw[7] = uni ? 1.0f : 0.0f;
     }
+    if (c.contract) {
+      // fixed scale: contract the Q^2 direction once.  P[ix][f] with the
+      // Hermite Q weights (cells with the full stencil) and Pl[ix][f] with the
+      // linear weights (bilinear cells), each node 12 floats (3 x float4).
+      // The node values occupy F; the tables are built in registers first.
+      __syncthreads();
+      float pv[2][(TT_MAX_NX * 12 + 255) / 256];
+      const int tot12 = c.n_x * 12;
+      int q = 0;
+      for (int k = threadIdx.x; k < tot12; k += blockDim.x, ++q) {
+        const int f = k % 12, ix = k / 12;
+        float hp = 0.f, lp = 0.f;
+        if (f < TT_NF) {
+          const float4 v = F[(size_t)ix * TT_NF + f];
+          hp = fmaf(qw[0], v.x, fmaf(qw[1], v.y, fmaf(qw[2], v.z, qw[3] * v.w)));
+          const float tb = qw[4];
+          lp = c.n_rows == 4 ? fmaf(tb, v.z - v.y, v.y) : fmaf(tb, v.y - v.x, v.x);
+        }
+        pv[0][q] = hp;
+        pv[1][q] = lp;
+      }
+      __syncthreads();
+      float* P = lds;
+      q = 0;
+      for (int k = threadIdx.x; k < tot12; k += blockDim.x, ++q) {
+        P[k] = pv[0][q];
+        P[tot12 + k] = pv[1][q];
+      }
+    }
   }
 
   // cell i with sa[i] <= a < sa[i+1], clamped to [0, n_x - 2]
@@ -141,11 +172,62 @@ struct TTbar {
     return lo;
   }
 
+  // xf of all flavours at ln x = a, fixed-scale contracted tables.
+  __device__ __forceinline__ void pdf_at_contracted(int i, float t, float (&xf)[TT_NF]) const {
+    const int nx = c.n_x;
+    const float4* P = F;                    // [ix][3] float4: Hermite-in-Q contraction
+    const float4* Pl = F + (size_t)nx * 3;  // [ix][3] float4: linear-in-Q contraction
+    float v[12];
+    if (c.n_rows == 4 && i >= 1 && i <= nx - 3) {
+      const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
+      const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
+      const float t2 = t * t, t3 = t2 * t;
+      const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
+      const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
+      float cx[4];
+      cx[0] = -0.5f * h10 * rm;
+      cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
+      cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
+      cx[3] = 0.5f * h11 * rp;
+#pragma unroll
+      for (int f = 0; f < 12; ++f) v[f] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4* node = P + (size_t)(i - 1 + k) * 3;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const float4 u = node[m];
+          v[4 * m] = fmaf(cx[k], u.x, v[4 * m]);
+          v[4 * m + 1] = fmaf(cx[k], u.y, v[4 * m + 1]);
+          v[4 * m + 2] = fmaf(cx[k], u.z, v[4 * m + 2]);
+          v[4 * m + 3] = fmaf(cx[k], u.w, v[4 * m + 3]);
+        }
+      }
+    } else {
+      const float4* n0 = Pl + (size_t)i * 3;
+      const float4* n1 = Pl + (size_t)(i + 1) * 3;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const float4 a0 = n0[m], a1 = n1[m];
+        v[4 * m] = fmaf(t, a1.x - a0.x, a0.x);
+        v[4 * m + 1] = fmaf(t, a1.y - a0.y, a0.y);
+        v[4 * m + 2] = fmaf(t, a1.z - a0.z, a0.z);
+        v[4 * m + 3] = fmaf(t, a1.w - a0.w, a0.w);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < TT_NF; ++f) xf[f] = v[f];
+  }
+
   // xf of all flavours at ln x = a (a <= 0).
   __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
     const int nx = c.n_x;
     const int i = cell(a);
     const float t = (a - sa[i]) * sinv[i];
+    if (c.contract) {
+      pdf_at_contracted(i, t, xf);
+      return;
+    }
     if (c.n_rows == 4 && i >= 1 && i <= nx - 3) {
       const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
       const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];

@@ -69,6 +69,13 @@ struct PointsSrc {
   }
 };
 
+// Offset (in doubles, even: 16-byte aligned) of the integrand tables after
+// the edges [D][nb+1] and, with histograms, [D][nb].
+__host__ __device__ inline int lds_table_offset(int D, int nb, bool hist) {
+  const int n = D * (nb + 1) + (hist ? D * nb : 0);
+  return (n + 1) & ~1;
+}
+
 // ---------------------------------------------------------------------------
 // Fused iteration kernel.
 // LDS: edges [D][nb+1] | histogram [D][nb] (HIST) | integrand staging.
@@ -76,11 +83,12 @@ struct PointsSrc {
 // ---------------------------------------------------------------------------
 template <int D, class F, class Src, bool HIST>
 __global__ __launch_bounds__(BLOCK) void k_vegas_iter(VegasArgs a, F f, Src src, double* __restrict__ partials) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   const int nb = a.nb;
   double* se = lds;
   double* sh = se + D * (nb + 1);
-  float* extra = (float*)(sh + (HIST ? D * nb : 0));
+  // integrand tables start on a 16-byte boundary (they are read as float4)
+  float* extra = (float*)(lds + lds_table_offset(D, nb, HIST));
   for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
   if (HIST)
     for (int k = threadIdx.x; k < D * nb; k += BLOCK) sh[k] = 0.0;
@@ -173,10 +181,10 @@ __global__ __launch_bounds__(64) void k_refine(double* __restrict__ edges, const
 template <int D, class F>
 __global__ __launch_bounds__(BLOCK) void k_vegas_sample(VegasArgs a, F f, PhiloxSrc<D> src, double* __restrict__ u_out,
                                                         double* __restrict__ g_out) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   const int nb = a.nb;
   double* se = lds;
-  float* extra = (float*)(se + D * (nb + 1));
+  float* extra = (float*)(lds + lds_table_offset(D, nb, false));
   for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
   F ff = f;
   if constexpr (F::kStage) ff.stage(extra);
@@ -271,6 +279,7 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
       t.pref = (float)(2.0 * conv / (32.0 * M_PI * s));
       t.g4 = (float)((4.0 * M_PI * as) * (4.0 * M_PI * as));
       t.v32 = pdf->v32;
+      t.fstride = pdf->fstride;
       t.lx = pdf->lx;
       t.lq2 = pdf->lq2;
       t.n_x = pdf->n_x;
@@ -280,6 +289,9 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
       t.lmu2 = log(mu2);
       if (j >= 1 && j <= nq - 3) { t.n_rows = 4; t.row0 = pdf->q_off[sub] + j - 1; }
       else { t.n_rows = 2; t.row0 = pdf->q_off[sub] + j; }
+      const double mode = c->n_params >= 5 ? c->params[4] : 0.0;
+      VGX_CHECK(mode == 0.0 || mode == 1.0, "TTBAR mode must be 0 (full stencil) or 1 (fixed-scale contraction)");
+      t.contract = mode == 1.0 ? 1 : 0;
       return VGX_OK;
     }
     default:
@@ -293,7 +305,7 @@ template <int D, class F, class Src, bool HIST>
 vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
   VegasArgs a{n, v->edges, v->nb, v->pstride};
   const int grid = grid_for(v, n);
-  const size_t lds = sizeof(double) * ((size_t)D * (v->nb + 1) + (HIST ? (size_t)D * v->nb : 0)) + extra_lds_bytes(v);
+  const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST) + extra_lds_bytes(v);
   hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
                      v->partials);
   VGX_HIP(hipGetLastError());
@@ -338,7 +350,7 @@ vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, c
   VegasArgs a{n, v->edges, v->nb, v->pstride};
   PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
   const int grid = grid_for(v, n);
-  const size_t lds = sizeof(double) * (size_t)D * (v->nb + 1) + extra_lds_bytes(v);
+  const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false) + extra_lds_bytes(v);
   hipLaunchKernelGGL((k_vegas_sample<D, F>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src, u, g);
   VGX_HIP(hipGetLastError());
   return VGX_OK;

@@ -303,3 +303,26 @@ def test_bad_arguments(vgx):
     with pytest.raises(vgx.VgxError):
         vgx.flow_create(1, np.zeros(10, dtype=np.float32))
     assert vgx.flow_num_params(13, L, K, H) == -1
+
+
+def test_full_batch_gradient_matches_oracle(vgx):
+    """The training launch at its full size (1e5 samples, d = 8)."""
+    import torch
+    dim = 8
+    print("flow gradient parity full batch 1e5 d=8", flush=True)
+    th = random_theta(dim, 77, out_scale=0.05)
+    thb = weights_bf16(th, dim)
+    f = make_flow(vgx, dim, th)
+    try:
+        n = 100_000
+        rng = np.random.default_rng(5)
+        yy = rng.uniform(size=(n, dim))
+        g = gauss(yy, 0.5, 0.3) + 0.05
+        P = vgx.flow_num_params(dim, L, K, H)
+        loss, grad = vgx.flow_loss_grad(f, torch.tensor(yy.T.copy(), device="cuda"), torch.tensor(g, device="cuda"), P)
+        lr, gr, _ = of.loss_and_grad(thb, yy, g, dim, L, K, H)
+        assert loss == pytest.approx(lr, rel=1e-2)
+        cos = float(np.dot(grad, gr) / (np.linalg.norm(grad) * np.linalg.norm(gr)))
+        assert cos > 0.995
+    finally:
+        vgx.flow_destroy(f)

@@ -25,8 +25,9 @@ pytestmark = pytest.mark.gpu
 PARAMS = np.array([C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]])
 
 
-def make(vgx, pdf_ctx, seed=C2["seed"]):
-    return vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], seed, 0, vgx.F32, PARAMS, pdf=pdf_ctx)
+def make(vgx, pdf_ctx, seed=C2["seed"], mode=0):
+    params = np.concatenate([PARAMS, [float(mode)]])
+    return vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], seed, 0, vgx.F32, params, pdf=pdf_ctx)
 
 
 def near_knot(grid, u):
@@ -45,11 +46,14 @@ def oracle_g(grid, u, e):
     return ttbar.integrand(x, grid, C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]) * jac, x
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("grid_kind", ["uniform", "adapted"])
-def test_per_event_integrand(vgx, pdf_ctx, c1_grid, grid_kind):
+def test_per_event_integrand(vgx, pdf_ctx, c1_grid, grid_kind, mode):
+    """mode 0: full (ln x, ln Q^2) stencil per event; mode 1: the Q^2
+    direction contracted once at the fixed scale (same interpolant)."""
     import torch
-    print(f"ttbar per-event, {grid_kind} grid", flush=True)
-    v = make(vgx, pdf_ctx)
+    print(f"ttbar per-event, {grid_kind} grid, mode {mode}", flush=True)
+    v = make(vgx, pdf_ctx, mode=mode)
     try:
         if grid_kind == "adapted":
             for it in range(3):
@@ -121,3 +125,36 @@ def test_full_run_against_quadrature(vgx, pdf_ctx, c1_grid):
             total += w1 * w2 * jt * ly * _lumi_sigma(c1_grid, tau, (u2 - 0.5) * ly)
     assert abs(res["mean"] - total) < 4 * res["sigma"] + 2e-5 * total
     assert res["sigma"] / res["mean"] < 2e-3
+
+
+def test_full_size_iteration_matches_oracle(vgx, pdf_ctx, c1_grid):
+    """The benchmark launch (1e7 events, same kernel and launch shape) against
+    the oracle over all 1e7 events (computed in chunks): the sums to the
+    per-event bar, the histogram to 2e-5."""
+    print("ttbar full-size 1e7 vs oracle", flush=True)
+    n = C2["n_per_iter"]
+    v = make(vgx, pdf_ctx)
+    try:
+        for it in range(2):          # an adapted grid for the measured iteration
+            vgx.vegas_iterate(v, 1_000_000, it)
+            vgx.vegas_refine(v)
+        e = vgx.vegas_get_grid(v, 3, C2["n_bins"])
+        r = vgx.vegas_iterate(v, n, 5)
+        h = vgx.vegas_get_hist(v, 3, C2["n_bins"])
+    finally:
+        vgx.vegas_destroy(v)
+    parts1, parts2 = [], []
+    hist = np.zeros((3, C2["n_bins"]))
+    chunk = 1_000_000
+    for first in range(0, n, chunk):
+        idx = np.arange(first, min(first + chunk, n), dtype=np.uint64)
+        u = sample_uniforms(C2["seed"], 0, 5, idx, 3)
+        w, _ = oracle_g(c1_grid, u, e)
+        parts1.append(math.fsum(w))
+        parts2.append(math.fsum(w * w))
+        _, _, bins = ov.vegas_map(u, e)
+        for j in range(3):
+            hist[j] += np.bincount(bins[:, j], weights=w * w, minlength=C2["n_bins"])
+    assert r["s1"] == pytest.approx(math.fsum(parts1), rel=1e-5)
+    assert r["s2"] == pytest.approx(math.fsum(parts2), rel=2e-5)
+    assert np.allclose(h, hist, rtol=2e-5, atol=1e-6 * hist.sum() / 3)
