@@ -702,10 +702,34 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restric
 // ---------------------------------------------------------------------------
 // Gradient reduction (fixed order over workgroup partials) + Adam.
 // ---------------------------------------------------------------------------
+constexpr int GSPLIT = 8;  // row groups of the first reduction stage
+
+// First stage: row group blockIdx.y sums the workgroup partial rows
+// r = y, y + GSPLIT, ... of every parameter (compensated, fixed order).
+__global__ __launch_bounds__(256) void k_flow_gsum(const FlowDesc* __restrict__ Dp, int64_t n_par, int rows,
+                                                  const float* __restrict__ gpart, float* __restrict__ gtmp) {
+  const FlowDesc& D = *Dp;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_par) return;
+  int l = 0;
+  while (l + 1 < D.L && p >= D.l[l + 1].p_off) ++l;
+  const int q = (int)(p - D.l[l].p_off);
+  const int np = D.l[l].n_par;
+  const float* base = gpart + (size_t)D.l[l].p_off * rows;
+  float acc = 0.0f, c = 0.0f;
+  for (int r = blockIdx.y; r < rows; r += GSPLIT) {
+    const float y = base[(size_t)r * np + q] - c;
+    const float t = acc + y;
+    c = (t - acc) - y;
+    acc = t;
+  }
+  gtmp[(size_t)blockIdx.y * n_par + p] = acc;
+}
+
 struct AdamArgs {
   int64_t n_par;
   int rows;              // workgroup partial rows per layer
-  const float* gpart;    // per layer: [rows][n_par_l] at offset p_off * rows
+  const float* gpart;    // first-stage sums [GSPLIT][n_par]
   const float* grad_in;  // alternative: a full gradient (flow_adam)
   float* grad_out;       // reduced gradient (nullable)
   float* master;
@@ -725,19 +749,8 @@ __global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ 
   if (a.grad_in) {
     g = a.grad_in[p];
   } else {
-    int l = 0;
-    while (l + 1 < D.L && p >= D.l[l + 1].p_off) ++l;
-    const int q = (int)(p - D.l[l].p_off);
-    const int np = D.l[l].n_par;
-    const float* base = a.gpart + (size_t)D.l[l].p_off * a.rows;
-    float acc = 0.0f, c = 0.0f;
-    for (int r = 0; r < a.rows; ++r) {  // compensated, fixed order
-      const float y = base[(size_t)r * np + q] - c;
-      const float t = acc + y;
-      c = (t - acc) - y;
-      acc = t;
-    }
-    g = acc;
+    g = 0.0f;
+    for (int r = 0; r < GSPLIT; ++r) g += a.gpart[(size_t)r * a.n_par + p];  // fixed order
   }
   if (a.grad_out) a.grad_out[p] = g;
   if (!a.do_adam) return;
@@ -804,6 +817,7 @@ struct vgx_flow {
   float* dz[2] = {nullptr, nullptr};  // [d][n]
   unsigned short* scr = nullptr;
   float* gpart = nullptr;       // [n_par * grid_w]
+  float* gtmp = nullptr;        // [GSPLIT][n_par]
   int grid_w = 0;
   int srows = 0;
   double* pinned = nullptr;
@@ -926,6 +940,41 @@ vgx_status pack(vgx_flow* f) {
   return VGX_OK;
 }
 
+// Allow the dynamic LDS the kernels of this flow need (beyond 64 KB), once.
+template <int NB>
+vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr) {
+  // never lower a limit another live flow may rely on
+  static size_t cur_f = 0, cur_b = 0, cur_w = 0;
+  fwd = fwd > cur_f ? fwd : cur_f;
+  bwd = bwd > cur_b ? bwd : cur_b;
+  wgr = wgr > cur_w ? wgr : cur_w;
+  cur_f = fwd;
+  cur_b = bwd;
+  cur_w = wgr;
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwd<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_wgrad<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wgr));
+  return VGX_OK;
+}
+
+vgx_status init_lds_limits(const vgx_flow* f) {
+  size_t fwd = (size_t)f->D.fw_total * 2 + (size_t)f->D.bias_total * 4, bwd = 0, wgr = 0;
+  for (int l = 0; l < f->L; ++l) {
+    const FlowLayerDesc& Ld = f->D.l[l];
+    const size_t b = (size_t)Ld.fw_len * 2 + (size_t)Ld.bw_len * 2 + (size_t)Ld.bias_len * 4;
+    bwd = b > bwd ? b : bwd;
+    wgr = (size_t)Ld.n_par * 4 > wgr ? (size_t)Ld.n_par * 4 : wgr;
+  }
+  switch (f->nbm) {
+    case 1: return set_lds_limits<1>(fwd, bwd, wgr);
+    case 2: return set_lds_limits<2>(fwd, bwd, wgr);
+    case 4: return set_lds_limits<4>(fwd, bwd, wgr);
+    default: return set_lds_limits<8>(fwd, bwd, wgr);
+  }
+}
+
 int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
   const int64_t tiles = (n + 31) / 32;
   const int64_t waves_per_wg = FBLOCK / 64;
@@ -940,8 +989,6 @@ vgx_status launch_fwd(vgx_flow* f, int grid, const FwdArgs& a, hipStream_t st) {
   const size_t lds = fwd_lds(f);
 #define L_(NB)                                                                                        \
   case NB:                                                                                            \
-    hipFuncSetAttribute((const void*)k_flow_fwd<NB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                        (int)lds);                                                                    \
     hipLaunchKernelGGL((k_flow_fwd<NB, MODE>), dim3(grid), dim3(FBLOCK), lds, st, f->d_desc, a, f->fw, f->bias); \
     break;
   switch (f->nbm) { L_(1) L_(2) L_(4) L_(8) default: set_error("flow: bad |B| bound"); return VGX_EINVAL; }
@@ -959,7 +1006,7 @@ vgx_status ensure_train(vgx_flow* f, int64_t n) {
   f->cap_n = 0;
   const int64_t tiles = (n + 31) / 32;
   f->srows = 32 + 4 * FH + FK * f->nbm;
-  f->grid_w = device_cus() / 4 > 0 ? device_cus() / 4 : 1;
+  f->grid_w = device_cus();
   VGX_TRY(dev_alloc((void**)&f->zsave, sizeof(float) * (size_t)f->L * f->dim * n));
   VGX_TRY(dev_alloc((void**)&f->rsave, sizeof(double) * (size_t)n));
   VGX_TRY(dev_alloc((void**)&f->lqsave, sizeof(double) * (size_t)n));
@@ -967,6 +1014,7 @@ vgx_status ensure_train(vgx_flow* f, int64_t n) {
   VGX_TRY(dev_alloc((void**)&f->dz[1], sizeof(float) * (size_t)f->dim * n));
   VGX_TRY(dev_alloc((void**)&f->scr, sizeof(unsigned short) * (size_t)tiles * f->srows * 32));
   VGX_TRY(dev_alloc((void**)&f->gpart, sizeof(float) * (size_t)f->n_par * f->grid_w));
+  if (!f->gtmp) VGX_TRY(dev_alloc((void**)&f->gtmp, sizeof(float) * (size_t)f->n_par * GSPLIT));
   // rows 16..31 of the zA block are never written and must read as zero
   VGX_HIP(hipMemsetAsync(f->scr, 0, sizeof(unsigned short) * (size_t)tiles * f->srows * 32, f->stream));
   f->cap_n = n;
@@ -1008,7 +1056,6 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     const size_t lds = (size_t)Ld.fw_len * 2 + (size_t)Ld.bw_len * 2 + (size_t)Ld.bias_len * 4;
 #define B_(NB)                                                                                        \
   case NB:                                                                                            \
-    hipFuncSetAttribute((const void*)k_flow_bwd<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     hipLaunchKernelGGL((k_flow_bwd<NB>), dim3(grid), dim3(FBLOCK), lds, f->stream, f->d_desc, b, f->fw, f->bw, f->bias); \
     break;
     switch (f->nbm) { B_(1) B_(2) B_(4) B_(8) default: return VGX_EINVAL; }
@@ -1023,7 +1070,6 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     const size_t wl = (size_t)Ld.n_par * 4;
 #define W_(NB)                                                                                        \
   case NB:                                                                                            \
-    hipFuncSetAttribute((const void*)k_flow_wgrad<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wl); \
     hipLaunchKernelGGL((k_flow_wgrad<NB>), dim3(wgrid), dim3(FBLOCK), wl, f->stream, f->d_desc, w); \
     break;
     switch (f->nbm) { W_(1) W_(2) W_(4) W_(8) default: return VGX_EINVAL; }
@@ -1035,10 +1081,15 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
 }
 
 vgx_status reduce_adam(vgx_flow* f, const float* grad_in, float* grad_out, float lr, bool adam, const double* loss) {
+  if (!grad_in) {
+    hipLaunchKernelGGL(k_flow_gsum, dim3((unsigned)((f->n_par + 255) / 256), GSPLIT), dim3(256), 0, f->stream,
+                       f->d_desc, f->n_par, f->grid_w, f->gpart, f->gtmp);
+    VGX_HIP(hipGetLastError());
+  }
   AdamArgs a{};
   a.n_par = f->n_par;
   a.rows = f->grid_w;
-  a.gpart = f->gpart;
+  a.gpart = f->gtmp;
   a.grad_in = grad_in;
   a.grad_out = grad_out;
   a.master = f->master;
@@ -1150,7 +1201,8 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
   if (e == hipSuccess) e = hipMemcpyAsync(f->d_desc, &f->D, sizeof(FlowDesc), hipMemcpyHostToDevice, f->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);  // host vectors die at return
   if (e != hipSuccess) { s = hip_fail(e, "flow_create copies", __FILE__, __LINE__); flow_destroy(f); return s; }
-  s = pack(f);
+  s = init_lds_limits(f);
+  if (s == VGX_OK) s = pack(f);
   if (s == VGX_OK) {
     e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) s = hip_fail(e, "flow_create pack", __FILE__, __LINE__);
@@ -1253,6 +1305,7 @@ extern "C" void flow_destroy(vgx_flow* f) {
   hipFree(f->fw_src); hipFree(f->bw_src); hipFree(f->b_src);
   hipFree(f->loss); hipFree(f->partials); hipFree(f->d_desc);
   hipFree(f->zsave); hipFree(f->rsave); hipFree(f->lqsave); hipFree(f->dz[0]); hipFree(f->dz[1]); hipFree(f->scr); hipFree(f->gpart);
+  hipFree(f->gtmp);
   if (f->pinned) hipHostFree(f->pinned);
   delete f;
 }

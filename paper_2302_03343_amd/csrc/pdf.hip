@@ -21,46 +21,11 @@
 namespace vgx {
 
 struct PdfKernelArgs {
-  int n_x, n_sub, n_flav, fstride;
+  int n_x, n_sub, n_flav;
   int nq[VGX_MAX_SUB];
   int q_off[VGX_MAX_SUB + 1];
   double q2_lo[VGX_MAX_SUB], q2_hi[VGX_MAX_SUB];
-  int x_uni;
-  double x_a0, x_inv;
-  int q_uni[VGX_MAX_SUB];
-  double q_b0[VGX_MAX_SUB], q_inv[VGX_MAX_SUB];
 };
-
-// Cell from a guess on a grid uniform in the log coordinate, settled on the
-// stored knots: the same cell as find_cell.
-__device__ __forceinline__ int settle_cell(const double* a, int n, double key, int guess) {
-  int i = guess < 0 ? 0 : (guess > n - 2 ? n - 2 : guess);
-  while (i > 0 && key < a[i]) --i;
-  while (i < n - 2 && a[i + 1] <= key) ++i;
-  return i;
-}
-
-// Load the FS node values of one (iq, ix) node (16-byte aligned) as doubles.
-template <int FS>
-__device__ __forceinline__ void load_node(const double* p, double (&v)[FS]) {
-#pragma unroll
-  for (int k = 0; k < FS / 2; ++k) {
-    const double2 t = ((const double2*)p)[k];
-    v[2 * k] = t.x;
-    v[2 * k + 1] = t.y;
-  }
-}
-template <int FS>
-__device__ __forceinline__ void load_node(const float* p, double (&v)[FS]) {
-#pragma unroll
-  for (int k = 0; k < FS / 4; ++k) {
-    const float4 t = ((const float4*)p)[k];
-    v[4 * k] = t.x;
-    v[4 * k + 1] = t.y;
-    v[4 * k + 2] = t.z;
-    v[4 * k + 3] = t.w;
-  }
-}
 
 // Weights (cm, c0, c1, c2) of the nodes k-1, k, k+1, k+2 such that
 // sum c * F equals the cubic Hermite between k and k+1 at fraction t with
@@ -112,8 +77,6 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
   __syncthreads();
 
   const int nf = NF > 0 ? NF : g.n_flav;
-  constexpr int FS = NF > 0 ? ((NF + 3) / 4) * 4 : 4;
-  const int fs = NF > 0 ? FS : g.fstride;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
     const double x = qx[q];
@@ -130,11 +93,10 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
     }
     const int nq = g.nq[s];
     const double* lq = slq2 + g.q_off[s];
+    const int i = find_cell(sx, g.n_x, x);
+    const int j = find_cell(sq2 + g.q_off[s], nq, q2);
     const double a = log(x), b = log(q2);
-    const int i = g.x_uni ? settle_cell(sx, g.n_x, x, (int)((a - g.x_a0) * g.x_inv)) : find_cell(sx, g.n_x, x);
-    const int j = g.q_uni[s] ? settle_cell(sq2 + g.q_off[s], nq, q2, (int)((b - g.q_b0[s]) * g.q_inv[s]))
-                             : find_cell(sq2 + g.q_off[s], nq, q2);
-    const ValT* V = vals + (int64_t)g.q_off[s] * g.n_x * fs;  // [iq][ix][f] of subgrid s
+    const ValT* V = vals + (int64_t)g.q_off[s] * g.n_x * nf;  // [iq][ix][f] of subgrid s
     double acc[NFM];
 #pragma unroll
     for (int f = 0; f < NFM; ++f) acc[f] = 0.0;
@@ -146,21 +108,14 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
       hermite_weights((b - lq[j]) / hb, hb / (lq[j] - lq[j - 1]), hb / (lq[j + 2] - lq[j + 1]), cq);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const ValT* row = V + ((int64_t)(j - 1 + r) * g.n_x + (i - 1)) * fs;
+        const ValT* row = V + ((int64_t)(j - 1 + r) * g.n_x + (i - 1)) * nf;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double w = cq[r] * cx[k];
-          const ValT* node = row + k * fs;
-          if constexpr (NF > 0) {
-            double v[FS];
-            load_node<FS>(node, v);
+          const ValT* node = row + k * nf;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) acc[f] = fma(w, v[f], acc[f]);
-          } else {
-#pragma unroll
-            for (int f = 0; f < NFM; ++f)
-              if (f < nf) acc[f] = fma(w, (double)node[f], acc[f]);
-          }
+          for (int f = 0; f < NFM; ++f)
+            if (f < nf) acc[f] = fma(w, (double)node[f], acc[f]);
         }
       }
     } else {
@@ -169,10 +124,10 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
       const double w[4] = {(1.0 - ta) * (1.0 - tb), ta * (1.0 - tb), (1.0 - ta) * tb, ta * tb};
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        const ValT* row = V + ((int64_t)(j + r) * g.n_x + i) * fs;
+        const ValT* row = V + ((int64_t)(j + r) * g.n_x + i) * nf;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          const ValT* node = row + k * fs;
+          const ValT* node = row + k * nf;
 #pragma unroll
           for (int f = 0; f < NFM; ++f)
             if (f < nf) acc[f] = fma(w[2 * r + k], (double)node[f], acc[f]);
@@ -204,7 +159,7 @@ extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** 
   p->n_x = d->n_x;
   p->n_sub = d->n_sub;
   p->n_flav = d->n_flav;
-  p->fstride = ((d->n_flav + 3) / 4) * 4;
+  p->fstride = d->n_flav;  // nodes stored densely (padding to 16 bytes measured slower)
   int tot = 0;
   for (int s = 0; s < d->n_sub; ++s) {
     if (d->nq_per_sub[s] < 2) { delete p; set_error("pdf_create: subgrid %d has < 2 knots", s); return VGX_EINVAL; }
@@ -228,13 +183,13 @@ extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** 
   }
   hipStream_t st = (hipStream_t)stream;
   hipGetDevice(&p->device);
-  const size_t nvals = (size_t)tot * p->n_x * p->fstride;
+  const size_t nvals = (size_t)tot * p->n_x * p->n_flav;
   p->h_x = (double*)malloc(sizeof(double) * p->n_x);
   p->h_q2 = (double*)malloc(sizeof(double) * tot);
   double* lx = (double*)malloc(sizeof(double) * p->n_x);
   double* lq = (double*)malloc(sizeof(double) * tot);
-  double* v = (double*)calloc(nvals, sizeof(double));
-  float* v32 = (float*)calloc(nvals, sizeof(float));
+  double* v = (double*)malloc(sizeof(double) * nvals);
+  float* v32 = (float*)malloc(sizeof(float) * nvals);
   if (!p->h_x || !p->h_q2 || !lx || !lq || !v || !v32) {
     free(lx); free(lq); free(v); free(v32); pdf_destroy(p);
     set_error("pdf_create: host allocation failed");
@@ -242,33 +197,13 @@ extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** 
   }
   for (int k = 0; k < p->n_x; ++k) { p->h_x[k] = d->x_knots[k]; lx[k] = log(d->x_knots[k]); }
   for (int k = 0; k < tot; ++k) { p->h_q2[k] = d->q2_knots[k]; lq[k] = log(d->q2_knots[k]); }
-  // knots uniform in the log coordinate get an O(1) cell guess (settled on the
-  // stored knots, so the cell is the same as a binary search's)
-  {
-    const double a0 = lx[0], da = (lx[p->n_x - 1] - lx[0]) / (p->n_x - 1);
-    bool uni = true;
-    for (int k = 0; k < p->n_x; ++k) uni = uni && fabs(lx[k] - (a0 + k * da)) <= 1e-6 * da;
-    p->x_uni = uni;
-    p->x_a0 = a0;
-    p->x_inv = 1.0 / da;
-    for (int s = 0; s < p->n_sub; ++s) {
-      const double* l = lq + p->q_off[s];
-      const int m = p->nq[s];
-      const double b0 = l[0], db = (l[m - 1] - l[0]) / (m - 1);
-      bool u2 = true;
-      for (int k = 0; k < m; ++k) u2 = u2 && fabs(l[k] - (b0 + k * db)) <= 1e-6 * db;
-      p->q_uni[s] = u2;
-      p->q_b0[s] = b0;
-      p->q_inv[s] = 1.0 / db;
-    }
-  }
   // re-layout [sub][flav][iq][ix] -> [iq_total][ix][flav]
   size_t src = 0;
   for (int s = 0; s < p->n_sub; ++s)
     for (int f = 0; f < p->n_flav; ++f)
       for (int iq = 0; iq < p->nq[s]; ++iq)
         for (int ix = 0; ix < p->n_x; ++ix, ++src) {
-          const size_t dst = ((size_t)(p->q_off[s] + iq) * p->n_x + ix) * p->fstride + f;
+          const size_t dst = ((size_t)(p->q_off[s] + iq) * p->n_x + ix) * p->n_flav + f;
           v[dst] = d->xf[src];
           v32[dst] = (float)d->xf[src];
         }
@@ -306,16 +241,12 @@ extern "C" vgx_status pdf_interp(const vgx_pdf* p, int64_t n, const double* x_de
   if (n == 0) return VGX_OK;
   VGX_CHECK(x_dev && q2_dev && out_dev, "pdf_interp: null device pointer");
   PdfKernelArgs g{};
-  g.n_x = p->n_x; g.n_sub = p->n_sub; g.n_flav = p->n_flav; g.fstride = p->fstride;
-  g.x_uni = p->x_uni; g.x_a0 = p->x_a0; g.x_inv = p->x_inv;
+  g.n_x = p->n_x; g.n_sub = p->n_sub; g.n_flav = p->n_flav;
   for (int s = 0; s < p->n_sub; ++s) {
     g.nq[s] = p->nq[s];
     g.q_off[s] = p->q_off[s];
     g.q2_lo[s] = p->h_q2[p->q_off[s]];
     g.q2_hi[s] = p->h_q2[p->q_off[s] + p->nq[s] - 1];
-    g.q_uni[s] = p->q_uni[s];
-    g.q_b0[s] = p->q_b0[s];
-    g.q_inv[s] = p->q_inv[s];
   }
   g.q_off[p->n_sub] = p->q_off[p->n_sub];
   const int block = 256;

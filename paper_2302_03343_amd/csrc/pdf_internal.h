@@ -10,12 +10,7 @@
 struct vgx_pdf {
   int device = 0;
   int n_x = 0, n_sub = 0, n_flav = 0;
-  int fstride = 0;                    // node stride: n_flav rounded up to 4 (16-byte aligned nodes)
-  // cell guesses for knots uniform in ln x / ln Q^2 (flag 0: binary search)
-  int x_uni = 0;
-  double x_a0 = 0.0, x_inv = 0.0;
-  int q_uni[VGX_MAX_SUB] = {0};
-  double q_b0[VGX_MAX_SUB] = {0.0}, q_inv[VGX_MAX_SUB] = {0.0};
+  int fstride = 0;                    // node stride (= n_flav)
   int nq[VGX_MAX_SUB] = {0};
   int q_off[VGX_MAX_SUB + 1] = {0};   // knot offset of each subgrid
   // host copies (knots only; values stay on the device)
@@ -26,7 +21,7 @@ struct vgx_pdf {
   double* lx = nullptr;               // [n_x]            ln x knots
   double* q2 = nullptr;               // [total q]        Q^2 knots
   double* lq2 = nullptr;              // [total q]        ln Q^2 knots
-  double* v64 = nullptr;              // [total q][n_x][fstride]  node values (FP64), zero padded
+  double* v64 = nullptr;              // [total q][n_x][fstride]  node values (FP64)
   float* v32 = nullptr;               // same, FP32 copy
   unsigned long long* oor = nullptr;  // out-of-range counter
 };

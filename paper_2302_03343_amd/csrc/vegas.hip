@@ -139,30 +139,32 @@ __global__ __launch_bounds__(BLOCK) void k_vegas_iter(VegasArgs a, F f, Src src,
 }
 
 // ---------------------------------------------------------------------------
-// Fixed-order reduction of the partial rows.  Workgroup b owns columns
-// 64b .. 64b+63; its 16 waves sum the rows r = wave, wave+16, ... with
-// compensation and are combined in wave order.  Workgroup 0 then turns
-// (S1, S2, n) into the iteration record and updates the combination.
+// Fixed-order reduction of the partial rows.  Workgroup b owns the 8 columns
+// 8b .. 8b+7; its 128 row groups sum the rows r = g, g+128, ... with
+// compensation and are then combined in group order.  Workgroup 0 (which
+// owns S1 and S2) turns (S1, S2, n) into the iteration record and updates
+// the combination.
 // ---------------------------------------------------------------------------
 constexpr int RBLOCK = 1024;
-constexpr int RGROUPS = RBLOCK / 64;
+constexpr int RCOLS = 8;
+constexpr int RGROUPS = RBLOCK / RCOLS;
 
 __global__ __launch_bounds__(RBLOCK) void k_reduce(const double* __restrict__ partials, int rows, int pstride,
                                                    int ncols, double* __restrict__ hist_out, int64_t n,
                                                    IterRecord* __restrict__ rec, int k_rec, Combined* __restrict__ comb) {
-  __shared__ double ss[RGROUPS][64], sc[RGROUPS][64];
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + lane;
+  __shared__ double ss[RGROUPS][RCOLS], sc[RGROUPS][RCOLS];
+  const int cl = threadIdx.x % RCOLS, grp = threadIdx.x / RCOLS;
+  const int col = blockIdx.x * RCOLS + cl;
   Comp acc;
   if (col < ncols)
     for (int r = grp; r < rows; r += RGROUPS) acc.add(partials[(size_t)r * pstride + col]);
-  ss[grp][lane] = acc.s;
-  sc[grp][lane] = acc.c;
+  ss[grp][cl] = acc.s;
+  sc[grp][cl] = acc.c;
   __syncthreads();
-  if (grp == 0) {
+  if (threadIdx.x < RCOLS) {
     Comp t;
-    for (int g = 0; g < RGROUPS; ++g) { t.add(ss[g][lane]); t.add(sc[g][lane]); }
-    ss[0][lane] = t.value();
+    for (int g = 0; g < RGROUPS; ++g) { t.add(ss[g][cl]); t.add(sc[g][cl]); }
+    ss[0][cl] = t.value();
     if (col >= 4 && col < ncols) hist_out[col - 4] = t.value();
   }
   __syncthreads();
@@ -397,19 +399,29 @@ vgx_status launch_sample_d(vgx_vegas* v, int64_t first, int64_t n, int32_t it, d
     case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12); \
   }
 
+vgx_status timed_flush(vgx_vegas* v) {
+  for (int k = 0; k < v->t_pending; ++k) {
+    VGX_HIP(hipEventSynchronize(v->ev[2 * k + 1]));
+    float ms = 0.f;
+    VGX_HIP(hipEventElapsedTime(&ms, v->ev[2 * k], v->ev[2 * k + 1]));
+    v->t_ms += ms;
+    v->t_launches += 1;
+  }
+  v->t_pending = 0;
+  return VGX_OK;
+}
+
 vgx_status timed_begin(vgx_vegas* v) {
-  if (v->timing) VGX_HIP(hipEventRecord(v->ev[0], v->stream));
+  if (!v->timing) return VGX_OK;
+  if (v->t_pending == vgx_vegas::kTimerPairs) VGX_TRY(timed_flush(v));
+  VGX_HIP(hipEventRecord(v->ev[2 * v->t_pending], v->stream));
   return VGX_OK;
 }
 
 vgx_status timed_end(vgx_vegas* v) {
   if (!v->timing) return VGX_OK;
-  VGX_HIP(hipEventRecord(v->ev[1], v->stream));
-  VGX_HIP(hipEventSynchronize(v->ev[1]));
-  float ms = 0.f;
-  VGX_HIP(hipEventElapsedTime(&ms, v->ev[0], v->ev[1]));
-  v->t_ms += ms;
-  v->t_launches += 1;
+  VGX_HIP(hipEventRecord(v->ev[2 * v->t_pending + 1], v->stream));
+  v->t_pending += 1;
   return VGX_OK;
 }
 
@@ -438,7 +450,7 @@ vgx_status launch_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t it, dou
 }
 
 vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n) {
-  const int blocks = (ncols + 63) / 64;
+  const int blocks = (ncols + RCOLS - 1) / RCOLS;
   hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(RBLOCK), 0, v->stream, v->partials, rows, v->pstride, ncols,
                      v->hist, n, v->rec, v->n_rec, v->comb);
   VGX_HIP(hipGetLastError());
@@ -643,10 +655,10 @@ extern "C" void* vegas_stream(vgx_vegas* v) { return v ? (void*)v->stream : null
 extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
   VGX_CHECK(v, "vegas_set_timing: null context");
   if (enable && !v->ev[0]) {
-    VGX_HIP(hipEventCreate(&v->ev[0]));
-    VGX_HIP(hipEventCreate(&v->ev[1]));
+    for (int k = 0; k < 2 * vgx_vegas::kTimerPairs; ++k) VGX_HIP(hipEventCreate(&v->ev[k]));
   }
   v->timing = enable != 0;
+  v->t_pending = 0;
   v->t_ms = 0.0;
   v->t_launches = 0;
   return VGX_OK;
@@ -654,6 +666,7 @@ extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
 
 extern "C" vgx_status vegas_kernel_time(vgx_vegas* v, double* ms, int64_t* launches) {
   VGX_CHECK(v && ms && launches, "vegas_kernel_time: null argument");
+  VGX_TRY(timed_flush(v));
   *ms = v->t_ms;
   *launches = v->t_launches;
   return VGX_OK;
@@ -668,7 +681,7 @@ extern "C" void vegas_destroy(vgx_vegas* v) {
   hipFree(v->rec);
   hipFree(v->comb);
   if (v->pinned) hipHostFree(v->pinned);
-  if (v->ev[0]) hipEventDestroy(v->ev[0]);
-  if (v->ev[1]) hipEventDestroy(v->ev[1]);
+  for (int k = 0; k < 2 * vgx_vegas::kTimerPairs; ++k)
+    if (v->ev[k]) hipEventDestroy(v->ev[k]);
   delete v;
 }

@@ -187,9 +187,12 @@ struct vgx_vegas {
   void* pinned = nullptr;           // host readback (IterRecord + Combined + grid)
   int n_rec = 0;
   bool have_hist = false;
-  // kernel timing
+  // kernel timing: event pairs recorded around the fused kernel, read back
+  // (and summed) only when asked for, so timing does not synchronise
+  static constexpr int kTimerPairs = 256;
   bool timing = false;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[2 * kTimerPairs] = {};
+  int t_pending = 0;
   double t_ms = 0.0;
   int64_t t_launches = 0;
 };
