@@ -39,6 +39,42 @@ FLOPS_PER_EVENT_F32 = 2 * (368 + 32) + 60
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector (packed) peak
 PEAK_FP32_UNPACKED = 78.6e12
 
+# HBM bytes per launch of the headline kernel, from the FETCH_SIZE/WRITE_SIZE
+# passes summarised in this file; used only while the kernel's sources still
+# hash to the digest recorded there (else the traffic is reported as null).
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttbar_lo_1e7_counters.md")
+
+
+def _profile_fields(path):
+    fields = {}
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].split(": ", 1)
+                    fields[k.strip()] = v.strip()
+    except OSError:
+        pass
+    return fields
+
+
+def measured_traffic(events_per_launch):
+    """Scaled HBM bytes per launch recorded for the current kernel sources,
+    or None when the record is missing, stale or for another launch size."""
+    import hashlib
+    f = _profile_fields(TRAFFIC_PROFILE)
+    try:
+        srcs = f["sources"].split()
+        h = hashlib.sha256()
+        for s in srcs:
+            with open(os.path.join(ROOT, s), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != f["source_sha256"] or int(f["events_per_launch"]) != events_per_launch:
+            return None
+        return float(f["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -56,19 +92,31 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(grid, n_sample):
+def cpu_baseline(grid, n_sample, chunk=250_000):
     """The FP64 oracle on the first n_sample events of iteration 0 (uniform
-    grid), timed on the host.  Returns events/s."""
+    grid), in chunks of consecutive sample indices, timed on the host.
+    Returns (events/s, seconds).  Library thread pools are held to one
+    thread, so the figure is for one core."""
+    from oracle import vegas as ov
+    from synth import C2
+    from threadpoolctl import threadpool_limits
+    e = ov.uniform_grid(3, C2["n_bins"])
+    with threadpool_limits(limits=1):
+        return _cpu_baseline_run(grid, n_sample, chunk, e)
+
+
+def _cpu_baseline_run(grid, n_sample, chunk, e):
     import numpy as np
     from oracle import ttbar as ot, vegas as ov
     from oracle.philox import sample_uniforms
     from synth import C2
-    e = ov.uniform_grid(3, C2["n_bins"])
     t0 = time.perf_counter()
-    u = sample_uniforms(C2["seed"], 0, 0, np.arange(n_sample, dtype=np.uint64), 3)
-    x, jac, idx = ov.vegas_map(u, e)
-    w = ot.integrand(x, grid, C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]) * jac
-    ov.estimate_from_weights(w, idx, 3, C2["n_bins"])
+    for s0 in range(0, n_sample, chunk):
+        idx_s = np.arange(s0, min(s0 + chunk, n_sample), dtype=np.uint64)
+        u = sample_uniforms(C2["seed"], 0, 0, idx_s, 3)
+        x, jac, idx = ov.vegas_map(u, e)
+        w = ot.integrand(x, grid, C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]) * jac
+        ov.estimate_from_weights(w, idx, 3, C2["n_bins"])
     dt = time.perf_counter() - t0
     return n_sample / dt, dt
 
@@ -380,7 +428,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
             "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
-            "traffic": None,
+            "traffic": measured_traffic(n),
+            "traffic_unit": "bytes/launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE scaled by a 2 GiB copy)",
             "kernel": "k_vegas_iter<3,TTbar,PhiloxSrc<3>,true>",
             "kernel_avg_ms": kern_avg_s * 1e3,
             "flops_per_event": FLOPS_PER_EVENT_F32,
@@ -410,11 +459,11 @@ def main():
                          "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
                          "batched_64": extra_batch(vgx)}
     if not args.no_cpu:
-        n_cpu = 300_000
+        n_cpu = 4_000_000
         eps, secs = cpu_baseline(grid, n_cpu)
         out["cpu_baseline"] = {"value": eps, "unit": "events/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {n_cpu} events of iteration 0 (uniform grid), FP64 numpy, "
-                                         f"{secs:.1f} s"}
+                               "sample": f"first {n_cpu} events of iteration 0 (uniform grid), FP64 numpy on one "
+                                         f"core, chunks of 250k, {secs:.1f} s"}
     vgx.pdf_destroy(pdf)
     print(json.dumps(out), flush=True)
 
