@@ -121,9 +121,26 @@ def _cpu_baseline_run(grid, n_sample, chunk, e):
     return n_sample / dt, dt
 
 
+def next_batch(res, rel_var, target, n_max, n_min=100_000):
+    """Samples for the next iteration or batch: the number that brings the
+    inverse-variance combination to sigma/|mean| = target if the new batch
+    has relative variance rel_var per sample (n var(E)/E^2 of the last
+    batch), with 5 % margin, clamped to [n_min, n_max]."""
+    mean, sigma = abs(res["mean"]), res["sigma"]
+    if not (mean > 0 and sigma > 0 and rel_var > 0 and math.isfinite(rel_var)):
+        return n_max
+    need_inv_var = 1.0 / (target * mean) ** 2 - 1.0 / sigma ** 2
+    if need_inv_var <= 0:
+        return n_min
+    n = int(math.ceil(1.05 * need_inv_var * rel_var * mean ** 2))
+    return max(n_min, min(n_max, n))
+
+
 def time_to_precision_vegas(vgx, pdf, params, n_iter_events, target=1e-4, max_iter=30, kind=None, dim=3,
                             seed=None):
-    """Plain VEGAS from a uniform grid until sigma/mean <= target."""
+    """Plain VEGAS from a uniform grid until sigma/mean <= target; the size
+    of an iteration is the configured one, or less when fewer samples
+    reach the target (the same rule as the flow pipeline's batches)."""
     import torch
     from synth import C2
     kind = vgx.TTBAR if kind is None else kind
@@ -135,16 +152,19 @@ def time_to_precision_vegas(vgx, pdf, params, n_iter_events, target=1e-4, max_it
         t0 = time.perf_counter()
         it = 0
         res = None
+        n_next, events = n_iter_events, 0
         while it < max_iter:
-            vgx.vegas_iterate(v, n_iter_events, it)
+            r = vgx.vegas_iterate(v, n_next, it)
             vgx.vegas_refine(v)
             res = vgx.vegas_result(v)
             it += 1
+            events += n_next
             if res["sigma"] <= target * abs(res["mean"]):
                 break
+            n_next = next_batch(res, r["var"] * r["n"] / r["mean"] ** 2, target, n_iter_events)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return dict(seconds=dt, iterations=it, events=it * n_iter_events, mean=res["mean"], sigma=res["sigma"],
+        return dict(seconds=dt, iterations=it, events=events, mean=res["mean"], sigma=res["sigma"],
                     reached=bool(res["sigma"] <= target * abs(res["mean"])))
     finally:
         vgx.vegas_destroy(v)
@@ -166,7 +186,8 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
     try:
         u = torch.empty((dim, batch), dtype=torch.float64, device="cuda")
         g = torch.empty(batch, dtype=torch.float64, device="cuda")
-        y = torch.empty((dim, n_flow), dtype=torch.float64, device="cuda")
+        ybuf = torch.empty(dim * n_flow, dtype=torch.float64, device="cuda")
+        y = ybuf.view(dim, n_flow)
         lq = torch.empty(n_flow, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -187,16 +208,22 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
         k = 0
         res = vgx.vegas_result(v)
         last_flow = None
+        # first flow batch: a pilot of n_flow/10 samples; then batches sized
+        # from the flow's measured variance per sample
+        n_next, flow_events = max(n_flow // 10, 1), 0
         while res["sigma"] > target * abs(res["mean"]) and k < max_batches:
-            vgx.flow_sample(f, n_flow, seed, 5, k, y, lq)
-            last_flow = vgx.vegas_iterate_points(v, y, lq)
+            yk = ybuf[:dim * n_next].view(dim, n_next)
+            vgx.flow_sample(f, n_next, seed, 5, k, yk, lq[:n_next])
+            last_flow = vgx.vegas_iterate_points(v, yk, lq[:n_next])
             res = vgx.vegas_result(v)
+            flow_events += n_next
             k += 1
+            n_next = next_batch(res, last_flow["var"] * last_flow["n"] / last_flow["mean"] ** 2, target, n_flow)
         torch.cuda.synchronize()
         t_end = time.perf_counter()
         out = dict(seconds=t_end - t0, seconds_excluding_training=(t_end - t0) - (t_train - t_warm),
                    training_seconds=t_train - t_warm, warmup_iterations=warm_iters, train_steps=steps,
-                   train_batch=batch, flow_batches=k, flow_batch_events=n_flow, mean=res["mean"], sigma=res["sigma"],
+                   train_batch=batch, flow_batches=k, flow_events=flow_events, mean=res["mean"], sigma=res["sigma"],
                    reached=bool(res["sigma"] <= target * abs(res["mean"])), loss_first=losses[0],
                    loss_last=losses[-1])
         if last_vegas and last_flow:

@@ -34,6 +34,7 @@
 //     densities and loss sums are FP64.
 #include "common.h"
 
+#include <algorithm>
 #include <math.h>
 #include <stdlib.h>
 #include <vector>
@@ -49,6 +50,7 @@ constexpr int FL_MAX = 8;    // layers
 constexpr int FAB = 8;       // max |A|, |B|
 constexpr int FDM = VGX_MAX_DIM;
 constexpr int FBLOCK = 256;
+constexpr int FWD_BLOCK = 512;  // forward kernels: 8 waves share one LDS copy of the weights
 
 struct FlowLayerDesc {
   int na, nb;
@@ -94,7 +96,16 @@ __device__ __forceinline__ bf16x8 to_b(const f32x16& c, int half) {
 // row (feature / bin) held by register v of lane half h in a 32x32 D tile
 __device__ __forceinline__ int drow(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
-__device__ __forceinline__ float xor32(float x) { return __shfl_xor(x, 32, 64); }
+// value held by lane l ^ 32 of the wave: v_permlane32_swap trades the upper
+// half of its first operand with the lower half of its second, so with both
+// operands x the lower lanes find x[l + 32] in the second result and the
+// upper lanes x[l - 32] in the first
+__device__ __forceinline__ unsigned xor32u(unsigned x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return (threadIdx.x & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ float xor32(float x) { return __uint_as_float(xor32u(__float_as_uint(x))); }
+__device__ __forceinline__ int xor32i(int x) { return (int)xor32u((unsigned)x); }
 
 // read / write z[j] for a runtime j without dynamic register indexing
 __device__ __forceinline__ float zget(const float (&z)[FDM], int j) {
@@ -131,7 +142,23 @@ __device__ __forceinline__ LayerLds layer_lds(const unsigned short* fw, const fl
   return r;
 }
 
-// Network forward of one layer for the wave's 32 samples (transposed form).
+// Accumulator tile holding bias b[row] in the register of each row of a
+// 32x32 D tile (rows 8 (v >> 2) + 4 h + (v & 3)): four 16-byte LDS reads.
+__device__ __forceinline__ f32x16 bias_tile(const float* b, int h) {
+  f32x16 r;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 q = *(const float4*)(b + 8 * g + 4 * h);
+    r[4 * g] = q.x;
+    r[4 * g + 1] = q.y;
+    r[4 * g + 2] = q.z;
+    r[4 * g + 3] = q.w;
+  }
+  return r;
+}
+
+// Network forward of one layer for the wave's 32 samples (transposed form);
+// the biases enter as the accumulators' initial values.
 template <int NBM>
 __device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, const LayerLds& W, f32x16 (&h1)[2],
                                         f32x16 (&h2)[2], f32x16 (&lg)[NBM]) {
@@ -141,34 +168,33 @@ __device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, 
   for (int e = 0; e < 8; ++e) bz[e] = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    h1[t] = mfma(W.w1p[(t * 32 + i) * 2 + h], bz, zero16());
+    h1[t] = mfma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
 #pragma unroll
-    for (int v = 0; v < 16; ++v) h1[t][v] = fmaxf(h1[t][v] + W.b1[32 * t + drow(v, h)], 0.0f);
+    for (int v = 0; v < 16; ++v) h1[t][v] = fmaxf(h1[t][v], 0.0f);
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    f32x16 acc = zero16();
+    f32x16 acc = bias_tile(W.b2 + 32 * t, h);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], to_b(h1[kk >> 1], kk & 1), acc);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v] + W.b2[32 * t + drow(v, h)], 0.0f);
+    for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v], 0.0f);
     h2[t] = acc;
   }
 #pragma unroll
   for (int t = 0; t < NBM; ++t) {
     if (t < nb) {
-      f32x16 acc = zero16();
+      f32x16 acc = bias_tile(W.b3 + 32 * t, h);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], to_b(h2[kk >> 1], kk & 1), acc);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] += W.b3[32 * t + drow(v, h)];
       lg[t] = acc;
     }
   }
 }
 
-// in-place softmax over the 32 bins of one B dim (16 here, 16 in lane^32)
-__device__ __forceinline__ void softmax32(f32x16& q) {
+// in place: exponentials of the 32 logits of one B dim less their maximum
+// (16 here, 16 in lane^32), unnormalised; returns their sum
+__device__ __forceinline__ float softexp32(f32x16& q) {
   float m = q[0];
 #pragma unroll
   for (int v = 1; v < 16; ++v) m = fmaxf(m, q[v]);
@@ -181,14 +207,19 @@ __device__ __forceinline__ void softmax32(f32x16& q) {
     q[v] = __expf(q[v] - m);
     s += q[v];
   }
-  s += xor32(s);
-  const float inv = 1.0f / s;
+  return s + xor32(s);
+}
+
+// in-place softmax over the 32 bins of one B dim
+__device__ __forceinline__ void softmax32(f32x16& q) {
+  const float inv = 1.0f / softexp32(q);
 #pragma unroll
   for (int v = 0; v < 16; ++v) q[v] *= inv;
 }
 
-// density direction for one B dim: returns z', sets the bin, alpha, Q_b
-__device__ __forceinline__ float cdf_fwd(const f32x16& q, float z, int& b, float& al, float& qb) {
+// density direction for one B dim: returns z', sets the bin, alpha, Q_b;
+// q holds the bin weights scaled by 1/inv (inv = 1 for probabilities)
+__device__ __forceinline__ float cdf_fwd(const f32x16& q, float z, int& b, float& al, float& qb, float inv = 1.0f) {
   const int h = (threadIdx.x >> 5) & 1;
   const float t = z * (float)FK;
   int bb = (int)floorf(t);
@@ -201,15 +232,17 @@ __device__ __forceinline__ float cdf_fwd(const f32x16& q, float z, int& b, float
     lt += (k < bb) ? q[v] : 0.0f;
     qq += (k == bb) ? q[v] : 0.0f;
   }
-  lt += xor32(lt);
-  qq += xor32(qq);
+  lt = (lt + xor32(lt)) * inv;
+  qq = (qq + xor32(qq)) * inv;
   b = bb;
   qb = qq;
   return lt + al * qq;
 }
 
-// sampling direction for one B dim: returns z, sets the bin and Q_b
-__device__ __forceinline__ float cdf_inv(const f32x16& q, float v, int& b, float& qb) {
+// sampling direction for one B dim: returns z, sets the bin and Q_b; q
+// holds unnormalised bin weights with sum sum (the search runs on v sum)
+__device__ __forceinline__ float cdf_inv(const f32x16& q, float v, float sum, int& b, float& qb) {
+  v *= sum;
   const int lane = threadIdx.x & 63, h = lane >> 5;
   float cs[4], ps[4];
 #pragma unroll
@@ -249,12 +282,15 @@ __device__ __forceinline__ float cdf_inv(const f32x16& q, float v, int& b, float
       run += qr;
     }
   }
-  const int src = (lane & 31) + 32 * (cstar & 1);
-  bb = __shfl(bb, src, 64);
-  cb = __shfl(cb, src, 64);
-  qq = __shfl(qq, src, 64);
+  // take the owner's values (own lane or lane ^ 32)
+  const bool own = (cstar & 1) == h;
+  const int bx = xor32i(bb);
+  const float cx = xor32(cb), qx = xor32(qq);
+  bb = own ? bb : bx;
+  cb = own ? cb : cx;
+  qq = own ? qq : qx;
   b = bb;
-  qb = qq;
+  qb = qq / sum;
   float frac = (v - cb) / qq;
   frac = frac < 0.0f ? 0.0f : (frac > 1.0f ? 1.0f : frac);
   return ((float)bb + frac) * (1.0f / (float)FK);
@@ -292,69 +328,68 @@ struct FwdArgs {
   uint32_t it, sid, k0, k1;  // sampling: Philox counter / key
 };
 
+// LDS of a forward kernel: packed weights | biases | per-lane z [d][FWD_BLOCK]
+__host__ __device__ inline size_t fwd_z_offset(int fw_total, int bias_total) {
+  return (((size_t)fw_total * 2 + (size_t)bias_total * 4) + 15) & ~(size_t)15;
+}
+
 template <int NBM, int MODE>
-__global__ __launch_bounds__(FBLOCK) void k_flow_fwd(const FlowDesc* __restrict__ Dp, FwdArgs a, const unsigned short* __restrict__ fw,
+__global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restrict__ Dp, FwdArgs a, const unsigned short* __restrict__ fw,
                                                      const float* __restrict__ bias) {
   extern __shared__ __align__(16) unsigned char flds[];
   const FlowDesc& D = *Dp;
   unsigned short* sfw = (unsigned short*)flds;
   float* sb = (float*)(flds + D.fw_total * 2);
+  // each lane keeps its sample's coordinates in its own LDS column (the
+  // layer masks index them with runtime, wave-uniform indices)
+  float* z = (float*)(flds + fwd_z_offset(D.fw_total, D.bias_total)) + threadIdx.x;
   copy16(sfw, fw, D.fw_total * 2);
   copy16(sb, bias, D.bias_total * 4);
   __syncthreads();
   const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
-  const int wave = blockIdx.x * (FBLOCK / 64) + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * (FBLOCK / 64);
+  const int wave = blockIdx.x * (FWD_BLOCK / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (FWD_BLOCK / 64);
   const int64_t ntiles = (a.n + 31) / 32;
+  const int d = D.d;
   Comp sr, sg;
   for (int64_t t = wave; t < ntiles; t += nwaves) {
     const int64_t i = t * 32 + s;
     const bool valid = i < a.n;
-    float z[FDM];
-#pragma unroll
-    for (int j = 0; j < FDM; ++j) z[j] = 0.5f;
     if (MODE == 2) {
+      for (int bk = 0; 4 * bk < d; ++bk) {
+        const u32x4 w = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), a.it, (a.sid << 8) | (uint32_t)bk,
+                                      a.k0, a.k1);
+        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-      for (int bk = 0; bk < (FDM + 3) / 4; ++bk) {
-        if (4 * bk < D.d) {
-          const u32x4 w = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), a.it, (a.sid << 8) | (uint32_t)bk,
-                                        a.k0, a.k1);
-          const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (4 * bk + e < FDM) z[4 * bk + e] = (float)word_to_unit(ww[e]);
-        }
+        for (int e = 0; e < 4; ++e)
+          if (4 * bk + e < d) z[(4 * bk + e) * FWD_BLOCK] = (float)word_to_unit(ww[e]);
       }
-    } else if (valid) {
-#pragma unroll
-      for (int j = 0; j < FDM; ++j)
-        if (j < D.d) z[j] = (float)a.yin[(int64_t)j * a.n + i];
+    } else {
+      for (int j = 0; j < d; ++j) z[j * FWD_BLOCK] = valid ? (float)a.yin[(int64_t)j * a.n + i] : 0.5f;
     }
     double lq = 0.0;
     for (int step = 0; step < D.L; ++step) {
       const int l = (MODE == 2) ? D.L - 1 - step : step;
       const FlowLayerDesc& L = D.l[l];
       if (MODE == 1 && valid && h == 0) {
-#pragma unroll
-        for (int j = 0; j < FDM; ++j)
-          if (j < D.d) a.zsave[((int64_t)l * D.d + j) * a.n + i] = z[j];
+        for (int j = 0; j < d; ++j) a.zsave[((int64_t)l * d + j) * a.n + i] = z[j * FWD_BLOCK];
       }
       float za[FAB];
 #pragma unroll
-      for (int e = 0; e < FAB; ++e) za[e] = (e < L.na) ? zget(z, L.a_idx[e]) : 0.0f;
+      for (int e = 0; e < FAB; ++e) za[e] = (e < L.na) ? z[L.a_idx[e] * FWD_BLOCK] : 0.0f;
       const LayerLds W = layer_lds(sfw, sb, L, 0, 0);
       f32x16 h1[2], h2[2], lg[NBM];
       mlp_fwd<NBM>(za, L.na, L.nb, W, h1, h2, lg);
 #pragma unroll
       for (int jb = 0; jb < NBM; ++jb) {
         if (jb < L.nb) {
-          softmax32(lg[jb]);
+          const float sum = softexp32(lg[jb]);
           const int j = L.b_idx[jb];
-          const float zj = zget(z, j);
+          const float zj = z[j * FWD_BLOCK];
           int b;
           float qb, al;
-          const float zn = (MODE == 2) ? cdf_inv(lg[jb], zj, b, qb) : cdf_fwd(lg[jb], zj, b, al, qb);
-          zset(z, j, zn);
+          const float zn = (MODE == 2) ? cdf_inv(lg[jb], zj, sum, b, qb) : cdf_fwd(lg[jb], zj, b, al, qb, 1.0f / sum);
+          z[j * FWD_BLOCK] = zn;
           lq += (double)logf((float)FK * qb);
         }
       }
@@ -362,9 +397,7 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_fwd(const FlowDesc* __restrict_
     if (valid && h == 0) {
       a.logq[i] = lq;
       if (a.out) {
-#pragma unroll
-        for (int j = 0; j < FDM; ++j)
-          if (j < D.d) a.out[(int64_t)j * a.n + i] = (double)z[j];
+        for (int j = 0; j < d; ++j) a.out[(int64_t)j * a.n + i] = (double)z[j * FWD_BLOCK];
       }
       if (MODE == 1) {
         const double gi = a.g[i];
@@ -376,14 +409,14 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_fwd(const FlowDesc* __restrict_
     }
   }
   if (MODE == 1) {
-    __shared__ double red[4][FBLOCK / 64];
+    __shared__ double red[4][FWD_BLOCK / 64];
     const double v0 = wave_sum(sr.s), v1 = wave_sum(sr.c), v2 = wave_sum(sg.s), v3 = wave_sum(sg.c);
     const int wv = threadIdx.x >> 6;
     if (lane == 0) { red[0][wv] = v0; red[1][wv] = v1; red[2][wv] = v2; red[3][wv] = v3; }
     __syncthreads();
     if (threadIdx.x < 4) {
       double acc = 0.0;
-      for (int k = 0; k < FBLOCK / 64; ++k) acc += red[threadIdx.x][k];
+      for (int k = 0; k < FWD_BLOCK / 64; ++k) acc += red[threadIdx.x][k];
       a.partials[blockIdx.x * 4 + threadIdx.x] = acc;
     }
   }
@@ -438,8 +471,14 @@ __device__ __forceinline__ void put_tile(unsigned short* base, int row0, const f
   }
 }
 
+// LDS of the backward kernel: the layer's forward and backward packs and
+// biases, then per-lane columns z, dz_out, dz [3][d][FBLOCK]
+__host__ __device__ inline size_t bwd_z_offset(int fw_len, int bw_len, int bias_len) {
+  return (((size_t)fw_len * 2 + (size_t)bw_len * 2 + (size_t)bias_len * 4) + 15) & ~(size_t)15;
+}
+
 template <int NBM>
-__global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict__ Dp, BwdArgs a, const unsigned short* __restrict__ fw,
+__global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const FlowDesc* __restrict__ Dp, BwdArgs a, const unsigned short* __restrict__ fw,
                                                      const unsigned short* __restrict__ bw,
                                                      const float* __restrict__ bias) {
   extern __shared__ __align__(16) unsigned char flds[];
@@ -448,6 +487,12 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
   unsigned short* sfw = (unsigned short*)flds;
   unsigned short* sbw = sfw + L.fw_len;
   float* sb = (float*)(sbw + L.bw_len);
+  const int d = D.d;
+  // the sample's coordinates (z), the incoming gradient (gz) and the
+  // outgoing gradient (dz) in the lane's own LDS columns
+  float* z = (float*)(flds + bwd_z_offset(L.fw_len, L.bw_len, L.bias_len)) + threadIdx.x;
+  float* gz = z + d * FBLOCK;
+  float* dz = gz + d * FBLOCK;
   copy16(sfw, fw + L.fw_off, L.fw_len * 2);
   copy16(sbw, bw + L.bw_off, L.bw_len * 2);
   copy16(sb, bias + L.bias_off, L.bias_len * 4);
@@ -465,28 +510,39 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
   for (int64_t t = wave; t < ntiles; t += nwaves) {
     const int64_t i = t * 32 + s;
     const bool valid = i < a.n;
-    float z[FDM], gz[FDM];
-#pragma unroll
-    for (int j = 0; j < FDM; ++j) { z[j] = 0.5f; gz[j] = 0.0f; }
-    float dlq = 0.0f;
-    if (valid) {
-#pragma unroll
-      for (int j = 0; j < FDM; ++j) {
-        if (j < D.d) {
-          z[j] = a.zin[(int64_t)j * a.n + i];
-          if (a.dzout) gz[j] = a.dzout[(int64_t)j * a.n + i];
-        }
-      }
-      dlq = (float)(a.rsave[i] * scale);
+    for (int j = 0; j < d; ++j) {
+      z[j * FBLOCK] = valid ? a.zin[(int64_t)j * a.n + i] : 0.5f;
+      const float g0 = (valid && a.dzout) ? a.dzout[(int64_t)j * a.n + i] : 0.0f;
+      gz[j * FBLOCK] = g0;
+      dz[j * FBLOCK] = g0;
     }
+    const float dlq = valid ? (float)(a.rsave[i] * scale) : 0.0f;
     float za[FAB];
 #pragma unroll
-    for (int e = 0; e < FAB; ++e) za[e] = (e < na) ? zget(z, L.a_idx[e]) : 0.0f;
+    for (int e = 0; e < FAB; ++e) za[e] = (e < na) ? z[L.a_idx[e] * FBLOCK] : 0.0f;
     f32x16 h1[2], h2[2], lg[NBM];
     mlp_fwd<NBM>(za, na, nb, W, h1, h2, lg);
-    float dz[FDM];
+    // BF16 operand tiles for the weight gradients, written as soon as they
+    // exist; only the ReLU masks of h1, h2 stay live (invalid samples carry
+    // zero deltas, so they add nothing)
+    unsigned short* base = a.scr + (size_t)t * a.srows * 32;
 #pragma unroll
-    for (int j = 0; j < FDM; ++j) dz[j] = gz[j];
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 x = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
+      base[(8 * h + e) * 32 + s] = *(const unsigned short*)&x;
+    }
+    put_tile(base, 32, h1[0], s, h);
+    put_tile(base, 64, h1[1], s, h);
+    put_tile(base, 96, h2[0], s, h);
+    put_tile(base, 128, h2[1], s, h);
+    unsigned m1[2] = {0u, 0u}, m2[2] = {0u, 0u};
+#pragma unroll
+    for (int to = 0; to < 2; ++to)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        m1[to] |= (h1[to][v] > 0.0f ? 1u : 0u) << v;
+        m2[to] |= (h2[to][v] > 0.0f ? 1u : 0u) << v;
+      }
     // bins, dQ and dlogit per transformed dim
 #pragma unroll
     for (int jb = 0; jb < NBM; ++jb) {
@@ -495,8 +551,8 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
         const int j = L.b_idx[jb];
         int b;
         float al, qb;
-        cdf_fwd(lg[jb], zget(z, j), b, al, qb);
-        const float g_out = zget(gz, j);
+        cdf_fwd(lg[jb], z[j * FBLOCK], b, al, qb);
+        const float g_out = gz[j * FBLOCK];
         float dq[16];
         float sdot = 0.0f;
 #pragma unroll
@@ -508,7 +564,8 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
         sdot += xor32(sdot);
 #pragma unroll
         for (int v = 0; v < 16; ++v) lg[jb][v] = lg[jb][v] * (dq[v] - sdot);  // dlogit
-        zset(dz, j, g_out * (float)FK * qb);
+        dz[j * FBLOCK] = g_out * (float)FK * qb;
+        put_tile(base, 288 + 32 * jb, lg[jb], s, h);
       }
     }
     // dh2 = W3^T dlogit, masked by relu'
@@ -520,9 +577,11 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
       for (int kk = 0; kk < 2 * NBM; ++kk)
         if (kk < 2 * nb) acc = mfma(w3t[((to * 2 * nb + kk) * 32 + s) * 2 + h], to_b(lg[kk >> 1], kk & 1), acc);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = h2[to][v] > 0.0f ? acc[v] : 0.0f;
+      for (int v = 0; v < 16; ++v) acc[v] = ((m2[to] >> v) & 1u) ? acc[v] : 0.0f;
       d2[to] = acc;
     }
+    put_tile(base, 224, d2[0], s, h);
+    put_tile(base, 256, d2[1], s, h);
     // dh1 = W2^T dpre2, masked
     f32x16 d1[2];
 #pragma unroll
@@ -531,9 +590,11 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc = mfma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], to_b(d2[kk >> 1], kk & 1), acc);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = h1[to][v] > 0.0f ? acc[v] : 0.0f;
+      for (int v = 0; v < 16; ++v) acc[v] = ((m1[to] >> v) & 1u) ? acc[v] : 0.0f;
       d1[to] = acc;
     }
+    put_tile(base, 160, d1[0], s, h);
+    put_tile(base, 192, d1[1], s, h);
     // dzA = W1^T dpre1: rows a = 4h + r in registers 0..3
     f32x16 d0 = zero16();
 #pragma unroll
@@ -547,34 +608,10 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwd(const FlowDesc* __restrict_
     }
 #pragma unroll
     for (int e = 0; e < FAB; ++e)
-      if (e < na) {
-        const int j = L.a_idx[e];
-        zset(dz, j, zget(dz, j) + dza[e]);
-      }
+      if (e < na) dz[L.a_idx[e] * FBLOCK] += dza[e];
     if (valid && h == 0) {
-#pragma unroll
-      for (int j = 0; j < FDM; ++j)
-        if (j < D.d) a.dzin[(int64_t)j * a.n + i] = dz[j];
+      for (int j = 0; j < d; ++j) a.dzin[(int64_t)j * a.n + i] = dz[j * FBLOCK];
     }
-    // BF16 operand tiles for the weight gradients (invalid samples carry
-    // zero deltas, so they add nothing)
-    unsigned short* base = a.scr + (size_t)t * a.srows * 32;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const __bf16 x = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
-      base[(8 * h + e) * 32 + s] = *(const unsigned short*)&x;
-    }
-    put_tile(base, 32, h1[0], s, h);
-    put_tile(base, 64, h1[1], s, h);
-    put_tile(base, 96, h2[0], s, h);
-    put_tile(base, 128, h2[1], s, h);
-    put_tile(base, 160, d1[0], s, h);
-    put_tile(base, 192, d1[1], s, h);
-    put_tile(base, 224, d2[0], s, h);
-    put_tile(base, 256, d2[1], s, h);
-#pragma unroll
-    for (int jb = 0; jb < NBM; ++jb)
-      if (jb < nb) put_tile(base, 288 + 32 * jb, lg[jb], s, h);
   }
 }
 
@@ -930,7 +967,14 @@ vgx_status build_desc(int dim, int L, FlowDesc& D, std::vector<int>& fws, std::v
   return VGX_OK;
 }
 
-size_t fwd_lds(const vgx_flow* f) { return (size_t)f->D.fw_total * 2 + (size_t)f->D.bias_total * 4; }
+size_t bwd_lds(const vgx_flow* f, int l) {
+  const FlowLayerDesc& Ld = f->D.l[l];
+  return bwd_z_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len) + sizeof(float) * 3 * (size_t)f->dim * FBLOCK;
+}
+
+size_t fwd_lds(const vgx_flow* f) {
+  return fwd_z_offset(f->D.fw_total, f->D.bias_total) + sizeof(float) * (size_t)f->dim * FWD_BLOCK;
+}
 
 vgx_status pack(vgx_flow* f) {
   const int tot = f->D.fw_total > f->D.bw_total ? f->D.fw_total : f->D.bw_total;
@@ -960,10 +1004,10 @@ vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr) {
 }
 
 vgx_status init_lds_limits(const vgx_flow* f) {
-  size_t fwd = (size_t)f->D.fw_total * 2 + (size_t)f->D.bias_total * 4, bwd = 0, wgr = 0;
+  size_t fwd = fwd_lds(f), bwd = 0, wgr = 0;
   for (int l = 0; l < f->L; ++l) {
     const FlowLayerDesc& Ld = f->D.l[l];
-    const size_t b = (size_t)Ld.fw_len * 2 + (size_t)Ld.bw_len * 2 + (size_t)Ld.bias_len * 4;
+    const size_t b = bwd_lds(f, l);
     bwd = b > bwd ? b : bwd;
     wgr = (size_t)Ld.n_par * 4 > wgr ? (size_t)Ld.n_par * 4 : wgr;
   }
@@ -977,7 +1021,7 @@ vgx_status init_lds_limits(const vgx_flow* f) {
 
 int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
   const int64_t tiles = (n + 31) / 32;
-  const int64_t waves_per_wg = FBLOCK / 64;
+  const int64_t waves_per_wg = FWD_BLOCK / 64;
   int64_t g = (tiles + waves_per_wg - 1) / waves_per_wg;
   const int64_t cap = (int64_t)device_cus() * per_cu;
   if (g > cap) g = cap;
@@ -989,7 +1033,7 @@ vgx_status launch_fwd(vgx_flow* f, int grid, const FwdArgs& a, hipStream_t st) {
   const size_t lds = fwd_lds(f);
 #define L_(NB)                                                                                        \
   case NB:                                                                                            \
-    hipLaunchKernelGGL((k_flow_fwd<NB, MODE>), dim3(grid), dim3(FBLOCK), lds, st, f->d_desc, a, f->fw, f->bias); \
+    hipLaunchKernelGGL((k_flow_fwd<NB, MODE>), dim3(grid), dim3(FWD_BLOCK), lds, st, f->d_desc, a, f->fw, f->bias); \
     break;
   switch (f->nbm) { L_(1) L_(2) L_(4) L_(8) default: set_error("flow: bad |B| bound"); return VGX_EINVAL; }
 #undef L_
@@ -1040,6 +1084,9 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
   hipLaunchKernelGGL(k_flow_loss, dim3(1), dim3(256), 0, f->stream, f->partials, grid, f->loss);
   VGX_HIP(hipGetLastError());
   const int wgrid = f->grid_w;
+  // backward: two resident workgroups per CU (the layer's packs in LDS)
+  const int64_t btiles = (n + 31) / 32;
+  const int bgrid = (int)std::min<int64_t>(std::max<int64_t>((btiles + 3) / 4, 1), 2 * (int64_t)device_cus());
   int cur = 0;
   for (int l = f->L - 1; l >= 0; --l) {
     const FlowLayerDesc& Ld = f->D.l[l];
@@ -1053,10 +1100,10 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     b.loss = f->loss;
     b.scr = f->scr;
     b.srows = f->srows;
-    const size_t lds = (size_t)Ld.fw_len * 2 + (size_t)Ld.bw_len * 2 + (size_t)Ld.bias_len * 4;
+    const size_t lds = bwd_lds(f, l);
 #define B_(NB)                                                                                        \
   case NB:                                                                                            \
-    hipLaunchKernelGGL((k_flow_bwd<NB>), dim3(grid), dim3(FBLOCK), lds, f->stream, f->d_desc, b, f->fw, f->bw, f->bias); \
+    hipLaunchKernelGGL((k_flow_bwd<NB>), dim3(bgrid), dim3(FBLOCK), lds, f->stream, f->d_desc, b, f->fw, f->bw, f->bias); \
     break;
     switch (f->nbm) { B_(1) B_(2) B_(4) B_(8) default: return VGX_EINVAL; }
 #undef B_

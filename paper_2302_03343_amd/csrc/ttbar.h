@@ -23,7 +23,12 @@
 //
 // PDF lookup at the fixed scale mu^2 = m_t^2: the four Q^2 rows j-1..j+2
 // around mu^2 (two rows if the Q stencil is incomplete) are staged in LDS as
-// FP32 [ix][flav][row] (one 16-byte read per node and flavour); per event
+// FP32 [node][flav][row] (one 16-byte read per node and flavour), the nodes
+// grouped by (node mod 4): step k of the 4-node stencil reads, in every
+// lane, the stencil node congruent to k mod 4, so lanes whose cells lie
+// close together read one address (a broadcast) and lanes further apart
+// fall on distinct banks (consecutive groups of four nodes are 11 x 16 bytes
+// apart, an odd multiple of 16 bytes); per event
 // and per x the cubic Hermite (secant
 // slopes) in ln x and then in ln Q^2 is evaluated for all 11 flavours, as a
 // 4x4 weighted sum w_rk = q_r c_k of the stencil (same linear function as
@@ -49,7 +54,11 @@ struct TTbarConst {
   int fstride;
   const double* lx; // device ln x knots
   const double* lq2;// device ln Q^2 knots (all subgrids)
-  int n_x;
+  int n_x;          // x knots of the grid
+  int ix0;          // first staged x node: events never reach ln x < ln tau0,
+                    // so nodes below the cell of ln tau0 (less a margin of two
+                    // cells) are not staged
+  int nxs;          // staged x nodes, n_x - ix0
   int row0;         // global index of the first staged Q^2 row
   int n_rows;       // 4 (bicubic in Q) or 2 (bilinear in Q)
   int j_local;      // cell index of mu^2 inside its subgrid
@@ -59,36 +68,45 @@ struct TTbarConst {
   int contract;     // 1: Q^2 direction contracted once per workgroup
 };
 
-// LDS footprint in floats: node values [n_x][11][4 rows] (16-byte aligned
-// float4 per node and flavour), ln x knots, inverse spacings, Q weights and
-// the cell-guess constants.
-__host__ __device__ inline int ttbar_lds_floats(int n_x) { return n_x * 4 * TT_NF + 2 * n_x + 16; }
+// LDS footprint in floats for nxs staged x nodes: node values, padded to a
+// multiple of 4 nodes, [4][nxs/4][11][4 rows] (16-byte aligned float4 per
+// node and flavour), ln x knots, inverse spacings, Q weights and the
+// cell-guess constants.
+__host__ __device__ inline int ttbar_lds_floats(int nxs) {
+  return ((nxs + 3) & ~3) * 4 * TT_NF + 2 * nxs + 16;
+}
 
 struct TTbar {
   static constexpr bool kStage = true;
   TTbarConst c;
-  const float4* F;  // LDS [n_x][11] float4: the (up to) four Q^2 rows of one node and flavour
-  float* sa;        // LDS ln x knots [n_x]
-  float* sinv;      // LDS 1/(a_{i+1} - a_i) [n_x]
+  // LDS tables are indexed by the staged node k = ix - ix0
+  const float4* F;  // LDS [4][nq4][11] float4: the (up to) four Q^2 rows of one node and flavour
+  int nq4;          // staged nodes per residue class mod 4
+  float* sa;        // LDS ln x knots [nxs]
+  float* sinv;      // LDS 1/(a_{k+1} - a_k) [nxs]
   float* qw;        // LDS [0..3] Q-row Hermite weights, [4] bilinear t_b, [5] a_0, [6] 1/da, [7] uniform flag
 
   __device__ void stage(float* lds) {
     float* Fs = lds;
     F = (const float4*)lds;
-    sa = Fs + c.n_x * 4 * TT_NF;
-    sinv = sa + c.n_x;
-    qw = sinv + c.n_x;
+    const int nxs = c.nxs;
+    nq4 = (nxs + 3) >> 2;
+    sa = Fs + nq4 * 4 * 4 * TT_NF;
+    sinv = sa + nxs;
+    qw = sinv + nxs;
     const int nr = c.n_rows;
-    const int tot = c.n_x * TT_NF * 4;
+    const int tot = nq4 * 4 * TT_NF * 4;
+    const double* lx = c.lx + c.ix0;
     for (int k = threadIdx.x; k < tot; k += blockDim.x) {
       const int r = k & 3;
       const int f = (k >> 2) % TT_NF;
-      const int ix = (k >> 2) / TT_NF;
-      Fs[k] = r < nr ? c.v32[((size_t)(c.row0 + r) * c.n_x + ix) * c.fstride + f] : 0.0f;
+      const int pos = (k >> 2) / TT_NF;            // (n mod 4) nq4 + n / 4
+      const int n = (pos % nq4) * 4 + pos / nq4;   // staged node
+      Fs[k] = (r < nr && n < nxs) ? c.v32[((size_t)(c.row0 + r) * c.n_x + c.ix0 + n) * c.fstride + f] : 0.0f;
     }
-    for (int k = threadIdx.x; k < c.n_x; k += blockDim.x) {
-      sa[k] = (float)c.lx[k];
-      sinv[k] = k + 1 < c.n_x ? (float)(1.0 / (c.lx[k + 1] - c.lx[k])) : 0.0f;
+    for (int k = threadIdx.x; k < nxs; k += blockDim.x) {
+      sa[k] = (float)lx[k];
+      sinv[k] = k + 1 < nxs ? (float)(1.0 / (lx[k + 1] - lx[k])) : 0.0f;
     }
     if (threadIdx.x == 0) {
       // weights of the Q rows at mu^2 (FP64 setup, FP32 storage)
@@ -112,11 +130,11 @@ struct TTbar {
       }
       qw[4] = (float)t;  // linear weight in ln Q^2 for the bilinear fallback
       // cell guess for knots uniform in ln x (checked here; else binary search)
-      const int n = c.n_x;
-      const double a0 = c.lx[0], da = (c.lx[n - 1] - c.lx[0]) / (n - 1);
+      const int n = nxs;
+      const double a0 = lx[0], da = (lx[n - 1] - lx[0]) / (n - 1);
       bool uni = true;
       for (int k = 0; k < n; ++k)
-        if (fabs(c.lx[k] - (a0 + k * da)) > 1e-3 * da) uni = false;
+        if (fabs(lx[k] - (a0 + k * da)) > 1e-3 * da) uni = false;
       qw[5] = (float)a0;
       qw[6] = (float)(1.0 / da);
       qw[7] = uni ? 1.0f : 0.0f;
@@ -128,13 +146,13 @@ struct TTbar {
       // The node values occupy F; the tables are built in registers first.
       __syncthreads();
       float pv[2][(TT_MAX_NX * 12 + 255) / 256];
-      const int tot12 = c.n_x * 12;
+      const int tot12 = nxs * 12;
       int q = 0;
       for (int k = threadIdx.x; k < tot12; k += blockDim.x, ++q) {
         const int f = k % 12, ix = k / 12;
         float hp = 0.f, lp = 0.f;
         if (f < TT_NF) {
-          const float4 v = F[(size_t)ix * TT_NF + f];
+          const float4 v = F[node_off(ix) + f];
           hp = fmaf(qw[0], v.x, fmaf(qw[1], v.y, fmaf(qw[2], v.z, qw[3] * v.w)));
           const float tb = qw[4];
           lp = c.n_rows == 4 ? fmaf(tb, v.z - v.y, v.y) : fmaf(tb, v.y - v.x, v.x);
@@ -152,15 +170,21 @@ struct TTbar {
     }
   }
 
-  // cell i with sa[i] <= a < sa[i+1], clamped to [0, n_x - 2]
+  // float4 offset of staged node n in F
+  __device__ __forceinline__ int node_off(int n) const { return ((n & 3) * nq4 + (n >> 2)) * TT_NF; }
+
+  // staged cell k with sa[k] <= a < sa[k+1], clamped to [k_lo, nxs - 2];
+  // k_lo = 1 when nodes below the staged range exist (never reached by
+  // events: it only keeps the stencil's node k - 1 inside the table)
   __device__ __forceinline__ int cell(float a) const {
-    const int nx = c.n_x;
+    const int nx = c.nxs;
+    const int klo = c.ix0 > 0 ? 1 : 0;
     if (qw[7] != 0.0f) {
       // guess from the uniform spacing, then settle on the stored knots
       // (the same cell as a binary search over sa)
       int i = (int)((a - qw[5]) * qw[6]);
-      i = i < 0 ? 0 : (i > nx - 2 ? nx - 2 : i);
-      while (i > 0 && a < sa[i]) --i;
+      i = i < klo ? klo : (i > nx - 2 ? nx - 2 : i);
+      while (i > klo && a < sa[i]) --i;
       while (i < nx - 2 && a >= sa[i + 1]) ++i;
       return i;
     }
@@ -169,16 +193,16 @@ struct TTbar {
       const int mid = (lo + hi) >> 1;
       if (sa[mid] <= a) lo = mid; else hi = mid;
     }
-    return lo;
+    return lo > klo ? lo : klo;
   }
 
   // xf of all flavours at ln x = a, fixed-scale contracted tables.
   __device__ __forceinline__ void pdf_at_contracted(int i, float t, float (&xf)[TT_NF]) const {
-    const int nx = c.n_x;
+    const int nx = c.nxs;
     const float4* P = F;                    // [ix][3] float4: Hermite-in-Q contraction
     const float4* Pl = F + (size_t)nx * 3;  // [ix][3] float4: linear-in-Q contraction
     float v[12];
-    if (c.n_rows == 4 && i >= 1 && i <= nx - 3) {
+    if (c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3) {
       const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
       const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
       const float t2 = t * t, t3 = t2 * t;
@@ -221,14 +245,14 @@ struct TTbar {
 
   // xf of all flavours at ln x = a (a <= 0).
   __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
-    const int nx = c.n_x;
+    const int nx = c.nxs;
     const int i = cell(a);
     const float t = (a - sa[i]) * sinv[i];
     if (c.contract) {
       pdf_at_contracted(i, t, xf);
       return;
     }
-    if (c.n_rows == 4 && i >= 1 && i <= nx - 3) {
+    if (c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3) {
       const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
       const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
       const float t2 = t * t, t3 = t2 * t;
@@ -240,12 +264,20 @@ struct TTbar {
       cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
       cx[3] = 0.5f * h11 * rp;
       const float q0 = qw[0], q1 = qw[1], q2 = qw[2], q3 = qw[3];
+      // step k visits the stencil node n_k = congruent to k mod 4 in
+      // [i-1, i+2]: n_k = 4 mb + k + 4 [k < r] with i-1 = 4 mb + r, weight
+      // cx[(k - r) mod 4]
+      const int base = i - 1, r = base & 3, mb = base >> 2;
+      const bool o1 = r & 1, o2 = r & 2;
+      const float d0 = o1 ? cx[3] : cx[0], d1 = o1 ? cx[0] : cx[1];
+      const float d2 = o1 ? cx[1] : cx[2], d3 = o1 ? cx[2] : cx[3];
+      const float cr[4] = {o2 ? d2 : d0, o2 ? d3 : d1, o2 ? d0 : d2, o2 ? d1 : d3};
 #pragma unroll
       for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float w0 = cx[k] * q0, w1 = cx[k] * q1, w2 = cx[k] * q2, w3 = cx[k] * q3;
-        const float4* node = F + (size_t)(i - 1 + k) * TT_NF;
+        const float w0 = cr[k] * q0, w1 = cr[k] * q1, w2 = cr[k] * q2, w3 = cr[k] * q3;
+        const float4* node = F + (size_t)((k * nq4 + mb + (k < r ? 1 : 0)) * TT_NF);
 #pragma unroll
         for (int f = 0; f < TT_NF; ++f) {
           const float4 v = node[f];
@@ -256,8 +288,8 @@ struct TTbar {
       // bilinear on rows (j, j+1): staged rows 1, 2 of four, or 0, 1 of two
       const float tb = qw[4];
       const float w00 = (1.f - t) * (1.f - tb), w01 = t * (1.f - tb), w10 = (1.f - t) * tb, w11 = t * tb;
-      const float4* n0 = F + (size_t)i * TT_NF;
-      const float4* n1 = F + (size_t)(i + 1) * TT_NF;
+      const float4* n0 = F + node_off(i);
+      const float4* n1 = F + node_off(i + 1);
       const bool four = c.n_rows == 4;
 #pragma unroll
       for (int f = 0; f < TT_NF; ++f) {
@@ -283,15 +315,20 @@ struct TTbar {
     const float w3 = (float)(1.0 - x[2]);          // 1 - u3
     const float u3 = (float)x[2];
     const float vf = (float)v;
-    const float rho = expf(-vf);
+    // v <= L0 (about 7.3 at 13 TeV): exp through the hardware exp2 loses at
+    // most |v| 2^-24 relative, well inside the FP32 integrand's tolerance;
+    // expm1 keeps full precision where beta -> 0.  Reciprocals use the
+    // hardware rcp (1 ulp).
+    const float rho = __expf(-vf);
     const float beta = sqrtf(-expm1f(-vf));
-    const float omb = rho / (1.f + beta);          // 1 - beta
+    const float omb = rho * __builtin_amdgcn_rcpf(1.f + beta);  // 1 - beta
     const float tau1 = 0.5f * (omb + 2.f * beta * w3);
     const float tau2 = 0.5f * (omb + 2.f * beta * u3);
     const float t12 = tau1 * tau2;
+    const float r12 = __builtin_amdgcn_rcpf(t12);
     const float ss = fmaf(tau1, tau1, tau2 * tau2);
     const float m_qq = c.g4 * (4.f / 9.f) * fmaf(0.5f, rho, ss);
-    const float m_gg = c.g4 * (1.f / (6.f * t12) - 0.375f) * (ss + rho - rho * rho / (4.f * t12));
+    const float m_gg = c.g4 * fmaf(r12, 1.f / 6.f, -0.375f) * (ss + rho - 0.25f * rho * rho * r12);
     float f1[TT_NF], f2[TT_NF];
     pdf_at(a1, f1);
     pdf_at(a2, f2);
@@ -299,7 +336,7 @@ struct TTbar {
     float lum_qq = 0.f;
 #pragma unroll
     for (int q = 6; q < 11; ++q) lum_qq = fmaf(f1[q], f2[10 - q], fmaf(f1[10 - q], f2[q], lum_qq));
-    const float inv_tau = expf((float)ltau);
+    const float inv_tau = __expf((float)ltau);
     const float jac = (float)(c.L0 * ltau);
     return (double)(c.pref * jac * beta * inv_tau * fmaf(lum_gg, m_gg, lum_qq * m_qq));
   }

@@ -161,11 +161,23 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const double* __restrict__ pa
   ss[grp][cl] = acc.s;
   sc[grp][cl] = acc.c;
   __syncthreads();
+  // pairwise merge of the row groups' compensated sums, in a fixed tree
+  for (int h = RGROUPS / 2; h > 0; h >>= 1) {
+    if (grp < h) {
+      Comp t;
+      t.s = ss[grp][cl];
+      t.c = sc[grp][cl];
+      t.add(ss[grp + h][cl]);
+      t.c += sc[grp + h][cl];
+      ss[grp][cl] = t.s;
+      sc[grp][cl] = t.c;
+    }
+    __syncthreads();
+  }
   if (threadIdx.x < RCOLS) {
-    Comp t;
-    for (int g = 0; g < RGROUPS; ++g) { t.add(ss[g][cl]); t.add(sc[g][cl]); }
-    ss[0][cl] = t.value();
-    if (col >= 4 && col < ncols) hist_out[col - 4] = t.value();
+    const double v = ss[0][cl] + sc[0][cl];
+    ss[0][cl] = v;
+    if (col >= 4 && col < ncols) hist_out[col - 4] = v;
   }
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -212,7 +224,22 @@ using namespace vgx;
 namespace {
 
 size_t extra_lds_bytes(const vgx_vegas* v) {
-  return v->kind == VGX_TTBAR ? sizeof(float) * (size_t)ttbar_lds_floats(v->tt.n_x) : 0;
+  return v->kind == VGX_TTBAR ? sizeof(float) * (size_t)ttbar_lds_floats(v->tt.nxs) : 0;
+}
+
+// Resident workgroups per CU of the t tbar iteration kernel (its LDS
+// footprint and registers decide); one grid-stride wave of workgroups fills
+// the chip.
+int ttbar_blocks_per_cu(const vgx_vegas* v) {
+  int occ = 0;
+  const size_t lds = sizeof(double) * (size_t)lds_table_offset(3, v->nb, true) + extra_lds_bytes(v);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &occ, reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>), BLOCK, lds);
+  if (e != hipSuccess || occ < 1) {
+    (void)hipGetLastError();
+    occ = 4;
+  }
+  return occ > 8 ? 8 : occ;
 }
 
 int grid_for(const vgx_vegas* v, int64_t n) {
@@ -285,6 +312,15 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
       t.lx = pdf->lx;
       t.lq2 = pdf->lq2;
       t.n_x = pdf->n_x;
+      // ln x1, ln x2 >= ln tau0 for every event; stage from two cells below
+      // the cell of ln tau0 (margin for FP32 rounding of ln x)
+      {
+        const double* hx = pdf->h_x;
+        int i0 = 0;
+        while (i0 < pdf->n_x - 2 && hx[i0 + 1] <= tau0) ++i0;
+        t.ix0 = i0 >= 2 ? i0 - 2 : 0;
+        t.nxs = pdf->n_x - t.ix0;
+      }
       t.j_local = j;
       t.nq_sub = nq;
       t.q_off = pdf->q_off[sub];
@@ -499,7 +535,7 @@ extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_veg
   v->stream_id = c->stream_id;
   vgx_status s = prepare_params(v, c);
   if (s != VGX_OK) { delete v; return s; }
-  v->max_wg = device_cus() * (c->kind == VGX_TTBAR ? 4 : 8);
+  v->max_wg = device_cus() * (c->kind == VGX_TTBAR ? ttbar_blocks_per_cu(v) : 8);
   v->pstride = 4 + v->dim * v->nb;
   const size_t ne = (size_t)v->dim * (v->nb + 1);
   do {
