@@ -1,10 +1,11 @@
-"""Workload constants of the five synthetic configurations.
+"""Workload constants of the synthetic configurations.
 
 C0  plain VEGAS on a d=4 normalised Gaussian product (FP64 integrand).
 C1  log-bicubic PDF interpolation alone on a synthetic 11-flavour grid.
 C2  LO pp -> t tbar at sqrt(s) = 13 TeV, 3-d (tau, y, cos theta*) integrand.
 C3  64 independent integrals of uneven dimension and sample count, batched.
 C4  coupling-flow proposal trained on VEGAS samples, compared with VEGAS.
+C5  LO Drell-Yan (gamma*/Z -> l+ l-) at sqrt(s) = 13 TeV on the C2 path.
 """
 
 # Flavour order of every PDF array: PDG ids -5..-1, gluon (21), 1..5.
@@ -58,4 +59,17 @@ C4 = dict(
     beta1=0.9, beta2=0.999, eps=1e-8,
     seed=4,
     gauss_dim=8, gauss_sigma=0.05, gauss_centre=0.5,
+)
+
+# LO Drell-Yan, q qbar -> gamma*/Z -> l+ l- (massless leptons), on the same
+# fused path as C2: 3-d (tau, y, cos theta*) over a dilepton-mass window,
+# PDFs at the fixed scale mu = M_Z.  Electroweak inputs: fixed alpha(M_Z),
+# on-shell sin^2 theta_W, Z mass and width.
+C5 = dict(
+    name="drell-yan-lo-13tev",
+    dim=3, n_bins=50, alpha=1.5, iterations=10, n_per_iter=10_000_000,
+    seed=5, stream=0,
+    sqrt_s=13000.0, m_lo=60.0, m_hi=120.0,
+    m_z=91.1876, gamma_z=2.4952, sw2=0.2312, alpha_em=1.0 / 128.0,
+    gev2_to_pb=3.893793721e8,
 )
