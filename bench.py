@@ -327,29 +327,48 @@ def extra_gauss(vgx):
     return out
 
 
-def extra_ttbar_contracted(vgx, pdf, params, n):
-    """The same t tbar iteration with the Q^2 direction of the PDF stencil
-    contracted once per workgroup at the fixed scale (mode 1)."""
-    import numpy as np
+def extra_hadronic(vgx, pdf, kind, params, seed, n, k=10):
+    """k GPU-resident iterations of n events of a fused hadronic integrand
+    after 3 adaptation iterations: events/s and the fused kernel's time."""
+    import torch
     from synth import C2
-    p = np.concatenate([params, [1.0]])
-    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], C2["seed"], 0, vgx.F32, p, pdf=pdf)
+    v = vgx.vegas_create(kind, 3, C2["n_bins"], C2["alpha"], seed, 0, vgx.F32, params, pdf=pdf)
     try:
         for it in range(3):
             vgx.vegas_iterate(v, n, it)
             vgx.vegas_refine(v)
+        torch.cuda.synchronize()
         vgx.vegas_set_timing(v, True)
         t0 = time.perf_counter()
-        k = 10
         for it in range(k):
-            vgx.vegas_iterate(v, n, 3 + it)
+            vgx.vegas_iterate_async(v, n, 3 + it)
             vgx.vegas_refine(v)
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ms, launches = vgx.vegas_kernel_time(v)
         r = vgx.vegas_result(v)
         return {"events_per_s": n * k / dt, "kernel_ms": ms / launches, "mean_pb": r["mean"], "sigma_pb": r["sigma"]}
     finally:
         vgx.vegas_destroy(v)
+
+
+def extra_ttbar_contracted(vgx, pdf, params, n):
+    """The same t tbar iteration with the Q^2 direction of the PDF stencil
+    contracted once per workgroup at the fixed scale (mode 1)."""
+    import numpy as np
+    from synth import C2
+    return extra_hadronic(vgx, pdf, vgx.TTBAR, np.concatenate([params, [1.0]]), C2["seed"], n)
+
+
+def extra_drellyan(vgx, pdf, n):
+    """LO Drell-Yan (photon/Z -> l+ l-, 60 < m_ll < 120 GeV) on the same fused
+    path: full stencil (mode 0) and fixed-scale contraction (mode 1)."""
+    import numpy as np
+    from synth import C5
+    p = np.array([C5["sqrt_s"], C5["m_lo"], C5["m_hi"], C5["m_z"], C5["gamma_z"], C5["sw2"], C5["alpha_em"],
+                  C5["gev2_to_pb"]])
+    return {f"mode{m}": extra_hadronic(vgx, pdf, vgx.DRELLYAN, np.concatenate([p, [float(m)]]), C5["seed"], n)
+            for m in (0, 1)}
 
 
 def extra_batch(vgx):
@@ -483,6 +502,7 @@ def main():
             out["time_to_1e-4"]["gauss8"] = {"vegas": gv, "flow": gf}
     if args.extras:
         out["extras"] = {"ttbar_fixed_scale_contraction": extra_ttbar_contracted(vgx, pdf, params, n),
+                         "drell_yan_1e7": extra_drellyan(vgx, pdf, n),
                          "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
                          "batched_64": extra_batch(vgx)}
     if not args.no_cpu:

@@ -70,7 +70,7 @@ enum {
   VGX_GENZ_OSC = 1,   /* cos(2 pi w_1 + sum c_j x_j).  params = [w_1, c_0..] */
   VGX_GENZ_PEAK = 2,  /* prod (c_j^-2 + (x_j - w_j)^2)^-1.
                          params = [w_0..w_{d-1}, c_0..c_{d-1}]               */
-  VGX_TTBAR = 3       /* LO pp -> t tbar, d = 3, (tau, y, cos theta*) map.
+  VGX_TTBAR = 3,      /* LO pp -> t tbar, d = 3, (tau, y, cos theta*) map.
                          params = [sqrt_s, m_top, alpha_s, gev2_to_pb(, mode)];
                          needs a PDF context, evaluated at mu^2 = m_top^2.
                          mode 0 (default): the full log-bicubic stencil in
@@ -79,6 +79,15 @@ enum {
                          contracted once per workgroup and each event does
                          the ln x direction only (same interpolant, FP32
                          rounding differs)                                    */
+  VGX_DRELLYAN = 4    /* LO pp -> photon or Z -> l+ l- (massless leptons), d = 3,
+                         (tau, y, cos theta*) map over the dilepton-mass
+                         window m_lo < m_ll < m_hi.
+                         params = [sqrt_s, m_lo, m_hi, m_z, gamma_z, sin2w,
+                         alpha, gev2_to_pb(, mode)]; needs a PDF context,
+                         evaluated at mu^2 = m_z^2; mode as for VGX_TTBAR.
+                         Thesis: master formula (MadFlow chapter) and
+                         factorisation (PDF chapter); the gamma + Z helicity
+                         amplitudes are textbook electroweak theory         */
 };
 enum { VGX_F64 = 0, VGX_F32 = 1 };   /* integrand / output precision          */
 
@@ -134,8 +143,9 @@ void pdf_destroy(vgx_pdf* pdf);
 typedef struct vgx_vegas vgx_vegas;
 
 typedef struct {
-  int32_t kind;             /* VGX_GAUSS, VGX_GENZ_OSC, VGX_GENZ_PEAK, VGX_TTBAR */
-  int32_t dim;              /* 1 .. VGX_MAX_DIM (3 for VGX_TTBAR)               */
+  int32_t kind;             /* VGX_GAUSS, VGX_GENZ_OSC, VGX_GENZ_PEAK, VGX_TTBAR,
+                               VGX_DRELLYAN                                     */
+  int32_t dim;              /* 1 .. VGX_MAX_DIM (3 for VGX_TTBAR, VGX_DRELLYAN) */
   int32_t n_bins;           /* bins per dimension, 2 .. VGX_MAX_BINS            */
   double alpha;             /* refinement damping exponent (e.g. 1.5)           */
   uint64_t seed;            /* Philox key                                       */
@@ -143,7 +153,8 @@ typedef struct {
   int32_t prec;             /* VGX_F64 or VGX_F32 integrand arithmetic          */
   const double* params;     /* host, integrand parameters (see the kinds)       */
   int32_t n_params;
-  const vgx_pdf* pdf;       /* VGX_TTBAR only; must outlive the context         */
+  const vgx_pdf* pdf;       /* VGX_TTBAR, VGX_DRELLYAN only; must outlive the
+                               context                                          */
 } vgx_vegas_cfg;
 
 typedef struct {
@@ -218,7 +229,7 @@ void vegas_destroy(vgx_vegas* v);
 /* ------------------------------------------------------------------------ */
 typedef struct vgx_batch vgx_batch;
 
-/* Bundle contexts (all on one device, non-TTBAR) into a batch.  The batch
+/* Bundle contexts (all on one device, no TTBAR or DRELLYAN) into a batch.  The batch
  * captures one iteration (persistent kernel + reductions + refinement) in
  * a HIP graph on first use.  tile = samples per work item (0: autotuned),
  * block = threads per workgroup (0: autotuned). */

@@ -21,288 +21,32 @@
 //   1 - beta cos = (1 - beta) + 2 beta (1 - x3),  1 + beta cos = (1 - beta) + 2 beta x3,
 //   1 - beta = rho/(1 + beta),  ln x_{1,2} = +/- y - l_tau/2  (no log needed).
 //
-// PDF lookup at the fixed scale mu^2 = m_t^2: the four Q^2 rows j-1..j+2
-// around mu^2 (two rows if the Q stencil is incomplete) are staged in LDS as
-// FP32 [node][flav][row] (one 16-byte read per node and flavour), the nodes
-// grouped by (node mod 4): step k of the 4-node stencil reads, in every
-// lane, the stencil node congruent to k mod 4, so lanes whose cells lie
-// close together read one address (a broadcast) and lanes further apart
-// fall on distinct banks (consecutive groups of four nodes are 11 x 16 bytes
-// apart, an odd multiple of 16 bytes); per event
-// and per x the cubic Hermite (secant
-// slopes) in ln x and then in ln Q^2 is evaluated for all 11 flavours, as a
-// 4x4 weighted sum w_rk = q_r c_k of the stencil (same linear function as
-// the Hermite-with-slopes formula).  Bilinear where the stencil is
-// incomplete.  Flavour order: -5..-1, g, 1..5.
+// PDF lookup: PdfRows (pdf_rows.h) at the fixed scale mu^2 = m_t^2.
 #pragma once
 
 #include "common.h"
-#include "pdf_internal.h"
+#include "pdf_rows.h"
 
 namespace vgx {
-
-constexpr int TT_NF = 11;
-constexpr int TT_MAX_NX = 256;
 
 struct TTbarConst {
   // kinematics (FP64, set on the host from sqrt_s, m_t, alpha_s, conv)
   double L0;        // ln(1/tau0)
   float pref;       // 2 conv / (32 pi s)
   float g4;         // (4 pi alpha_s)^2
-  // PDF staging
-  const float* v32; // device [iq][ix][fstride] FP32 grid
-  int fstride;
-  const double* lx; // device ln x knots
-  const double* lq2;// device ln Q^2 knots (all subgrids)
-  int n_x;          // x knots of the grid
-  int ix0;          // first staged x node: events never reach ln x < ln tau0,
-                    // so nodes below the cell of ln tau0 (less a margin of two
-                    // cells) are not staged
-  int nxs;          // staged x nodes, n_x - ix0
-  int row0;         // global index of the first staged Q^2 row
-  int n_rows;       // 4 (bicubic in Q) or 2 (bilinear in Q)
-  int j_local;      // cell index of mu^2 inside its subgrid
-  int nq_sub;       // knots in that subgrid
-  int q_off;        // global knot offset of the subgrid
-  double lmu2;      // ln mu^2
-  int contract;     // 1: Q^2 direction contracted once per workgroup
+  PdfRowsConst pdf; // PDF rows at mu^2 = m_t^2, staged from x >= tau0
 };
 
-// LDS footprint in floats for nxs staged x nodes: node values, padded to a
-// multiple of 4 nodes, [4][nxs/4][11][4 rows] (16-byte aligned float4 per
-// node and flavour), ln x knots, inverse spacings, Q weights and the
-// cell-guess constants.
-__host__ __device__ inline int ttbar_lds_floats(int nxs) {
-  return ((nxs + 3) & ~3) * 4 * TT_NF + 2 * nxs + 16;
-}
+__host__ __device__ inline int ttbar_lds_floats(int nxs) { return pdf_rows_lds_floats(nxs); }
 
 struct TTbar {
   static constexpr bool kStage = true;
   TTbarConst c;
-  // LDS tables are indexed by the staged node k = ix - ix0
-  const float4* F;  // LDS [4][nq4][11] float4: the (up to) four Q^2 rows of one node and flavour
-  int nq4;          // staged nodes per residue class mod 4
-  float* sa;        // LDS ln x knots [nxs]
-  float* sinv;      // LDS 1/(a_{k+1} - a_k) [nxs]
-  float* qw;        // LDS [0..3] Q-row Hermite weights, [4] bilinear t_b, [5] a_0, [6] 1/da, [7] uniform flag
+  PdfRows P;
 
   __device__ void stage(float* lds) {
-    float* Fs = lds;
-    F = (const float4*)lds;
-    const int nxs = c.nxs;
-    nq4 = (nxs + 3) >> 2;
-    sa = Fs + nq4 * 4 * 4 * TT_NF;
-    sinv = sa + nxs;
-    qw = sinv + nxs;
-    const int nr = c.n_rows;
-    const int tot = nq4 * 4 * TT_NF * 4;
-    const double* lx = c.lx + c.ix0;
-    for (int k = threadIdx.x; k < tot; k += blockDim.x) {
-      const int r = k & 3;
-      const int f = (k >> 2) % TT_NF;
-      const int pos = (k >> 2) / TT_NF;            // (n mod 4) nq4 + n / 4
-      const int n = (pos % nq4) * 4 + pos / nq4;   // staged node
-      Fs[k] = (r < nr && n < nxs) ? c.v32[((size_t)(c.row0 + r) * c.n_x + c.ix0 + n) * c.fstride + f] : 0.0f;
-    }
-    for (int k = threadIdx.x; k < nxs; k += blockDim.x) {
-      sa[k] = (float)lx[k];
-      sinv[k] = k + 1 < nxs ? (float)(1.0 / (lx[k + 1] - lx[k])) : 0.0f;
-    }
-    if (threadIdx.x == 0) {
-      // weights of the Q rows at mu^2 (FP64 setup, FP32 storage)
-      const double* lq = c.lq2 + c.q_off;
-      const int j = c.j_local;
-      const double hb = lq[j + 1] - lq[j];
-      const double t = (c.lmu2 - lq[j]) / hb;
-      if (c.n_rows == 4) {
-        const double rm = hb / (lq[j] - lq[j - 1]), rp = hb / (lq[j + 2] - lq[j + 1]);
-        const double t2 = t * t, t3 = t2 * t;
-        const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
-        qw[0] = (float)(-0.5 * h10 * rm);
-        qw[1] = (float)(h00 - 0.5 * h10 + 0.5 * h10 * rm - 0.5 * h11);
-        qw[2] = (float)(h01 + 0.5 * h10 - 0.5 * h11 * rp + 0.5 * h11);
-        qw[3] = (float)(0.5 * h11 * rp);
-      } else {
-        qw[0] = (float)(1.0 - t);
-        qw[1] = (float)t;
-        qw[2] = 0.0f;
-        qw[3] = 0.0f;
-      }
-      qw[4] = (float)t;  // linear weight in ln Q^2 for the bilinear fallback
-      // cell guess for knots uniform in ln x (checked here; else binary search)
-      const int n = nxs;
-      const double a0 = lx[0], da = (lx[n - 1] - lx[0]) / (n - 1);
-      bool uni = true;
-      for (int k = 0; k < n; ++k)
-        if (fabs(lx[k] - (a0 + k * da)) > 1e-3 * da) uni = false;
-      qw[5] = (float)a0;
-      qw[6] = (float)(1.0 / da);
-      qw[7] = uni ? 1.0f : 0.0f;
-    }
-    if (c.contract) {
-      // fixed scale: contract the Q^2 direction once.  P[ix][f] with the
-      // Hermite Q weights (cells with the full stencil) and Pl[ix][f] with the
-      // linear weights (bilinear cells), each node 12 floats (3 x float4).
-      // The node values occupy F; the tables are built in registers first.
-      __syncthreads();
-      float pv[2][(TT_MAX_NX * 12 + 255) / 256];
-      const int tot12 = nxs * 12;
-      int q = 0;
-      for (int k = threadIdx.x; k < tot12; k += blockDim.x, ++q) {
-        const int f = k % 12, ix = k / 12;
-        float hp = 0.f, lp = 0.f;
-        if (f < TT_NF) {
-          const float4 v = F[node_off(ix) + f];
-          hp = fmaf(qw[0], v.x, fmaf(qw[1], v.y, fmaf(qw[2], v.z, qw[3] * v.w)));
-          const float tb = qw[4];
-          lp = c.n_rows == 4 ? fmaf(tb, v.z - v.y, v.y) : fmaf(tb, v.y - v.x, v.x);
-        }
-        pv[0][q] = hp;
-        pv[1][q] = lp;
-      }
-      __syncthreads();
-      float* P = lds;
-      q = 0;
-      for (int k = threadIdx.x; k < tot12; k += blockDim.x, ++q) {
-        P[k] = pv[0][q];
-        P[tot12 + k] = pv[1][q];
-      }
-    }
-  }
-
-  // float4 offset of staged node n in F
-  __device__ __forceinline__ int node_off(int n) const { return ((n & 3) * nq4 + (n >> 2)) * TT_NF; }
-
-  // staged cell k with sa[k] <= a < sa[k+1], clamped to [k_lo, nxs - 2];
-  // k_lo = 1 when nodes below the staged range exist (never reached by
-  // events: it only keeps the stencil's node k - 1 inside the table)
-  __device__ __forceinline__ int cell(float a) const {
-    const int nx = c.nxs;
-    const int klo = c.ix0 > 0 ? 1 : 0;
-    if (qw[7] != 0.0f) {
-      // guess from the uniform spacing, then settle on the stored knots
-      // (the same cell as a binary search over sa)
-      int i = (int)((a - qw[5]) * qw[6]);
-      i = i < klo ? klo : (i > nx - 2 ? nx - 2 : i);
-      while (i > klo && a < sa[i]) --i;
-      while (i < nx - 2 && a >= sa[i + 1]) ++i;
-      return i;
-    }
-    int lo = 0, hi = nx - 1;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (sa[mid] <= a) lo = mid; else hi = mid;
-    }
-    return lo > klo ? lo : klo;
-  }
-
-  // xf of all flavours at ln x = a, fixed-scale contracted tables.
-  __device__ __forceinline__ void pdf_at_contracted(int i, float t, float (&xf)[TT_NF]) const {
-    const int nx = c.nxs;
-    const float4* P = F;                    // [ix][3] float4: Hermite-in-Q contraction
-    const float4* Pl = F + (size_t)nx * 3;  // [ix][3] float4: linear-in-Q contraction
-    float v[12];
-    if (c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3) {
-      const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
-      const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
-      const float t2 = t * t, t3 = t2 * t;
-      const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
-      const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
-      float cx[4];
-      cx[0] = -0.5f * h10 * rm;
-      cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
-      cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
-      cx[3] = 0.5f * h11 * rp;
-#pragma unroll
-      for (int f = 0; f < 12; ++f) v[f] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float4* node = P + (size_t)(i - 1 + k) * 3;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const float4 u = node[m];
-          v[4 * m] = fmaf(cx[k], u.x, v[4 * m]);
-          v[4 * m + 1] = fmaf(cx[k], u.y, v[4 * m + 1]);
-          v[4 * m + 2] = fmaf(cx[k], u.z, v[4 * m + 2]);
-          v[4 * m + 3] = fmaf(cx[k], u.w, v[4 * m + 3]);
-        }
-      }
-    } else {
-      const float4* n0 = Pl + (size_t)i * 3;
-      const float4* n1 = Pl + (size_t)(i + 1) * 3;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const float4 a0 = n0[m], a1 = n1[m];
-        v[4 * m] = fmaf(t, a1.x - a0.x, a0.x);
-        v[4 * m + 1] = fmaf(t, a1.y - a0.y, a0.y);
-        v[4 * m + 2] = fmaf(t, a1.z - a0.z, a0.z);
-        v[4 * m + 3] = fmaf(t, a1.w - a0.w, a0.w);
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < TT_NF; ++f) xf[f] = v[f];
-  }
-
-  // xf of all flavours at ln x = a (a <= 0).
-  __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
-    const int nx = c.nxs;
-    const int i = cell(a);
-    const float t = (a - sa[i]) * sinv[i];
-    if (c.contract) {
-      pdf_at_contracted(i, t, xf);
-      return;
-    }
-    if (c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3) {
-      const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
-      const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
-      const float t2 = t * t, t3 = t2 * t;
-      const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
-      const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
-      float cx[4];
-      cx[0] = -0.5f * h10 * rm;
-      cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
-      cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
-      cx[3] = 0.5f * h11 * rp;
-      const float q0 = qw[0], q1 = qw[1], q2 = qw[2], q3 = qw[3];
-      // step k visits the stencil node n_k = congruent to k mod 4 in
-      // [i-1, i+2]: n_k = 4 mb + k + 4 [k < r] with i-1 = 4 mb + r, weight
-      // cx[(k - r) mod 4]
-      const int base = i - 1, r = base & 3, mb = base >> 2;
-      const bool o1 = r & 1, o2 = r & 2;
-      const float d0 = o1 ? cx[3] : cx[0], d1 = o1 ? cx[0] : cx[1];
-      const float d2 = o1 ? cx[1] : cx[2], d3 = o1 ? cx[2] : cx[3];
-      const float cr[4] = {o2 ? d2 : d0, o2 ? d3 : d1, o2 ? d0 : d2, o2 ? d1 : d3};
-#pragma unroll
-      for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float w0 = cr[k] * q0, w1 = cr[k] * q1, w2 = cr[k] * q2, w3 = cr[k] * q3;
-        const float4* node = F + (size_t)((k * nq4 + mb + (k < r ? 1 : 0)) * TT_NF);
-#pragma unroll
-        for (int f = 0; f < TT_NF; ++f) {
-          const float4 v = node[f];
-          xf[f] = fmaf(w0, v.x, fmaf(w1, v.y, fmaf(w2, v.z, fmaf(w3, v.w, xf[f]))));
-        }
-      }
-    } else {
-      // bilinear on rows (j, j+1): staged rows 1, 2 of four, or 0, 1 of two
-      const float tb = qw[4];
-      const float w00 = (1.f - t) * (1.f - tb), w01 = t * (1.f - tb), w10 = (1.f - t) * tb, w11 = t * tb;
-      const float4* n0 = F + node_off(i);
-      const float4* n1 = F + node_off(i + 1);
-      const bool four = c.n_rows == 4;
-#pragma unroll
-      for (int f = 0; f < TT_NF; ++f) {
-        const float4 a0 = n0[f], a1 = n1[f];
-        const float lo0 = four ? a0.y : a0.x, hi0 = four ? a0.z : a0.y;
-        const float lo1 = four ? a1.y : a1.x, hi1 = four ? a1.z : a1.y;
-        float v = w00 * lo0;
-        v = fmaf(w01, lo1, v);
-        v = fmaf(w10, hi0, v);
-        v = fmaf(w11, hi1, v);
-        xf[f] = v;
-      }
-    }
+    P.c = c.pdf;
+    P.stage(lds);
   }
 
   __device__ __forceinline__ double eval(const double (&x)[3]) const {
@@ -330,8 +74,8 @@ struct TTbar {
     const float m_qq = c.g4 * (4.f / 9.f) * fmaf(0.5f, rho, ss);
     const float m_gg = c.g4 * fmaf(r12, 1.f / 6.f, -0.375f) * (ss + rho - 0.25f * rho * rho * r12);
     float f1[TT_NF], f2[TT_NF];
-    pdf_at(a1, f1);
-    pdf_at(a2, f2);
+    P.pdf_at(a1, f1);
+    P.pdf_at(a2, f2);
     const float lum_gg = f1[5] * f2[5];
     float lum_qq = 0.f;
 #pragma unroll

@@ -27,6 +27,7 @@
 #include "integrands.h"
 #include "pdf_internal.h"
 #include "ttbar.h"
+#include "drellyan.h"
 #include "vegas_internal.h"
 
 #include <math.h>
@@ -223,18 +224,23 @@ using namespace vgx;
 
 namespace {
 
+bool uses_pdf(int kind) { return kind == VGX_TTBAR || kind == VGX_DRELLYAN; }
+
 size_t extra_lds_bytes(const vgx_vegas* v) {
-  return v->kind == VGX_TTBAR ? sizeof(float) * (size_t)ttbar_lds_floats(v->tt.nxs) : 0;
+  if (v->kind == VGX_TTBAR) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->tt.pdf.nxs);
+  if (v->kind == VGX_DRELLYAN) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->dy.pdf.nxs);
+  return 0;
 }
 
-// Resident workgroups per CU of the t tbar iteration kernel (its LDS
-// footprint and registers decide); one grid-stride wave of workgroups fills
-// the chip.
-int ttbar_blocks_per_cu(const vgx_vegas* v) {
+// Resident workgroups per CU of a hadronic integrand's iteration kernel (its
+// LDS footprint and registers decide); one grid-stride wave of workgroups
+// fills the chip.
+int hadronic_blocks_per_cu(const vgx_vegas* v) {
   int occ = 0;
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(3, v->nb, true) + extra_lds_bytes(v);
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &occ, reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>), BLOCK, lds);
+  const void* k = v->kind == VGX_TTBAR ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>)
+                                       : reinterpret_cast<const void*>(&k_vegas_iter<3, DrellYan, PhiloxSrc<3>, true>);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, BLOCK, lds);
   if (e != hipSuccess || occ < 1) {
     (void)hipGetLastError();
     occ = 4;
@@ -245,6 +251,45 @@ int ttbar_blocks_per_cu(const vgx_vegas* v) {
 int grid_for(const vgx_vegas* v, int64_t n) {
   const int64_t want = (n + BLOCK - 1) / BLOCK;
   return (int)(want < v->max_wg ? (want > 0 ? want : 1) : v->max_wg);
+}
+
+// PDF rows at the fixed scale mu2 for an integrand whose momentum fractions
+// never fall below x_min.
+vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, double x_min, bool contract,
+                          const char* who) {
+  VGX_CHECK(pdf->n_flav == TT_NF, "%s needs an 11-flavour PDF (order -5..-1, g, 1..5)", who);
+  VGX_CHECK(pdf->n_x <= TT_MAX_NX, "%s supports at most %d x knots", who, TT_MAX_NX);
+  VGX_CHECK(x_min >= pdf->h_x[0], "%s: smallest momentum fraction below the PDF x range", who);
+  int sub = -1;
+  for (int k = 0; k < pdf->n_sub; ++k) {
+    const double lo = pdf->h_q2[pdf->q_off[k]], hi = pdf->h_q2[pdf->q_off[k] + pdf->nq[k] - 1];
+    const bool last = k == pdf->n_sub - 1;
+    if (mu2 >= lo && (mu2 < hi || (last && mu2 <= hi))) sub = k;
+  }
+  VGX_CHECK(sub >= 0, "%s: mu^2 outside the PDF Q^2 range", who);
+  const double* q = pdf->h_q2 + pdf->q_off[sub];
+  const int nq = pdf->nq[sub];
+  int j = 0;
+  while (j < nq - 2 && q[j + 1] <= mu2) ++j;
+  t.v32 = pdf->v32;
+  t.fstride = pdf->fstride;
+  t.lx = pdf->lx;
+  t.lq2 = pdf->lq2;
+  t.n_x = pdf->n_x;
+  // every event has ln x >= ln x_min; stage from two cells below the cell of
+  // x_min (margin for FP32 rounding of ln x)
+  int i0 = 0;
+  while (i0 < pdf->n_x - 2 && pdf->h_x[i0 + 1] <= x_min) ++i0;
+  t.ix0 = i0 >= 2 ? i0 - 2 : 0;
+  t.nxs = pdf->n_x - t.ix0;
+  t.j_local = j;
+  t.nq_sub = nq;
+  t.q_off = pdf->q_off[sub];
+  t.lmu2 = log(mu2);
+  if (j >= 1 && j <= nq - 3) { t.n_rows = 4; t.row0 = pdf->q_off[sub] + j - 1; }
+  else { t.n_rows = 2; t.row0 = pdf->q_off[sub] + j; }
+  t.contract = contract ? 1 : 0;
+  return VGX_OK;
 }
 
 // Build the device-side integrand parameters from the user's parameters.
@@ -283,53 +328,56 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
       VGX_CHECK(d == 3, "TTBAR needs dim 3");
       VGX_CHECK(c->n_params >= 4, "TTBAR needs [sqrt_s, m_top, alpha_s, gev2_to_pb]");
       VGX_CHECK(c->pdf, "TTBAR needs a PDF context");
-      const vgx_pdf* pdf = c->pdf;
-      VGX_CHECK(pdf->n_flav == TT_NF, "TTBAR needs an 11-flavour PDF (order -5..-1, g, 1..5)");
-      VGX_CHECK(pdf->n_x <= TT_MAX_NX, "TTBAR supports at most %d x knots", TT_MAX_NX);
       const double rs = c->params[0], mt = c->params[1], as = c->params[2], conv = c->params[3];
       VGX_CHECK(rs > 2.0 * mt && mt > 0.0 && as > 0.0, "TTBAR: need sqrt_s > 2 m_top > 0");
       const double s = rs * rs;
       const double tau0 = 4.0 * mt * mt / s;
-      VGX_CHECK(tau0 >= pdf->h_x[0], "TTBAR: tau0 below the PDF x range");
-      const double mu2 = mt * mt;
-      int sub = -1;
-      for (int k = 0; k < pdf->n_sub; ++k) {
-        const double lo = pdf->h_q2[pdf->q_off[k]], hi = pdf->h_q2[pdf->q_off[k] + pdf->nq[k] - 1];
-        const bool last = k == pdf->n_sub - 1;
-        if (mu2 >= lo && (mu2 < hi || (last && mu2 <= hi))) sub = k;
-      }
-      VGX_CHECK(sub >= 0, "TTBAR: mu^2 = m_top^2 outside the PDF Q^2 range");
-      const double* q = pdf->h_q2 + pdf->q_off[sub];
-      const int nq = pdf->nq[sub];
-      int j = 0;
-      while (j < nq - 2 && q[j + 1] <= mu2) ++j;
+      const double mode = c->n_params >= 5 ? c->params[4] : 0.0;
+      VGX_CHECK(mode == 0.0 || mode == 1.0, "TTBAR mode must be 0 (full stencil) or 1 (fixed-scale contraction)");
       TTbarConst& t = v->tt;
+      VGX_TRY(setup_pdf_rows(t.pdf, c->pdf, mt * mt, tau0, mode == 1.0, "TTBAR"));
       t.L0 = log(1.0 / tau0);
       t.pref = (float)(2.0 * conv / (32.0 * M_PI * s));
       t.g4 = (float)((4.0 * M_PI * as) * (4.0 * M_PI * as));
-      t.v32 = pdf->v32;
-      t.fstride = pdf->fstride;
-      t.lx = pdf->lx;
-      t.lq2 = pdf->lq2;
-      t.n_x = pdf->n_x;
-      // ln x1, ln x2 >= ln tau0 for every event; stage from two cells below
-      // the cell of ln tau0 (margin for FP32 rounding of ln x)
-      {
-        const double* hx = pdf->h_x;
-        int i0 = 0;
-        while (i0 < pdf->n_x - 2 && hx[i0 + 1] <= tau0) ++i0;
-        t.ix0 = i0 >= 2 ? i0 - 2 : 0;
-        t.nxs = pdf->n_x - t.ix0;
+      return VGX_OK;
+    }
+    case VGX_DRELLYAN: {
+      VGX_CHECK(d == 3, "DRELLYAN needs dim 3");
+      VGX_CHECK(c->n_params >= 8,
+                "DRELLYAN needs [sqrt_s, m_lo, m_hi, m_z, gamma_z, sin2w, alpha, gev2_to_pb]");
+      VGX_CHECK(c->pdf, "DRELLYAN needs a PDF context");
+      const double* q = c->params;
+      const double rs = q[0], mlo = q[1], mhi = q[2], mz = q[3], gz = q[4], sw2 = q[5], al = q[6], conv = q[7];
+      VGX_CHECK(mlo > 0.0 && mhi > mlo && mhi < rs, "DRELLYAN: need 0 < m_lo < m_hi < sqrt_s");
+      VGX_CHECK(mz > 0.0 && gz > 0.0 && sw2 > 0.0 && sw2 < 1.0 && al > 0.0, "DRELLYAN: bad electroweak inputs");
+      const double mode = c->n_params >= 9 ? q[8] : 0.0;
+      VGX_CHECK(mode == 0.0 || mode == 1.0, "DRELLYAN mode must be 0 (full stencil) or 1 (fixed-scale contraction)");
+      const double s = rs * rs, tlo = mlo * mlo / s, thi = mhi * mhi / s;
+      DYConst& t = v->dy;
+      VGX_TRY(setup_pdf_rows(t.pdf, c->pdf, mz * mz, tlo, mode == 1.0, "DRELLYAN"));
+      t.Llo = log(1.0 / tlo);
+      t.Lr = log(thi / tlo);
+      t.mlo2 = mlo * mlo;
+      t.mz2d = mz * mz;
+      // F = J/tau conv dsigma/dcos summed: J/tau = 2 Lr ln(1/tau), dsigma/dcos
+      // = (e^4/12) A / (32 pi s_hat)
+      const double e4 = (4.0 * M_PI * al) * (4.0 * M_PI * al);
+      t.pref = (float)(2.0 * t.Lr * conv * e4 / (12.0 * 32.0 * M_PI));
+      t.mg2 = (float)(mz * mz * gz * gz);
+      t.kap = (float)(1.0 / (sw2 * (1.0 - sw2)));
+      // helicity sums: same (LL + RR) and opposite (LR + RL) helicity pairs,
+      // S = a0 + a1 Re chi + a2 |chi|^2, for up- and down-type quarks
+      const double ql = -1.0, gll = -0.5 + sw2, grl = sw2;
+      for (int k = 0; k < 2; ++k) {
+        const double qq = k == 0 ? 2.0 / 3.0 : -1.0 / 3.0, t3 = k == 0 ? 0.5 : -0.5;
+        const double glq = t3 - qq * sw2, grq = -qq * sw2;
+        const double qq2 = qq * ql;
+        t.a0[k] = (float)(2.0 * qq2 * qq2);
+        t.as1[k] = (float)(2.0 * qq2 * (glq * gll + grq * grl));
+        t.as2[k] = (float)(glq * gll * glq * gll + grq * grl * grq * grl);
+        t.ao1[k] = (float)(2.0 * qq2 * (glq * grl + grq * gll));
+        t.ao2[k] = (float)(glq * grl * glq * grl + grq * gll * grq * gll);
       }
-      t.j_local = j;
-      t.nq_sub = nq;
-      t.q_off = pdf->q_off[sub];
-      t.lmu2 = log(mu2);
-      if (j >= 1 && j <= nq - 3) { t.n_rows = 4; t.row0 = pdf->q_off[sub] + j - 1; }
-      else { t.n_rows = 2; t.row0 = pdf->q_off[sub] + j; }
-      const double mode = c->n_params >= 5 ? c->params[4] : 0.0;
-      VGX_CHECK(mode == 0.0 || mode == 1.0, "TTBAR mode must be 0 (full stencil) or 1 (fixed-scale contraction)");
-      t.contract = mode == 1.0 ? 1 : 0;
       return VGX_OK;
     }
     default:
@@ -359,6 +407,15 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
       return launch_iter_f<3, TTbar, Src, HIST>(v, n, f, src);
     }
     set_error("TTBAR needs dim 3");
+    return VGX_EINVAL;
+  }
+  if (v->kind == VGX_DRELLYAN) {
+    if constexpr (D == 3) {
+      DrellYan f{};
+      f.c = v->dy;
+      return launch_iter_f<3, DrellYan, Src, HIST>(v, n, f, src);
+    }
+    set_error("DRELLYAN needs dim 3");
     return VGX_EINVAL;
   }
 #define VGX_LAUNCH_KIND(T)                                                     \
@@ -403,6 +460,15 @@ vgx_status launch_sample_d(vgx_vegas* v, int64_t first, int64_t n, int32_t it, d
       return launch_sample_f<3, TTbar>(v, first, n, it, f, u, g);
     }
     set_error("TTBAR needs dim 3");
+    return VGX_EINVAL;
+  }
+  if (v->kind == VGX_DRELLYAN) {
+    if constexpr (D == 3) {
+      DrellYan f{};
+      f.c = v->dy;
+      return launch_sample_f<3, DrellYan>(v, first, n, it, f, u, g);
+    }
+    set_error("DRELLYAN needs dim 3");
     return VGX_EINVAL;
   }
 #define VGX_SAMPLE_KIND(T)                                                     \
@@ -535,7 +601,7 @@ extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_veg
   v->stream_id = c->stream_id;
   vgx_status s = prepare_params(v, c);
   if (s != VGX_OK) { delete v; return s; }
-  v->max_wg = device_cus() * (c->kind == VGX_TTBAR ? ttbar_blocks_per_cu(v) : 8);
+  v->max_wg = device_cus() * (uses_pdf(c->kind) ? hadronic_blocks_per_cu(v) : 8);
   v->pstride = 4 + v->dim * v->nb;
   const size_t ne = (size_t)v->dim * (v->nb + 1);
   do {

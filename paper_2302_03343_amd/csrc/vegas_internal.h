@@ -7,6 +7,7 @@
 #include "common.h"
 #include "integrands.h"
 #include "ttbar.h"
+#include "drellyan.h"
 
 namespace vgx {
 
@@ -177,6 +178,7 @@ struct vgx_vegas {
   uint32_t stream_id = 0;
   vgx::IntegrandParams prm{};
   vgx::TTbarConst tt{};
+  vgx::DYConst dy{};
   int max_wg = 0;
   int pstride = 0;
   double* edges = nullptr;          // [dim][nb+1]
