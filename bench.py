@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--extras", action="store_true",
                     help="also measure the other workloads (PDF interpolation alone, plain Gaussian VEGAS, "
                          "batched integrals) as extra fields")
+    ap.add_argument("--pdf-only", action="store_true",
+                    help="only the PDF interpolation workload (1e8 queries, FP64 and FP32 outputs); one JSON line")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 2 GiB device copy (reference for scaling HBM counters) and exit")
     return ap.parse_args()
@@ -242,6 +244,19 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
     finally:
         vgx.flow_destroy(f)
         vgx.vegas_destroy(v)
+
+
+def pdf_only():
+    """The PDF interpolation workload alone (for profiling its kernel)."""
+    from paper_2302_03343_amd import vgx
+    from synth import synthetic_pdf_grid
+    grid = synthetic_pdf_grid()
+    pdf = vgx.pdf_create(grid.x_knots, grid.q2_knots, grid.xf)
+    try:
+        print(json.dumps({"workload": "pdf-logbicubic-11flav, 1e8 log-uniform queries",
+                          "pdf_interp_1e8": extra_pdf(vgx, pdf)}), flush=True)
+    finally:
+        vgx.pdf_destroy(pdf)
 
 
 def copy_reference():
@@ -404,6 +419,9 @@ def main():
     args = parse()
     if args.copy_reference:
         copy_reference()
+        return
+    if args.pdf_only:
+        pdf_only()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",

@@ -67,7 +67,8 @@ struct PdfRows {
   int nq4;          // staged nodes per residue class mod 4
   float* sa;        // LDS ln x knots [nxs]
   float* sinv;      // LDS 1/(a_{k+1} - a_k) [nxs]
-  float* qw;        // LDS [0..3] Q-row Hermite weights, [4] bilinear t_b, [5] a_0, [6] 1/da, [7] uniform flag
+  float* qw;        // LDS [0..3] Q-row Hermite weights, [4] bilinear t_b, [5] a_0, [6] 1/da, [7] uniform flag,
+                    // [8..11] linear Q-row weights of the bilinear fallback
 
   __device__ void stage(float* lds) {
     float* Fs = lds;
@@ -122,23 +123,34 @@ struct PdfRows {
       qw[6] = (float)(1.0 / da);
       qw[7] = uni ? 1.0f : 0.0f;
     }
+    if (threadIdx.x == 0) {
+      // linear Q weights on the cell (j, j+1) for the bilinear fallback: rows
+      // 1, 2 of four staged rows, or 0, 1 of two
+      const float tb = qw[4];
+      const bool four = c.n_rows == 4;
+      qw[8] = four ? 0.0f : 1.0f - tb;
+      qw[9] = four ? 1.0f - tb : tb;
+      qw[10] = four ? tb : 0.0f;
+      qw[11] = 0.0f;
+    }
     if (c.contract) {
-      // fixed scale: contract the Q^2 direction once.  P[ix][f] with the
-      // Hermite Q weights (cells with the full stencil) and Pl[ix][f] with the
-      // linear weights (bilinear cells), each node 12 floats (3 x float4).
-      // The node values occupy F; the tables are built in registers first.
+      // fixed scale: contract the Q^2 direction once.  P with the Hermite Q
+      // weights (cells with the full stencil) and Pl with the linear ones
+      // (bilinear cells), 12 floats (3 x float4) per node, nodes grouped by
+      // residue mod 4 like F.  The node values occupy F; the tables are
+      // built in registers first.
       __syncthreads();
       float pv[2][(TT_MAX_NX * 12 + 255) / 256];
-      const int tot12 = nxs * 12;
+      const int tot12 = nq4 * 4 * 12;
       int q = 0;
       for (int k = threadIdx.x; k < tot12; k += blockDim.x, ++q) {
-        const int f = k % 12, ix = k / 12;
+        const int f = k % 12, pos = k / 12;
+        const int n = (pos % nq4) * 4 + pos / nq4;
         float hp = 0.f, lp = 0.f;
-        if (f < TT_NF) {
-          const float4 v = F[node_off(ix) + f];
+        if (f < TT_NF && n < nxs) {
+          const float4 v = F[node_off(n) + f];
           hp = fmaf(qw[0], v.x, fmaf(qw[1], v.y, fmaf(qw[2], v.z, qw[3] * v.w)));
-          const float tb = qw[4];
-          lp = c.n_rows == 4 ? fmaf(tb, v.z - v.y, v.y) : fmaf(tb, v.y - v.x, v.x);
+          lp = fmaf(qw[8], v.x, fmaf(qw[9], v.y, qw[10] * v.z));
         }
         pv[0][q] = hp;
         pv[1][q] = lp;
@@ -179,111 +191,92 @@ struct PdfRows {
     return lo > klo ? lo : klo;
   }
 
-  // xf of all flavours at ln x = a, fixed-scale contracted tables.
-  __device__ __forceinline__ void pdf_at_contracted(int i, float t, float (&xf)[TT_NF]) const {
+  // Stencil window of the cell holding ln x = a: nodes base..base+3 with x
+  // weights w.  full: both axes have their four knots, w is the cubic
+  // Hermite (secant slopes); else the bilinear fallback, expressed as the
+  // same 4-node window with weights (1 - t, t) on the cell's corners and
+  // zeros elsewhere, so that every lane runs one code path.
+  __device__ __forceinline__ void window(float a, int& base, float (&w)[4], bool& full) const {
     const int nx = c.nxs;
-    const float4* P = F;                    // [ix][3] float4: Hermite-in-Q contraction
-    const float4* Pl = F + (size_t)nx * 3;  // [ix][3] float4: linear-in-Q contraction
-    float v[12];
-    if (c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3) {
-      const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
-      const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
-      const float t2 = t * t, t3 = t2 * t;
-      const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
-      const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
-      float cx[4];
-      cx[0] = -0.5f * h10 * rm;
-      cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
-      cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
-      cx[3] = 0.5f * h11 * rp;
-#pragma unroll
-      for (int f = 0; f < 12; ++f) v[f] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float4* node = P + (size_t)(i - 1 + k) * 3;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const float4 u = node[m];
-          v[4 * m] = fmaf(cx[k], u.x, v[4 * m]);
-          v[4 * m + 1] = fmaf(cx[k], u.y, v[4 * m + 1]);
-          v[4 * m + 2] = fmaf(cx[k], u.z, v[4 * m + 2]);
-          v[4 * m + 3] = fmaf(cx[k], u.w, v[4 * m + 3]);
-        }
-      }
-    } else {
-      const float4* n0 = Pl + (size_t)i * 3;
-      const float4* n1 = Pl + (size_t)(i + 1) * 3;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const float4 a0 = n0[m], a1 = n1[m];
-        v[4 * m] = fmaf(t, a1.x - a0.x, a0.x);
-        v[4 * m + 1] = fmaf(t, a1.y - a0.y, a0.y);
-        v[4 * m + 2] = fmaf(t, a1.z - a0.z, a0.z);
-        v[4 * m + 3] = fmaf(t, a1.w - a0.w, a0.w);
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < TT_NF; ++f) xf[f] = v[f];
+    const int i = cell(a);
+    const float t = (a - sa[i]) * sinv[i];
+    full = c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3;
+    base = i - 1 < 0 ? 0 : (i - 1 > nx - 4 ? nx - 4 : i - 1);
+    const int pos = i - base;  // 1 for the full stencil
+    const float hk = sa[i + 1] - sa[i];
+    const float rm = hk * sinv[i >= 1 ? i - 1 : 0];
+    const float rp = hk * sinv[i + 1];
+    const float t2 = t * t, t3 = t2 * t;
+    const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
+    const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
+    const float c0 = -0.5f * h10 * rm;
+    const float c1 = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
+    const float c2 = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
+    const float c3 = 0.5f * h11 * rp;
+    const float u = 1.f - t;
+    w[0] = full ? c0 : (pos == 0 ? u : 0.f);
+    w[1] = full ? c1 : (pos == 1 ? u : (pos == 0 ? t : 0.f));
+    w[2] = full ? c2 : (pos == 2 ? u : (pos == 1 ? t : 0.f));
+    w[3] = full ? c3 : (pos == 2 ? t : 0.f);
+  }
+
+  // step k of a window starting at base visits node 4 mb + k + 4 [k < r]
+  // (base = 4 mb + r), the window position (k - r) mod 4: the weights
+  // rotated by r
+  __device__ __forceinline__ static void rotate(const float (&w)[4], int r, float (&cr)[4]) {
+    const bool o1 = r & 1, o2 = r & 2;
+    const float d0 = o1 ? w[3] : w[0], d1 = o1 ? w[0] : w[1];
+    const float d2 = o1 ? w[1] : w[2], d3 = o1 ? w[2] : w[3];
+    cr[0] = o2 ? d2 : d0;
+    cr[1] = o2 ? d3 : d1;
+    cr[2] = o2 ? d0 : d2;
+    cr[3] = o2 ? d1 : d3;
   }
 
   // xf of all flavours at ln x = a (a <= 0).
   __device__ __forceinline__ void pdf_at(float a, float (&xf)[TT_NF]) const {
-    const int nx = c.nxs;
-    const int i = cell(a);
-    const float t = (a - sa[i]) * sinv[i];
+    int base;
+    float w[4];
+    bool full;
+    window(a, base, w, full);
+    const int r = base & 3, mb = base >> 2;
+    float cr[4];
+    rotate(w, r, cr);
     if (c.contract) {
-      pdf_at_contracted(i, t, xf);
-      return;
-    }
-    if (c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3) {
-      const float rm = (sa[i + 1] - sa[i]) * sinv[i - 1];
-      const float rp = (sa[i + 1] - sa[i]) * sinv[i + 1];
-      const float t2 = t * t, t3 = t2 * t;
-      const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
-      const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
-      float cx[4];
-      cx[0] = -0.5f * h10 * rm;
-      cx[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
-      cx[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
-      cx[3] = 0.5f * h11 * rp;
-      const float q0 = qw[0], q1 = qw[1], q2 = qw[2], q3 = qw[3];
-      // step k visits the stencil node n_k = congruent to k mod 4 in
-      // [i-1, i+2]: n_k = 4 mb + k + 4 [k < r] with i-1 = 4 mb + r, weight
-      // cx[(k - r) mod 4]
-      const int base = i - 1, r = base & 3, mb = base >> 2;
-      const bool o1 = r & 1, o2 = r & 2;
-      const float d0 = o1 ? cx[3] : cx[0], d1 = o1 ? cx[0] : cx[1];
-      const float d2 = o1 ? cx[1] : cx[2], d3 = o1 ? cx[2] : cx[3];
-      const float cr[4] = {o2 ? d2 : d0, o2 ? d3 : d1, o2 ? d0 : d2, o2 ? d1 : d3};
+      // Hermite-in-Q table for full cells, linear-in-Q table otherwise
+      const float4* T = F + (full ? 0 : nq4 * 4 * 3);
+      float v[12];
 #pragma unroll
-      for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
+      for (int f = 0; f < 12; ++f) v[f] = 0.0f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float w0 = cr[k] * q0, w1 = cr[k] * q1, w2 = cr[k] * q2, w3 = cr[k] * q3;
-        const float4* node = F + (size_t)((k * nq4 + mb + (k < r ? 1 : 0)) * TT_NF);
+        const float4* node = T + (size_t)((k * nq4 + mb + (k < r ? 1 : 0)) * 3);
 #pragma unroll
-        for (int f = 0; f < TT_NF; ++f) {
-          const float4 v = node[f];
-          xf[f] = fmaf(w0, v.x, fmaf(w1, v.y, fmaf(w2, v.z, fmaf(w3, v.w, xf[f]))));
+        for (int m = 0; m < 3; ++m) {
+          const float4 u = node[m];
+          v[4 * m] = fmaf(cr[k], u.x, v[4 * m]);
+          v[4 * m + 1] = fmaf(cr[k], u.y, v[4 * m + 1]);
+          v[4 * m + 2] = fmaf(cr[k], u.z, v[4 * m + 2]);
+          v[4 * m + 3] = fmaf(cr[k], u.w, v[4 * m + 3]);
         }
       }
-    } else {
-      // bilinear on rows (j, j+1): staged rows 1, 2 of four, or 0, 1 of two
-      const float tb = qw[4];
-      const float w00 = (1.f - t) * (1.f - tb), w01 = t * (1.f - tb), w10 = (1.f - t) * tb, w11 = t * tb;
-      const float4* n0 = F + node_off(i);
-      const float4* n1 = F + node_off(i + 1);
-      const bool four = c.n_rows == 4;
+#pragma unroll
+      for (int f = 0; f < TT_NF; ++f) xf[f] = v[f];
+      return;
+    }
+    // Q weights: Hermite for full cells, linear on the cell otherwise
+    const float q0 = full ? qw[0] : qw[8], q1 = full ? qw[1] : qw[9];
+    const float q2 = full ? qw[2] : qw[10], q3 = full ? qw[3] : qw[11];
+#pragma unroll
+    for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float w0 = cr[k] * q0, w1 = cr[k] * q1, w2 = cr[k] * q2, w3 = cr[k] * q3;
+      const float4* node = F + (size_t)((k * nq4 + mb + (k < r ? 1 : 0)) * TT_NF);
 #pragma unroll
       for (int f = 0; f < TT_NF; ++f) {
-        const float4 a0 = n0[f], a1 = n1[f];
-        const float lo0 = four ? a0.y : a0.x, hi0 = four ? a0.z : a0.y;
-        const float lo1 = four ? a1.y : a1.x, hi1 = four ? a1.z : a1.y;
-        float v = w00 * lo0;
-        v = fmaf(w01, lo1, v);
-        v = fmaf(w10, hi0, v);
-        v = fmaf(w11, hi1, v);
-        xf[f] = v;
+        const float4 v = node[f];
+        xf[f] = fmaf(w0, v.x, fmaf(w1, v.y, fmaf(w2, v.z, fmaf(w3, v.w, xf[f]))));
       }
     }
   }

@@ -64,7 +64,7 @@ struct TTbar {
     // expm1 keeps full precision where beta -> 0.  Reciprocals use the
     // hardware rcp (1 ulp).
     const float rho = __expf(-vf);
-    const float beta = sqrtf(-expm1f(-vf));
+    const float beta = __builtin_amdgcn_sqrtf(-expm1f(-vf));  // hardware sqrt, 1 ulp
     const float omb = rho * __builtin_amdgcn_rcpf(1.f + beta);  // 1 - beta
     const float tau1 = 0.5f * (omb + 2.f * beta * w3);
     const float tau2 = 0.5f * (omb + 2.f * beta * u3);

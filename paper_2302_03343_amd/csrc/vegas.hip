@@ -281,7 +281,9 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
   int i0 = 0;
   while (i0 < pdf->n_x - 2 && pdf->h_x[i0 + 1] <= x_min) ++i0;
   t.ix0 = i0 >= 2 ? i0 - 2 : 0;
+  if (pdf->n_x - t.ix0 < 4) t.ix0 = pdf->n_x - 4 > 0 ? pdf->n_x - 4 : 0;
   t.nxs = pdf->n_x - t.ix0;
+  VGX_CHECK(t.nxs >= 4, "%s needs at least 4 x knots", who);
   t.j_local = j;
   t.nq_sub = nq;
   t.q_off = pdf->q_off[sub];

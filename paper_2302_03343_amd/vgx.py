@@ -33,6 +33,17 @@ if not os.path.exists(LIB_PATH):
         f"libvgx.so not found at {LIB_PATH}; build it with `python -m paper_2302_03343_amd.build` "
         "(the HIP path has no CPU fallback)")
 
+# One HIP runtime per process: PyTorch ships its own copy of the HIP runtime
+# (same soname as the system one).  Loading PyTorch first makes the library's
+# dependency resolve to that already-loaded copy, so device memory, streams
+# and synchronisation are shared with the caller's tensors; loaded the other
+# way round, the process would hold two runtimes that do not see each other's
+# streams (and the library's launches would not run on the caller's queues).
+try:
+    import torch  # noqa: F401  (for its HIP runtime)
+except ImportError:  # C-ABI use without PyTorch: the system runtime
+    torch = None
+
 _lib = C.CDLL(LIB_PATH)
 _vp = C.c_void_p
 _i32, _i64, _u32, _u64, _f32, _f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float, C.c_double
