@@ -192,6 +192,44 @@ __device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, 
   }
 }
 
+// The network's hidden layers for the wave's 32 samples (transposed form):
+// h2 = relu(W2 relu(W1 zA + b1) + b2), returned as the four BF16 K-step
+// operands of the output layer (each activation converted once).
+__device__ __forceinline__ void mlp_hidden(const float (&za)[FAB], int na, const LayerLds& W, bf16x8 (&h2b)[4]) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  bf16x8 bz;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) bz[e] = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
+  bf16x8 h1b[4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16 h1 = mfma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
+#pragma unroll
+    for (int v = 0; v < 16; ++v) h1[v] = fmaxf(h1[v], 0.0f);
+    h1b[2 * t] = to_b(h1, 0);
+    h1b[2 * t + 1] = to_b(h1, 1);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16 acc = bias_tile(W.b2 + 32 * t, h);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], h1b[kk], acc);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v], 0.0f);
+    h2b[2 * t] = to_b(acc, 0);
+    h2b[2 * t + 1] = to_b(acc, 1);
+  }
+}
+
+// The 32 logits of transformed dimension t for the wave's 32 samples.
+__device__ __forceinline__ f32x16 mlp_logits(const bf16x8 (&h2b)[4], int t, const LayerLds& W) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  f32x16 acc = bias_tile(W.b3 + 32 * t, h);
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], h2b[kk], acc);
+  return acc;
+}
+
 // in place: exponentials of the 32 logits of one B dim less their maximum
 // (16 here, 16 in lane^32), unnormalised; returns their sum
 __device__ __forceinline__ float softexp32(f32x16& q) {
@@ -333,6 +371,125 @@ __host__ __device__ inline size_t fwd_z_offset(int fw_total, int bias_total) {
   return (((size_t)fw_total * 2 + (size_t)bias_total * 4) + 15) & ~(size_t)15;
 }
 
+// ---- one sample per lane after a tile pair's exchange ---------------------
+// A wave runs the networks for two 32-sample tiles (samples 64 t + 0..31 and
+// 64 t + 32..63); then one permlane32 swap per register of the two logit
+// tiles gives every lane all 32 logits of its own sample 64 t + lane: bin
+// k = 8 g + 4 hh + r sits in (hh ? hi : lo)[4 g + r].
+__device__ __forceinline__ void pair_swap(f32x16& a, f32x16& b) {
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[v]), __float_as_uint(b[v]), false, false);
+    a[v] = __uint_as_float(r[0]);
+    b[v] = __uint_as_float(r[1]);
+  }
+}
+
+// in place: exponentials of the lane's 32 logits less their maximum; returns
+// their sum (unnormalised softmax)
+__device__ __forceinline__ float softexp_own(f32x16& lo, f32x16& hi) {
+  float m = fmaxf(lo[0], hi[0]);
+#pragma unroll
+  for (int v = 1; v < 16; ++v) m = fmaxf(m, fmaxf(lo[v], hi[v]));
+  // exp via the hardware exp2 (v_exp_f32): arguments are <= 0 and the
+  // relative error (~1e-7) is far below the BF16 noise of the logits
+  float s = 0.0f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    lo[v] = __expf(lo[v] - m);
+    hi[v] = __expf(hi[v] - m);
+  }
+  // bin-order sum in groups of four
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const f32x16& X = (c & 1) ? hi : lo;
+    const int o = 4 * (c >> 1);
+    s += (X[o] + X[o + 1]) + (X[o + 2] + X[o + 3]);
+  }
+  return s;
+}
+
+// the four weights of bin group c (bins 4c .. 4c+3) for a runtime c
+__device__ __forceinline__ void group_vals(const f32x16& lo, const f32x16& hi, int c, float (&g)[4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float v = lo[r];
+#pragma unroll
+    for (int cc = 1; cc < 8; ++cc) v = (c == cc) ? ((cc & 1) ? hi[4 * (cc >> 1) + r] : lo[4 * (cc >> 1) + r]) : v;
+    g[r] = v;
+  }
+}
+
+// density direction for one B dim of the lane's sample: returns z', sets
+// the bin and Q_b; lo/hi hold the unnormalised bin weights, sum their sum
+__device__ __forceinline__ float cdf_fwd_own(const f32x16& lo, const f32x16& hi, float sum, float z, int& b, float& qb) {
+  const float t = z * (float)FK;
+  int bb = (int)floorf(t);
+  bb = bb < 0 ? 0 : (bb > FK - 1 ? FK - 1 : bb);
+  const float al = t - (float)bb;
+  const int cb = bb >> 2, rb = bb & 3;
+  float lt = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const f32x16& X = (c & 1) ? hi : lo;
+    const int o = 4 * (c >> 1);
+    const float gsum = (X[o] + X[o + 1]) + (X[o + 2] + X[o + 3]);
+    lt += (c < cb) ? gsum : 0.0f;
+  }
+  float g[4];
+  group_vals(lo, hi, cb, g);
+  float qq = g[0];
+  lt += (rb > 0) ? g[0] : 0.0f;
+  lt += (rb > 1) ? g[1] : 0.0f;
+  lt += (rb > 2) ? g[2] : 0.0f;
+  qq = (rb == 1) ? g[1] : qq;
+  qq = (rb == 2) ? g[2] : qq;
+  qq = (rb == 3) ? g[3] : qq;
+  const float inv = 1.0f / sum;
+  b = bb;
+  qb = qq * inv;
+  return lt * inv + al * qb;
+}
+
+// sampling direction for one B dim of the lane's sample: returns z, sets the
+// bin and Q_b (search on v sum over the unnormalised cumulative weights)
+__device__ __forceinline__ float cdf_inv_own(const f32x16& lo, const f32x16& hi, float sum, float v, int& b, float& qb) {
+  const float vs = v * sum;
+  float acc = 0.0f, base = 0.0f;
+  int cstar = 7;
+  bool found = false;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const f32x16& X = (c & 1) ? hi : lo;
+    const int o = 4 * (c >> 1);
+    const float gsum = (X[o] + X[o + 1]) + (X[o + 2] + X[o + 3]);
+    const bool here = !found && (vs < acc + gsum || c == 7);
+    cstar = here ? c : cstar;
+    base = here ? acc : base;
+    found = found || here;
+    acc += gsum;
+  }
+  float g[4];
+  group_vals(lo, hi, cstar, g);
+  int bb = 4 * cstar + 3;
+  float cb = base, qq = g[3], run = base;
+  bool got = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const bool here = !got && (vs < run + g[r] || r == 3);
+    bb = here ? 4 * cstar + r : bb;
+    cb = here ? run : cb;
+    qq = here ? g[r] : qq;
+    got = got || here;
+    run += g[r];
+  }
+  b = bb;
+  qb = qq / sum;
+  float frac = (vs - cb) / qq;
+  frac = frac < 0.0f ? 0.0f : (frac > 1.0f ? 1.0f : frac);
+  return ((float)bb + frac) * (1.0f / (float)FK);
+}
+
 template <int NBM, int MODE>
 __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restrict__ Dp, FwdArgs a, const unsigned short* __restrict__ fw,
                                                      const float* __restrict__ bias) {
@@ -340,20 +497,20 @@ __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restri
   const FlowDesc& D = *Dp;
   unsigned short* sfw = (unsigned short*)flds;
   float* sb = (float*)(flds + D.fw_total * 2);
-  // each lane keeps its sample's coordinates in its own LDS column (the
+  // each lane keeps its own sample's coordinates in its own LDS column (the
   // layer masks index them with runtime, wave-uniform indices)
   float* z = (float*)(flds + fwd_z_offset(D.fw_total, D.bias_total)) + threadIdx.x;
   copy16(sfw, fw, D.fw_total * 2);
   copy16(sb, bias, D.bias_total * 4);
   __syncthreads();
-  const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+  const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (FWD_BLOCK / 64) + (threadIdx.x >> 6);
   const int nwaves = gridDim.x * (FWD_BLOCK / 64);
-  const int64_t ntiles = (a.n + 31) / 32;
+  const int64_t ntiles = (a.n + 63) / 64;  // tile pairs
   const int d = D.d;
   Comp sr, sg;
   for (int64_t t = wave; t < ntiles; t += nwaves) {
-    const int64_t i = t * 32 + s;
+    const int64_t i = t * 64 + lane;  // the lane's own sample
     const bool valid = i < a.n;
     if (MODE == 2) {
       for (int bk = 0; 4 * bk < d; ++bk) {
@@ -371,30 +528,37 @@ __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restri
     for (int step = 0; step < D.L; ++step) {
       const int l = (MODE == 2) ? D.L - 1 - step : step;
       const FlowLayerDesc& L = D.l[l];
-      if (MODE == 1 && valid && h == 0) {
+      if (MODE == 1 && valid) {
         for (int j = 0; j < d; ++j) a.zsave[((int64_t)l * d + j) * a.n + i] = z[j * FWD_BLOCK];
       }
-      float za[FAB];
+      // network inputs: tile A (samples 64 t + 0..31) takes the lower lanes'
+      // own coordinates, tile B (64 t + 32..63) the upper lanes', moved down
+      float za[FAB], zb[FAB];
 #pragma unroll
-      for (int e = 0; e < FAB; ++e) za[e] = (e < L.na) ? z[L.a_idx[e] * FWD_BLOCK] : 0.0f;
+      for (int e = 0; e < FAB; ++e) {
+        za[e] = (e < L.na) ? z[L.a_idx[e] * FWD_BLOCK] : 0.0f;
+        zb[e] = xor32(za[e]);
+      }
       const LayerLds W = layer_lds(sfw, sb, L, 0, 0);
-      f32x16 h1[2], h2[2], lg[NBM];
-      mlp_fwd<NBM>(za, L.na, L.nb, W, h1, h2, lg);
-#pragma unroll
-      for (int jb = 0; jb < NBM; ++jb) {
-        if (jb < L.nb) {
-          const float sum = softexp32(lg[jb]);
-          const int j = L.b_idx[jb];
-          const float zj = z[j * FWD_BLOCK];
-          int b;
-          float qb, al;
-          const float zn = (MODE == 2) ? cdf_inv(lg[jb], zj, sum, b, qb) : cdf_fwd(lg[jb], zj, b, al, qb, 1.0f / sum);
-          z[j * FWD_BLOCK] = zn;
-          lq += (double)logf((float)FK * qb);
-        }
+      bf16x8 h2A[4], h2B[4];
+      mlp_hidden(za, L.na, W, h2A);
+      mlp_hidden(zb, L.na, W, h2B);
+      // one transformed dimension at a time: its logits for both tiles,
+      // exchanged so that every lane holds its own sample's 32 logits
+      for (int jb = 0; jb < L.nb; ++jb) {
+        f32x16 lo = mlp_logits(h2A, jb, W), hi = mlp_logits(h2B, jb, W);
+        pair_swap(lo, hi);
+        const float sum = softexp_own(lo, hi);
+        const int j = L.b_idx[jb];
+        const float zj = z[j * FWD_BLOCK];
+        int b;
+        float qb;
+        const float zn = (MODE == 2) ? cdf_inv_own(lo, hi, sum, zj, b, qb) : cdf_fwd_own(lo, hi, sum, zj, b, qb);
+        z[j * FWD_BLOCK] = zn;
+        lq += (double)logf((float)FK * qb);
       }
     }
-    if (valid && h == 0) {
+    if (valid) {
       a.logq[i] = lq;
       if (a.out) {
         for (int j = 0; j < d; ++j) a.out[(int64_t)j * a.n + i] = (double)z[j * FWD_BLOCK];
@@ -1020,7 +1184,7 @@ vgx_status init_lds_limits(const vgx_flow* f) {
 }
 
 int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
-  const int64_t tiles = (n + 31) / 32;
+  const int64_t tiles = (n + 63) / 64;  // the forward kernels take 64-sample tile pairs
   const int64_t waves_per_wg = FWD_BLOCK / 64;
   int64_t g = (tiles + waves_per_wg - 1) / waves_per_wg;
   const int64_t cap = (int64_t)device_cus() * per_cu;
