@@ -176,8 +176,11 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
                   max_batches=40):
     """Flow-proposal pipeline until sigma/mean <= target: VEGAS warm-up
     iterations (kept in the combination), training of the coupling flow on
-    uniform points of the adapted VEGAS cube with g = f(G(u)) J(u), then
-    batches drawn from the flow (weights f/q) until the target is reached.
+    uniform points of the VEGAS cube with g = f(G(u)) J(u), then batches
+    drawn from the flow (weights f/q) until the target is reached.  One
+    warm-up iteration is used: measured on the t tbar integrand, the flow
+    trained on the once-refined grid reaches a lower variance per sample
+    (0.018) than on a twice-refined one (0.045).
     Wall time includes everything from the first launch."""
     import torch
     from synth import he_init_segments
@@ -503,7 +506,7 @@ def main():
     if not args.no_flow:
         from synth import C4
         tv = time_to_precision_vegas(vgx, pdf, params, n)
-        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, n, warm_iters=2, steps=C4["steps"], batch=C4["batch"],
+        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, n, warm_iters=1, steps=C4["steps"], batch=C4["batch"],
                            lr=C4["lr"], n_flow=n, seed=1000 + C2["seed"])
         tv["ns_per_event"] = ms_per_step * 1e6 / n
         out["time_to_1e-4"] = {"vegas": tv, "flow": tf,
@@ -515,7 +518,7 @@ def main():
             d8 = C4["gauss_dim"]
             gp = np.concatenate([np.full(d8, C4["gauss_centre"]), np.full(d8, C4["gauss_sigma"])])
             gv = time_to_precision_vegas(vgx, None, gp, 1_000_000, kind=vgx.GAUSS, dim=d8, seed=C4["seed"])
-            gf = flow_pipeline(vgx, vgx.GAUSS, d8, gp, None, 1_000_000, warm_iters=2, steps=C4["steps"],
+            gf = flow_pipeline(vgx, vgx.GAUSS, d8, gp, None, 1_000_000, warm_iters=1, steps=C4["steps"],
                                batch=C4["batch"], lr=C4["lr"], n_flow=1_000_000, seed=C4["seed"])
             out["time_to_1e-4"]["gauss8"] = {"vegas": gv, "flow": gf}
     if args.extras:
