@@ -7,14 +7,14 @@ the method, no grid map, no interpolation, no integrand, no training step),
 so that the GPU path and the oracle, which both consume these inputs, share
 no computation.
 """
-from .configs import C0, C1, C2, C3, C4, C5, FLAVOURS
+from .configs import C0, C1, C2, C3, C4, C5, C6, FLAVOURS
 from .pdfgrid import synthetic_pdf_grid, PdfGridData
 from .queries import pdf_queries
 from .batch import batch_specs, BatchSpec
 from .flowinit import he_init_segments
 
 __all__ = [
-    "C0", "C1", "C2", "C3", "C4", "C5", "FLAVOURS",
+    "C0", "C1", "C2", "C3", "C4", "C5", "C6", "FLAVOURS",
     "synthetic_pdf_grid", "PdfGridData", "pdf_queries",
     "batch_specs", "BatchSpec", "he_init_segments",
 ]

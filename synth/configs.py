@@ -6,6 +6,7 @@ C2  LO pp -> t tbar at sqrt(s) = 13 TeV, 3-d (tau, y, cos theta*) integrand.
 C3  64 independent integrals of uneven dimension and sample count, batched.
 C4  coupling-flow proposal trained on VEGAS samples, compared with VEGAS.
 C5  LO Drell-Yan (gamma*/Z -> l+ l-) at sqrt(s) = 13 TeV on the C2 path.
+C6  LO s-channel single top (u dbar -> t bbar) at sqrt(s) = 8 TeV on the C2 path.
 """
 
 # Flavour order of every PDF array: PDG ids -5..-1, gluon (21), 1..5.
@@ -71,5 +72,17 @@ C5 = dict(
     seed=5, stream=0,
     sqrt_s=13000.0, m_lo=60.0, m_hi=120.0,
     m_z=91.1876, gamma_z=2.4952, sw2=0.2312, alpha_em=1.0 / 128.0,
+    gev2_to_pb=3.893793721e8,
+)
+
+# LO single top (s channel): u dbar, c sbar -> W* -> t bbar, the thesis's own
+# LO example (pp -> t + 1 jet at the LHC Run 1 energy, m_t = 173.2 GeV), on
+# the same fused path: 3-d (tau, y, cos theta*), PDFs at mu = m_t, diagonal
+# CKM matrix, fixed alpha and sin^2 theta_W.
+C6 = dict(
+    name="single-top-s-lo-8tev",
+    dim=3, n_bins=50, alpha=1.5, iterations=10, n_per_iter=10_000_000,
+    seed=6, stream=0,
+    sqrt_s=8000.0, m_top=173.2, m_w=80.385, gamma_w=2.085, sw2=0.2312, alpha_em=1.0 / 128.0,
     gev2_to_pb=3.893793721e8,
 )

@@ -19,9 +19,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import drellyan, integrands, ttbar, vegas  # noqa: E402
+from oracle import drellyan, integrands, singletop, ttbar, vegas  # noqa: E402
 from oracle.philox import sample_words  # noqa: E402
-from synth import C0, C2, C5, synthetic_pdf_grid  # noqa: E402
+from synth import C0, C2, C5, C6, synthetic_pdf_grid  # noqa: E402
 
 U = [[0.1, 0.2, 0.3], [0.5, 0.5, 0.5], [0.9, 0.05, 0.75], [0.33, 0.66, 0.99], [0.01, 0.99, 0.01]]
 
@@ -37,6 +37,7 @@ def build():
         "ttbar_integrand_pb": ttbar.integrand(u, grid, C2["sqrt_s"], C2["m_top"], C2["alpha_s"],
                                               C2["gev2_to_pb"]).tolist(),
         "drellyan_integrand_pb": drellyan.integrand_from_config(u, grid, C5).tolist(),
+        "singletop_integrand_pb": singletop.integrand_from_config(u, grid, C6).tolist(),
         "points": U,
     }
     for seed, it, stream, idx in [(0, 0, 0, 0), (2, 3, 7, 123456789), (2**63 + 5, 9, (1 << 22) + 1, 2**40 + 3)]:

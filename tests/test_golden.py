@@ -18,7 +18,7 @@ def test_oracle_matches_its_frozen_values():
         ref = json.load(fh)
     got = mod.build()
     assert got["philox_words"] == ref["philox_words"]
-    for key in ("ttbar_integrand_pb", "drellyan_integrand_pb"):
+    for key in ("ttbar_integrand_pb", "drellyan_integrand_pb", "singletop_integrand_pb"):
         assert got[key] == pytest.approx(ref[key], rel=1e-13, abs=0)
     for key in ("mean", "sigma", "chi2_dof"):
         assert got["vegas_gauss4_3x20000"][key] == pytest.approx(ref["vegas_gauss4_3x20000"][key], rel=1e-12)

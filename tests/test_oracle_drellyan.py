@@ -9,62 +9,29 @@ from oracle import drellyan as dy, vegas
 from oracle.pdf import interp
 from oracle.ttbar import IDX
 from synth import C5, synthetic_pdf_grid
+from tests import dirac
 
 AL, MZ, GZ, SW2 = C5["alpha_em"], C5["m_z"], C5["gamma_z"], C5["sw2"]
 
-# --- brute-force Dirac algebra ---------------------------------------------
-_I2, _Z2 = np.eye(2), np.zeros((2, 2))
-_SIG = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]], complex)]
-GAM = [np.block([[_I2, _Z2], [_Z2, -_I2]]).astype(complex)] + [np.block([[_Z2, s], [-s, _Z2]]) for s in _SIG]
-G5 = 1j * GAM[0] @ GAM[1] @ GAM[2] @ GAM[3]
-PL, PR = (np.eye(4) - G5) / 2, (np.eye(4) + G5) / 2
-METRIC = np.array([1.0, -1.0, -1.0, -1.0])
-
-
-def _slash(p):
-    return p[0] * GAM[0] - p[1] * GAM[1] - p[2] * GAM[2] - p[3] * GAM[3]
-
-
-def _bar(m):
-    return GAM[0] @ m.conj().T @ GAM[0]
-
-
 def _vertices(kind):
-    """[photon, Z] vertex matrices gamma^mu (couplings) for mu = 0..3."""
+    """[photon, Z] vertex matrices for a fermion kind."""
     q, t3 = dy.CHARGES[kind]
     e = math.sqrt(4 * math.pi * AL)
     sw, cw = math.sqrt(SW2), math.sqrt(1 - SW2)
     gl, gr = t3 - q * SW2, -q * SW2
-    chir = gl * PL + gr * PR
-    return [[e * q * GAM[m] for m in range(4)], [e / (sw * cw) * GAM[m] @ chir for m in range(4)]]
+    return [dirac.vector_vertex(e * q), dirac.vector_vertex(e / (sw * cw), gl * dirac.PL + gr * dirac.PR)]
 
 
 def m2_trace(p1, p2, p3, p4, kind):
-    """Spin-summed, colour-averaged |M|^2 of q(p1) qbar(p2) -> l-(p3) l+(p4)
-    from Dirac traces, divided by 4 (spin average)."""
+    """Spin- and colour-averaged |M|^2 of q(p1) qbar(p2) -> l-(p3) l+(p4)
+    from Dirac traces: spin average 1/4, colour N_c / N_c^2."""
     s = (p1[0] + p2[0]) ** 2 - sum((p1[k] + p2[k]) ** 2 for k in (1, 2, 3))
-    prop = [1.0 / s, 1.0 / (s - MZ * MZ + 1j * MZ * GZ)]
-    vq, vl = _vertices(kind), _vertices("l")
-    s1, s2, s3, s4 = _slash(p1), _slash(p2), _slash(p3), _slash(p4)
-    tot = 0.0 + 0.0j
-    for a in range(2):
-        for b in range(2):
-            for mu in range(4):
-                for rho in range(4):
-                    hq = np.trace(vq[a][mu] @ s1 @ _bar(vq[b][rho]) @ s2)
-                    hl = np.trace(vl[a][mu] @ s4 @ _bar(vl[b][rho]) @ s3)
-                    tot += prop[a] * np.conj(prop[b]) * METRIC[mu] * METRIC[rho] * hq * hl
-    assert abs(tot.imag) < 1e-9 * abs(tot.real)
-    return tot.real / 4.0 / 3.0  # spins; colour: N_c / N_c^2
+    props = [1.0 / s, 1.0 / (s - MZ * MZ + 1j * MZ * GZ)]
+    return dirac.spin_sum(_vertices(kind), _vertices("l"), props, p1, p2, p3, p4) / 4.0 / 3.0
 
 
 def _momenta(rs, cos, phi, quark_along_plus_z=True):
-    e = rs / 2
-    sin = math.sqrt(1 - cos * cos)
-    pa, pb = np.array([e, 0, 0, e]), np.array([e, 0, 0, -e])
-    p3 = np.array([e, e * sin * math.cos(phi), e * sin * math.sin(phi), e * cos])
-    p4 = np.array([e, -p3[1], -p3[2], -p3[3]])
-    return (pa, pb, p3, p4) if quark_along_plus_z else (pb, pa, p3, p4)
+    return dirac.cm_momenta(rs, cos, phi, 0.0, quark_along_plus_z)
 
 
 @pytest.mark.parametrize("kind", ["u", "d"])
