@@ -378,6 +378,16 @@ def extra_ttbar_contracted(vgx, pdf, params, n):
     return extra_hadronic(vgx, pdf, vgx.TTBAR, np.concatenate([params, [1.0]]), C2["seed"], n)
 
 
+def extra_singletop(vgx, pdf, n):
+    """LO s-channel single top (u dbar, c sbar -> t bbar) at 8 TeV, the
+    thesis's own LO example, on the same fused path (full stencil)."""
+    import numpy as np
+    from synth import C6
+    p = np.array([C6["sqrt_s"], C6["m_top"], C6["m_w"], C6["gamma_w"], C6["sw2"], C6["alpha_em"], C6["gev2_to_pb"],
+                  0.0])
+    return extra_hadronic(vgx, pdf, vgx.SINGLETOP, p, C6["seed"], n)
+
+
 def extra_drellyan(vgx, pdf, n):
     """LO Drell-Yan (photon/Z -> l+ l-, 60 < m_ll < 120 GeV) on the same fused
     path: full stencil (mode 0) and fixed-scale contraction (mode 1)."""
@@ -524,6 +534,7 @@ def main():
     if args.extras:
         out["extras"] = {"ttbar_fixed_scale_contraction": extra_ttbar_contracted(vgx, pdf, params, n),
                          "drell_yan_1e7": extra_drellyan(vgx, pdf, n),
+                         "single_top_s_1e7": extra_singletop(vgx, pdf, n),
                          "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
                          "batched_64": extra_batch(vgx)}
     if not args.no_cpu:

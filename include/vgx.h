@@ -79,7 +79,7 @@ enum {
                          contracted once per workgroup and each event does
                          the ln x direction only (same interpolant, FP32
                          rounding differs)                                    */
-  VGX_DRELLYAN = 4    /* LO pp -> photon or Z -> l+ l- (massless leptons), d = 3,
+  VGX_DRELLYAN = 4,   /* LO pp -> photon or Z -> l+ l- (massless leptons), d = 3,
                          (tau, y, cos theta*) map over the dilepton-mass
                          window m_lo < m_ll < m_hi.
                          params = [sqrt_s, m_lo, m_hi, m_z, gamma_z, sin2w,
@@ -88,6 +88,13 @@ enum {
                          Thesis: master formula (MadFlow chapter) and
                          factorisation (PDF chapter); the gamma + Z helicity
                          amplitudes are textbook electroweak theory         */
+  VGX_SINGLETOP = 5   /* LO s-channel single top, u dbar and c sbar -> W ->
+                         t bbar (the thesis's LO single-top example), d = 3,
+                         (tau, y, cos theta*) map from threshold m_top^2.
+                         params = [sqrt_s, m_top, m_w, gamma_w, sin2w, alpha,
+                         gev2_to_pb(, mode)]; needs a PDF context, evaluated
+                         at mu^2 = m_top^2; diagonal CKM matrix; mode as for
+                         VGX_TTBAR                                          */
 };
 enum { VGX_F64 = 0, VGX_F32 = 1 };   /* integrand / output precision          */
 
@@ -144,8 +151,8 @@ typedef struct vgx_vegas vgx_vegas;
 
 typedef struct {
   int32_t kind;             /* VGX_GAUSS, VGX_GENZ_OSC, VGX_GENZ_PEAK, VGX_TTBAR,
-                               VGX_DRELLYAN                                     */
-  int32_t dim;              /* 1 .. VGX_MAX_DIM (3 for VGX_TTBAR, VGX_DRELLYAN) */
+                               VGX_DRELLYAN, VGX_SINGLETOP                      */
+  int32_t dim;              /* 1 .. VGX_MAX_DIM (3 for the hadronic kinds)      */
   int32_t n_bins;           /* bins per dimension, 2 .. VGX_MAX_BINS            */
   double alpha;             /* refinement damping exponent (e.g. 1.5)           */
   uint64_t seed;            /* Philox key                                       */
@@ -153,8 +160,7 @@ typedef struct {
   int32_t prec;             /* VGX_F64 or VGX_F32 integrand arithmetic          */
   const double* params;     /* host, integrand parameters (see the kinds)       */
   int32_t n_params;
-  const vgx_pdf* pdf;       /* VGX_TTBAR, VGX_DRELLYAN only; must outlive the
-                               context                                          */
+  const vgx_pdf* pdf;       /* hadronic kinds only; must outlive the context    */
 } vgx_vegas_cfg;
 
 typedef struct {
@@ -229,7 +235,7 @@ void vegas_destroy(vgx_vegas* v);
 /* ------------------------------------------------------------------------ */
 typedef struct vgx_batch vgx_batch;
 
-/* Bundle contexts (all on one device, no TTBAR or DRELLYAN) into a batch.  The batch
+/* Bundle contexts (all on one device, no hadronic kinds) into a batch.  The batch
  * captures one iteration (persistent kernel + reductions + refinement) in
  * a HIP graph on first use.  tile = samples per work item (0: autotuned),
  * block = threads per workgroup (0: autotuned). */

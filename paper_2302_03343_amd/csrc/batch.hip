@@ -330,7 +330,7 @@ extern "C" vgx_status batch_create(vgx_vegas* const* ctxs, int32_t count, const 
   hipGetDevice(&dev);
   for (int k = 0; k < count; ++k) {
     VGX_CHECK(ctxs[k], "batch_create: null context %d", k);
-    VGX_CHECK(ctxs[k]->kind != VGX_TTBAR && ctxs[k]->kind != VGX_DRELLYAN,
+    VGX_CHECK(ctxs[k]->kind != VGX_TTBAR && ctxs[k]->kind != VGX_DRELLYAN && ctxs[k]->kind != VGX_SINGLETOP,
               "batch_create: context %d has a PDF integrand (not batchable)", k);
     VGX_CHECK(ctxs[k]->device == dev, "batch_create: context %d is on another device", k);
     VGX_CHECK(n_samples[k] >= 2, "batch_create: n_samples[%d] < 2", k);

@@ -28,6 +28,7 @@
 #include "pdf_internal.h"
 #include "ttbar.h"
 #include "drellyan.h"
+#include "singletop.h"
 #include "vegas_internal.h"
 
 #include <math.h>
@@ -224,11 +225,12 @@ using namespace vgx;
 
 namespace {
 
-bool uses_pdf(int kind) { return kind == VGX_TTBAR || kind == VGX_DRELLYAN; }
+bool uses_pdf(int kind) { return kind == VGX_TTBAR || kind == VGX_DRELLYAN || kind == VGX_SINGLETOP; }
 
 size_t extra_lds_bytes(const vgx_vegas* v) {
   if (v->kind == VGX_TTBAR) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->tt.pdf.nxs);
   if (v->kind == VGX_DRELLYAN) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->dy.pdf.nxs);
+  if (v->kind == VGX_SINGLETOP) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->st.pdf.nxs);
   return 0;
 }
 
@@ -238,8 +240,9 @@ size_t extra_lds_bytes(const vgx_vegas* v) {
 int hadronic_blocks_per_cu(const vgx_vegas* v) {
   int occ = 0;
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(3, v->nb, true) + extra_lds_bytes(v);
-  const void* k = v->kind == VGX_TTBAR ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>)
-                                       : reinterpret_cast<const void*>(&k_vegas_iter<3, DrellYan, PhiloxSrc<3>, true>);
+  const void* k = v->kind == VGX_TTBAR      ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>)
+                  : v->kind == VGX_DRELLYAN ? reinterpret_cast<const void*>(&k_vegas_iter<3, DrellYan, PhiloxSrc<3>, true>)
+                                            : reinterpret_cast<const void*>(&k_vegas_iter<3, SingleTop, PhiloxSrc<3>, true>);
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, BLOCK, lds);
   if (e != hipSuccess || occ < 1) {
     (void)hipGetLastError();
@@ -382,6 +385,27 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
       }
       return VGX_OK;
     }
+    case VGX_SINGLETOP: {
+      VGX_CHECK(d == 3, "SINGLETOP needs dim 3");
+      VGX_CHECK(c->n_params >= 7, "SINGLETOP needs [sqrt_s, m_top, m_w, gamma_w, sin2w, alpha, gev2_to_pb]");
+      VGX_CHECK(c->pdf, "SINGLETOP needs a PDF context");
+      const double* q = c->params;
+      const double rs = q[0], mt = q[1], mw = q[2], gw = q[3], sw2 = q[4], al = q[5], conv = q[6];
+      VGX_CHECK(mt > 0.0 && rs > mt, "SINGLETOP: need sqrt_s > m_top > 0");
+      VGX_CHECK(mw > 0.0 && gw > 0.0 && sw2 > 0.0 && sw2 < 1.0 && al > 0.0, "SINGLETOP: bad electroweak inputs");
+      const double mode = c->n_params >= 8 ? q[7] : 0.0;
+      VGX_CHECK(mode == 0.0 || mode == 1.0, "SINGLETOP mode must be 0 (full stencil) or 1 (fixed-scale contraction)");
+      const double s = rs * rs, tau0 = mt * mt / s;
+      STConst& t = v->st;
+      VGX_TRY(setup_pdf_rows(t.pdf, c->pdf, mt * mt, tau0, mode == 1.0, "SINGLETOP"));
+      t.L0 = log(1.0 / tau0);
+      t.mt2 = (float)(mt * mt);
+      t.mw2 = (float)(mw * mw);
+      t.mwg2 = (float)(mw * mw * gw * gw);
+      const double g2 = 4.0 * M_PI * al / sw2;
+      t.pref = (float)(2.0 * t.L0 * conv * g2 * g2 / (128.0 * M_PI));
+      return VGX_OK;
+    }
     default:
       set_error("unknown integrand kind %d", c->kind);
       return VGX_EINVAL;
@@ -418,6 +442,15 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
       return launch_iter_f<3, DrellYan, Src, HIST>(v, n, f, src);
     }
     set_error("DRELLYAN needs dim 3");
+    return VGX_EINVAL;
+  }
+  if (v->kind == VGX_SINGLETOP) {
+    if constexpr (D == 3) {
+      SingleTop f{};
+      f.c = v->st;
+      return launch_iter_f<3, SingleTop, Src, HIST>(v, n, f, src);
+    }
+    set_error("SINGLETOP needs dim 3");
     return VGX_EINVAL;
   }
 #define VGX_LAUNCH_KIND(T)                                                     \
@@ -471,6 +504,15 @@ vgx_status launch_sample_d(vgx_vegas* v, int64_t first, int64_t n, int32_t it, d
       return launch_sample_f<3, DrellYan>(v, first, n, it, f, u, g);
     }
     set_error("DRELLYAN needs dim 3");
+    return VGX_EINVAL;
+  }
+  if (v->kind == VGX_SINGLETOP) {
+    if constexpr (D == 3) {
+      SingleTop f{};
+      f.c = v->st;
+      return launch_sample_f<3, SingleTop>(v, first, n, it, f, u, g);
+    }
+    set_error("SINGLETOP needs dim 3");
     return VGX_EINVAL;
   }
 #define VGX_SAMPLE_KIND(T)                                                     \

@@ -8,6 +8,7 @@
 #include "integrands.h"
 #include "ttbar.h"
 #include "drellyan.h"
+#include "singletop.h"
 
 namespace vgx {
 
@@ -179,6 +180,7 @@ struct vgx_vegas {
   vgx::IntegrandParams prm{};
   vgx::TTbarConst tt{};
   vgx::DYConst dy{};
+  vgx::STConst st{};
   int max_wg = 0;
   int pstride = 0;
   double* edges = nullptr;          // [dim][nb+1]

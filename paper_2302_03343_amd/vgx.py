@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libvgx.so")
 VGX_OK, VGX_EINVAL, VGX_ENOMEM, VGX_EDEVICE, VGX_ERANGE, VGX_ENUMERIC, VGX_EFALLBACK, VGX_ESTATE = range(8)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ERANGE", 5: "ENUMERIC",
                 6: "EFALLBACK", 7: "ESTATE"}
-GAUSS, GENZ_OSC, GENZ_PEAK, TTBAR, DRELLYAN = 0, 1, 2, 3, 4
+GAUSS, GENZ_OSC, GENZ_PEAK, TTBAR, DRELLYAN, SINGLETOP = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 MAX_DIM, MAX_BINS = 12, 256
 
