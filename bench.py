@@ -527,9 +527,12 @@ def main():
             import numpy as np
             d8 = C4["gauss_dim"]
             gp = np.concatenate([np.full(d8, C4["gauss_centre"]), np.full(d8, C4["gauss_sigma"])])
-            gv = time_to_precision_vegas(vgx, None, gp, 1_000_000, kind=vgx.GAUSS, dim=d8, seed=C4["seed"])
-            gf = flow_pipeline(vgx, vgx.GAUSS, d8, gp, None, 1_000_000, warm_iters=1, steps=C4["steps"],
-                               batch=C4["batch"], lr=C4["lr"], n_flow=1_000_000, seed=C4["seed"])
+            # VEGAS: iterations of 1e7 (at most 30); flow: two warm-up
+            # iterations of 1e6 (the narrow peak needs the second refinement
+            # before the flow's training points see it), batches up to 1e7
+            gv = time_to_precision_vegas(vgx, None, gp, 10_000_000, kind=vgx.GAUSS, dim=d8, seed=C4["seed"])
+            gf = flow_pipeline(vgx, vgx.GAUSS, d8, gp, None, 1_000_000, warm_iters=2, steps=C4["steps"],
+                               batch=C4["batch"], lr=C4["lr"], n_flow=10_000_000, seed=C4["seed"])
             out["time_to_1e-4"]["gauss8"] = {"vegas": gv, "flow": gf}
     if args.extras:
         out["extras"] = {"ttbar_fixed_scale_contraction": extra_ttbar_contracted(vgx, pdf, params, n),
