@@ -41,6 +41,8 @@ __host__ __device__ inline int ttbar_lds_floats(int nxs) { return pdf_rows_lds_f
 
 struct TTbar {
   static constexpr bool kStage = true;
+  // five waves per SIMD (<= 96 VGPRs) measured faster than four
+  static constexpr int kMinWaves = 5;
   TTbarConst c;
   PdfRows P;
 

@@ -34,6 +34,8 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 namespace vgx {
 
 constexpr int BLOCK = 256;
@@ -83,8 +85,16 @@ __host__ __device__ inline int lds_table_offset(int D, int nb, bool hist) {
 // LDS: edges [D][nb+1] | histogram [D][nb] (HIST) | integrand staging.
 // Partial row per workgroup: [S1.s, S1.c, S2.s, S2.c, hist[D][nb]].
 // ---------------------------------------------------------------------------
+// Minimum waves per SIMD an integrand asks of the iteration kernel (its
+// register budget): F::kMinWaves when declared, else 1 (no constraint).
+template <class F, class = void>
+struct MinWaves { static constexpr int value = 1; };
+template <class F>
+struct MinWaves<F, std::void_t<decltype(F::kMinWaves)>> { static constexpr int value = F::kMinWaves; };
+
 template <int D, class F, class Src, bool HIST>
-__global__ __launch_bounds__(BLOCK) void k_vegas_iter(VegasArgs a, F f, Src src, double* __restrict__ partials) {
+__global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasArgs a, F f, Src src,
+                                                                          double* __restrict__ partials) {
   extern __shared__ __align__(16) double lds[];
   const int nb = a.nb;
   double* se = lds;
