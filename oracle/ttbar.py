@@ -25,6 +25,11 @@ parametrisation; the readings used here are:
         * beta / (32 pi s_hat) * 0.3893793721e9 pb GeV^2,
     PDFs at mu^2 = m_t^2, fixed alpha_s, no cuts.
 
+Dynamic scale (the survey's next step on this path; the thesis's PDF tools
+evaluate xf at any (x, Q^2) and alpha_s(Q) by log-cubic interpolation):
+integrand_dynamic() sets mu^2 = s_hat/4 per event, with alpha_s(mu) from the
+PDF set's alpha_s table.
+
 Pins: tests/test_oracle_ttbar.py -- the partonic cross sections against
 their closed forms
   sigma_qq = 8 pi alpha_s^2/(27 s_hat) beta (1 + rho/2),
@@ -88,6 +93,27 @@ def phase_space(u, sqrt_s, mt):
     tau2 = 0.5 * (1.0 + beta * cos)
     return dict(tau=tau, y=y, cos=cos, jac=jac, x1=x1, x2=x2, shat=shat, rho=rho,
                 beta=beta, tau1=tau1, tau2=tau2)
+
+
+def integrand_dynamic(u, grid, alphas_table, sqrt_s, mt, gev2_to_pb):
+    """F(u) in pb with the scale set per event, mu^2 = s_hat/4 (the PDFs at
+    (x, mu^2) and alpha_s(mu) from the alpha_s table by the log-cubic rule);
+    otherwise as integrand()."""
+    from . import alphas as alphas_oracle
+    k = phase_space(u, sqrt_s, mt)
+    mu2 = k["shat"] / 4.0
+    f1 = pdf_oracle.interp(grid, k["x1"], mu2)
+    f2 = pdf_oracle.interp(grid, k["x2"], mu2)
+    a_s = alphas_oracle.interp(alphas_table, mu2)
+    g4 = (4.0 * math.pi * a_s) ** 2
+    mgg = m2_gg(k["tau1"], k["tau2"], k["rho"], g4)
+    mqq = m2_qq(k["tau1"], k["tau2"], k["rho"], g4)
+    lum_gg = f1[IDX[21]] * f2[IDX[21]]
+    lum_qq = np.zeros_like(lum_gg)
+    for q in (1, 2, 3, 4, 5):
+        lum_qq = lum_qq + f1[IDX[q]] * f2[IDX[-q]] + f1[IDX[-q]] * f2[IDX[q]]
+    dps = k["beta"] / (32.0 * math.pi * k["shat"])
+    return k["jac"] / k["tau"] * (lum_gg * mgg + lum_qq * mqq) * dps * gev2_to_pb
 
 
 def integrand(u, grid, sqrt_s, mt, alpha_s, gev2_to_pb):

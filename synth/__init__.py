@@ -12,9 +12,10 @@ from .pdfgrid import synthetic_pdf_grid, PdfGridData
 from .queries import pdf_queries
 from .batch import batch_specs, BatchSpec
 from .flowinit import he_init_segments
+from .alphas import synthetic_alphas, AlphasTable
 
 __all__ = [
     "C0", "C1", "C2", "C3", "C4", "C5", "C6", "FLAVOURS",
     "synthetic_pdf_grid", "PdfGridData", "pdf_queries",
-    "batch_specs", "BatchSpec", "he_init_segments",
+    "batch_specs", "BatchSpec", "he_init_segments", "synthetic_alphas", "AlphasTable",
 ]

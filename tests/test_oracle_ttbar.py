@@ -109,3 +109,43 @@ def test_hadronic_cross_section_vegas_vs_quadrature():
     assert res["sigma"] / res["mean"] < 5e-3
     # LO t tbar at 13 TeV is O(500 pb); the synthetic PDFs land in the same range
     assert 50.0 < total < 5000.0
+
+
+def test_dynamic_scale_hadronic_cross_section_vs_quadrature():
+    """mu^2 = s_hat/4 per event with running alpha_s: VEGAS on the oracle
+    integrand against 2-d quadrature of the closed-form partonic cross
+    sections, each evaluated with alpha_s and the PDFs at its own scale."""
+    from oracle.alphas import interp as alphas_interp
+    from oracle.pdf import interp
+    from synth import synthetic_alphas
+    grid = synthetic_pdf_grid()
+    table = synthetic_alphas(grid)
+    s = C2["sqrt_s"] ** 2
+    tau0 = 4 * MT * MT / s
+    n = 100
+    xg, wg = np.polynomial.legendre.leggauss(n)
+    uu, ww = 0.5 * (xg + 1), 0.5 * wg
+    total = 0.0
+    I = ttbar.IDX
+    for u1, w1 in zip(uu, ww):
+        tau = tau0 ** (1 - u1)
+        sh = tau * s
+        a_s = alphas_interp(table, [sh / 4])[0]
+        jt = tau * math.log(1 / tau0)
+        ly = math.log(1 / tau)
+        ys = (uu - 0.5) * ly
+        x1, x2 = math.sqrt(tau) * np.exp(ys), math.sqrt(tau) * np.exp(-ys)
+        f1 = interp(grid, x1, np.full(n, sh / 4))
+        f2 = interp(grid, x2, np.full(n, sh / 4))
+        gg = f1[I[21]] * f2[I[21]]
+        qq = sum(f1[I[q]] * f2[I[-q]] + f1[I[-q]] * f2[I[q]] for q in (1, 2, 3, 4, 5))
+        lum = (gg * ttbar.sigma_hat_gg(sh, MT, a_s) + qq * ttbar.sigma_hat_qq(sh, MT, a_s)) / tau
+        total += w1 * jt * ly * np.sum(ww * lum) * C2["gev2_to_pb"]
+    f = lambda u: ttbar.integrand_dynamic(u, grid, table, C2["sqrt_s"], MT, C2["gev2_to_pb"])
+    res = vegas.run(f, 3, 50, 1.5, 5, 40000, seed=C2["seed"])
+    assert abs(res["mean"] - total) < 4 * res["sigma"]
+    assert res["sigma"] / res["mean"] < 5e-3
+    # alpha_s(mu) <= alpha_s(m_t) ~ 0.108 < 0.118 for mu = sqrt(s_hat)/2 >= m_t: below the fixed-scale value
+    fixed = ttbar.integrand(np.random.default_rng(0).uniform(size=(2000, 3)), grid, C2["sqrt_s"], MT, AS,
+                            C2["gev2_to_pb"]).mean()
+    assert total < fixed
