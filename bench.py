@@ -378,6 +378,16 @@ def extra_ttbar_contracted(vgx, pdf, params, n):
     return extra_hadronic(vgx, pdf, vgx.TTBAR, np.concatenate([params, [1.0]]), C2["seed"], n)
 
 
+def extra_ttbar_dynamic(vgx, pdf, grid, params, n):
+    """The same t tbar workload with the scale set per event, mu^2 = s_hat/4,
+    and running alpha_s(mu) (mode 2): the full per-event 2-d stencil."""
+    import numpy as np
+    from synth import C2, synthetic_alphas
+    table = synthetic_alphas(grid)
+    vgx.pdf_set_alphas(pdf, table.q2_knots, table.values)
+    return extra_hadronic(vgx, pdf, vgx.TTBAR, np.concatenate([params, [2.0]]), C2["seed"], n)
+
+
 def extra_singletop(vgx, pdf, n):
     """LO s-channel single top (u dbar, c sbar -> t bbar) at 8 TeV, the
     thesis's own LO example, on the same fused path (full stencil)."""
@@ -536,6 +546,7 @@ def main():
             out["time_to_1e-4"]["gauss8"] = {"vegas": gv, "flow": gf}
     if args.extras:
         out["extras"] = {"ttbar_fixed_scale_contraction": extra_ttbar_contracted(vgx, pdf, params, n),
+                         "ttbar_dynamic_scale": extra_ttbar_dynamic(vgx, pdf, grid, params, n),
                          "drell_yan_1e7": extra_drellyan(vgx, pdf, n),
                          "single_top_s_1e7": extra_singletop(vgx, pdf, n),
                          "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),

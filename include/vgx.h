@@ -78,7 +78,11 @@ enum {
                          identical for every event at the fixed scale, is
                          contracted once per workgroup and each event does
                          the ln x direction only (same interpolant, FP32
-                         rounding differs)                                    */
+                         rounding differs); mode 2: the scale set per event,
+                         mu^2 = s_hat/4, PDFs at (x, mu^2) and alpha_s(mu)
+                         from the PDF's alpha_s table (pdf_set_alphas;
+                         params[2] unused); the scales [m_top^2, s/4] must
+                         lie in one PDF subgrid and one alpha_s subgrid      */
   VGX_DRELLYAN = 4,   /* LO pp -> photon or Z -> l+ l- (massless leptons), d = 3,
                          (tau, y, cos theta*) map over the dilepton-mass
                          window m_lo < m_ll < m_hi.
@@ -141,6 +145,26 @@ vgx_status pdf_out_of_range(vgx_pdf* pdf, void* stream, int64_t* count_host);
 
 /* Grid limits in x and Q^2. */
 vgx_status pdf_bounds(const vgx_pdf* pdf, double* xmin, double* xmax, double* q2min, double* q2max);
+
+/* Attach an alpha_s(Q) table to a PDF context (sync; replaces any previous
+ * one).  Thesis, PDF chapter (alpha_s paragraphs): sets carry alpha_s at knots
+ * on the Q line, interpolated log-cubically with subgrids at the flavour
+ * thresholds.
+ *   n        : number of knots, >= 2.
+ *   q2_knots : host [n], ascending; a knot equal to its predecessor starts a
+ *              new subgrid (the threshold knot duplicated); each subgrid >= 2.
+ *   alphas   : host [n] values.
+ * Host arrays may be freed after the call.  VGX_EINVAL on malformed knots. */
+vgx_status pdf_set_alphas(vgx_pdf* pdf, int32_t n, const double* q2_knots, const double* alphas, void* stream);
+
+/* alpha_s at n scales (async): cubic Hermite in ln Q^2 with secant-average
+ * slopes on interior cells of the subgrid holding Q^2 (the upper subgrid at a
+ * threshold), linear on a subgrid's first and last cells, the top value
+ * above the last knot, NaN below the first (the thesis's rule there is
+ * garbled; read as out of range).
+ *   q2_dev  : device [n] FP64;  out_dev : device [n] FP64.
+ * VGX_EINVAL if no table is attached.  n = 0 is a no-op. */
+vgx_status pdf_alphas(const vgx_pdf* pdf, int64_t n, const double* q2_dev, double* out_dev, void* stream);
 
 void pdf_destroy(vgx_pdf* pdf);
 

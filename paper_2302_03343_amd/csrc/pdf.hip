@@ -140,6 +140,61 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
   }
 }
 
+// alpha_s(Q): log-cubic interpolation on the table's subgrids (thesis PDF
+// chapter, alpha_s paragraphs): cubic Hermite in ln Q^2 with secant-average
+// slopes on interior cells, linear on a subgrid's edge cells, the top value
+// above the last knot, NaN below the first.
+struct AlphasArgs {
+  int n_sub;
+  int nq[VGX_MAX_SUB];
+  int off[VGX_MAX_SUB + 1];
+  double q2_lo[VGX_MAX_SUB], q2_hi[VGX_MAX_SUB];
+  double top;
+};
+
+__global__ __launch_bounds__(256) void k_alphas(AlphasArgs g, int64_t n, const double* __restrict__ qq2,
+                                                const double* __restrict__ klq2, const double* __restrict__ kval,
+                                                double* __restrict__ out) {
+  extern __shared__ double lds[];
+  const int nt = g.off[g.n_sub];
+  double* sl = lds;        // ln Q^2 knots
+  double* sv = lds + nt;   // values
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) { sl[k] = klq2[k]; sv[k] = kval[k]; }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double q2 = qq2[q];
+    if (q2 > g.q2_hi[g.n_sub - 1]) { out[q] = g.top; continue; }
+    int s = -1;
+    for (int k = 0; k < g.n_sub; ++k) {
+      const bool last = (k == g.n_sub - 1);
+      if (q2 >= g.q2_lo[k] && (q2 < g.q2_hi[k] || (last && q2 <= g.q2_hi[k]))) s = k;
+    }
+    if (s < 0) { out[q] = (double)NAN; continue; }
+    const double* b = sl + g.off[s];
+    const double* v = sv + g.off[s];
+    const int nq = g.nq[s];
+    const double lb = log(q2);
+    int lo = 0, hi = nq - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (b[mid] <= lb) lo = mid; else hi = mid;
+    }
+    const int j = lo;
+    const double h = b[j + 1] - b[j];
+    const double t = (lb - b[j]) / h;
+    double r;
+    if (j >= 1 && j <= nq - 3) {
+      double c[4];
+      hermite_weights(t, h / (b[j] - b[j - 1]), h / (b[j + 2] - b[j + 1]), c);
+      r = c[0] * v[j - 1] + c[1] * v[j] + c[2] * v[j + 1] + c[3] * v[j + 2];
+    } else {
+      r = v[j] + t * (v[j + 1] - v[j]);
+    }
+    out[q] = r;
+  }
+}
+
 }  // namespace vgx
 
 using namespace vgx;
@@ -299,6 +354,78 @@ extern "C" void pdf_destroy(vgx_pdf* p) {
   if (!p) return;
   hipFree(p->x); hipFree(p->lx); hipFree(p->q2); hipFree(p->lq2);
   hipFree(p->v64); hipFree(p->v32); hipFree(p->oor);
-  free(p->h_x); free(p->h_q2);
+  hipFree(p->a_lq2); hipFree(p->a_val);
+  free(p->h_x); free(p->h_q2); free(p->h_aq2); free(p->h_aval);
   delete p;
+}
+
+extern "C" vgx_status pdf_set_alphas(vgx_pdf* p, int32_t n, const double* q2_knots, const double* alphas,
+                                     void* stream) {
+  VGX_CHECK(p && q2_knots && alphas, "pdf_set_alphas: null argument");
+  VGX_CHECK(n >= 2, "pdf_set_alphas: need at least 2 knots");
+  // subgrids: a knot equal to the previous one starts a new subgrid
+  int ns = 0, start = 0;
+  int nq[VGX_MAX_SUB], off[VGX_MAX_SUB + 1];
+  for (int k = 0; k < n; ++k) {
+    VGX_CHECK(q2_knots[k] > 0.0 && isfinite(alphas[k]), "pdf_set_alphas: knots must be > 0, values finite");
+    if (k > 0) {
+      VGX_CHECK(q2_knots[k] >= q2_knots[k - 1], "pdf_set_alphas: knots must be ascending");
+      if (q2_knots[k] == q2_knots[k - 1]) {
+        VGX_CHECK(ns < VGX_MAX_SUB - 1, "pdf_set_alphas: more than %d subgrids", VGX_MAX_SUB);
+        VGX_CHECK(k - start >= 2, "pdf_set_alphas: subgrid %d has < 2 knots", ns);
+        off[ns] = start; nq[ns] = k - start; ++ns; start = k;
+      }
+    }
+  }
+  VGX_CHECK(n - start >= 2, "pdf_set_alphas: subgrid %d has < 2 knots", ns);
+  off[ns] = start; nq[ns] = n - start; ++ns; off[ns] = n;
+  double* hq = (double*)malloc(sizeof(double) * n);
+  double* hv = (double*)malloc(sizeof(double) * n);
+  double* lq = (double*)malloc(sizeof(double) * n);
+  if (!hq || !hv || !lq) { free(hq); free(hv); free(lq); set_error("pdf_set_alphas: host allocation failed"); return VGX_ENOMEM; }
+  for (int k = 0; k < n; ++k) { hq[k] = q2_knots[k]; hv[k] = alphas[k]; lq[k] = log(q2_knots[k]); }
+  double *dl = nullptr, *dv = nullptr;
+  vgx_status s = dev_alloc((void**)&dl, sizeof(double) * n);
+  if (s == VGX_OK) s = dev_alloc((void**)&dv, sizeof(double) * n);
+  if (s == VGX_OK) {
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(dl, lq, sizeof(double) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dv, hv, sizeof(double) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "pdf_set_alphas copies", __FILE__, __LINE__);
+  }
+  free(lq);
+  if (s != VGX_OK) { hipFree(dl); hipFree(dv); free(hq); free(hv); return s; }
+  hipFree(p->a_lq2); hipFree(p->a_val); free(p->h_aq2); free(p->h_aval);
+  p->a_lq2 = dl; p->a_val = dv; p->h_aq2 = hq; p->h_aval = hv;
+  p->a_nsub = ns;
+  for (int k = 0; k < ns; ++k) { p->a_nq[k] = nq[k]; p->a_off[k] = off[k]; }
+  p->a_off[ns] = n;
+  return VGX_OK;
+}
+
+extern "C" vgx_status pdf_alphas(const vgx_pdf* p, int64_t n, const double* q2_dev, double* out_dev, void* stream) {
+  VGX_CHECK(p, "pdf_alphas: null context");
+  VGX_CHECK(n >= 0, "pdf_alphas: n < 0");
+  if (n == 0) return VGX_OK;
+  VGX_CHECK(p->a_nsub > 0, "pdf_alphas: no alpha_s table (pdf_set_alphas)");
+  VGX_CHECK(q2_dev && out_dev, "pdf_alphas: null device pointer");
+  AlphasArgs g{};
+  g.n_sub = p->a_nsub;
+  for (int s = 0; s < p->a_nsub; ++s) {
+    g.nq[s] = p->a_nq[s];
+    g.off[s] = p->a_off[s];
+    g.q2_lo[s] = p->h_aq2[p->a_off[s]];
+    g.q2_hi[s] = p->h_aq2[p->a_off[s] + p->a_nq[s] - 1];
+  }
+  g.off[p->a_nsub] = p->a_off[p->a_nsub];
+  g.top = p->h_aval[p->a_off[p->a_nsub] - 1];
+  const int block = 256;
+  const int64_t want = (n + block - 1) / block;
+  const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
+  const size_t lds = sizeof(double) * 2 * (size_t)p->a_off[p->a_nsub];
+  hipLaunchKernelGGL(k_alphas, dim3(grid), dim3(block), lds, (hipStream_t)stream, g, n, q2_dev, p->a_lq2, p->a_val,
+                     out_dev);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
 }

@@ -24,4 +24,13 @@ struct vgx_pdf {
   double* v64 = nullptr;              // [total q][n_x][fstride]  node values (FP64)
   float* v32 = nullptr;               // same, FP32 copy
   unsigned long long* oor = nullptr;  // out-of-range counter
+  // alpha_s(Q) table (optional; pdf_set_alphas): knots on the Q^2 line split
+  // into subgrids at duplicated knots
+  int a_nsub = 0;
+  int a_nq[VGX_MAX_SUB] = {0};
+  int a_off[VGX_MAX_SUB + 1] = {0};
+  double* h_aq2 = nullptr;            // host [total] knots
+  double* h_aval = nullptr;           // host [total] values
+  double* a_lq2 = nullptr;            // device [total] ln Q^2 knots
+  double* a_val = nullptr;            // device [total] values
 };

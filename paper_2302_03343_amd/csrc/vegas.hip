@@ -29,6 +29,7 @@
 #include "ttbar.h"
 #include "drellyan.h"
 #include "singletop.h"
+#include "ttbar_dyn.h"
 #include "vegas_internal.h"
 
 #include <math.h>
@@ -238,6 +239,8 @@ namespace {
 bool uses_pdf(int kind) { return kind == VGX_TTBAR || kind == VGX_DRELLYAN || kind == VGX_SINGLETOP; }
 
 size_t extra_lds_bytes(const vgx_vegas* v) {
+  if (v->kind == VGX_TTBAR && v->tt_dyn)
+    return sizeof(float) * (size_t)ttdyn_lds_floats(v->ttd.nxs, v->ttd.R, v->ttd.a_nq);
   if (v->kind == VGX_TTBAR) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->tt.pdf.nxs);
   if (v->kind == VGX_DRELLYAN) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->dy.pdf.nxs);
   if (v->kind == VGX_SINGLETOP) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->st.pdf.nxs);
@@ -250,7 +253,9 @@ size_t extra_lds_bytes(const vgx_vegas* v) {
 int hadronic_blocks_per_cu(const vgx_vegas* v) {
   int occ = 0;
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(3, v->nb, true) + extra_lds_bytes(v);
-  const void* k = v->kind == VGX_TTBAR      ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>)
+  const void* k = (v->kind == VGX_TTBAR && v->tt_dyn)
+                      ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbarDyn, PhiloxSrc<3>, true>)
+                  : v->kind == VGX_TTBAR    ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>)
                   : v->kind == VGX_DRELLYAN ? reinterpret_cast<const void*>(&k_vegas_iter<3, DrellYan, PhiloxSrc<3>, true>)
                                             : reinterpret_cast<const void*>(&k_vegas_iter<3, SingleTop, PhiloxSrc<3>, true>);
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, BLOCK, lds);
@@ -307,6 +312,73 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
   return VGX_OK;
 }
 
+// Index of the subgrid holding q2 in a list of subgrids (upper one at a
+// threshold, the last closed at its top), -1 if outside.
+int subgrid_of(const double* knots, const int* off, const int* nq, int n_sub, double q2) {
+  int sub = -1;
+  for (int k = 0; k < n_sub; ++k) {
+    const double lo = knots[off[k]], hi = knots[off[k] + nq[k] - 1];
+    const bool last = k == n_sub - 1;
+    if (q2 >= lo && (q2 < hi || (last && q2 <= hi))) sub = k;
+  }
+  return sub;
+}
+
+// cell j with q[j] <= v < q[j+1], clamped to [0, n - 2]
+int host_cell(const double* q, int n, double v) {
+  int j = 0;
+  while (j < n - 2 && q[j + 1] <= v) ++j;
+  return j;
+}
+
+// t tbar with mu^2 = s_hat/4 per event: the Q^2 rows the scales reach,
+// [m_t^2, s/4] plus the stencil margins, and the alpha_s subgrid holding them.
+vgx_status setup_ttbar_dynamic(TTDynConst& t, const vgx_pdf* pdf, double rs, double mt, double conv) {
+  VGX_CHECK(pdf->n_flav == TT_NF, "TTBAR needs an 11-flavour PDF (order -5..-1, g, 1..5)");
+  VGX_CHECK(pdf->n_x <= TT_MAX_NX && pdf->n_x >= 4, "TTBAR supports 4 .. %d x knots", TT_MAX_NX);
+  VGX_CHECK(pdf->a_nsub > 0, "TTBAR mode 2 needs an alpha_s table on the PDF (pdf_set_alphas)");
+  const double s = rs * rs, tau0 = 4.0 * mt * mt / s;
+  VGX_CHECK(tau0 >= pdf->h_x[0], "TTBAR: tau0 below the PDF x range");
+  const double mu2_lo = mt * mt, mu2_hi = s / 4.0;
+  const int sub = subgrid_of(pdf->h_q2, pdf->q_off, pdf->nq, pdf->n_sub, mu2_lo);
+  VGX_CHECK(sub >= 0 && sub == subgrid_of(pdf->h_q2, pdf->q_off, pdf->nq, pdf->n_sub, mu2_hi),
+            "TTBAR mode 2: the scales [m_t^2, s/4] must lie in one PDF subgrid");
+  const int nq = pdf->nq[sub];
+  VGX_CHECK(nq >= 4, "TTBAR mode 2: the PDF subgrid needs at least 4 Q^2 knots");
+  const double* q = pdf->h_q2 + pdf->q_off[sub];
+  const int jlo = host_cell(q, nq, mu2_lo), jhi = host_cell(q, nq, mu2_hi);
+  int r0 = jlo - 1 < nq - 4 ? jlo - 1 : nq - 4;
+  r0 = r0 < 0 ? 0 : r0;
+  int r1 = jhi + 2 > r0 + 3 ? jhi + 2 : r0 + 3;
+  r1 = r1 > nq - 1 ? nq - 1 : r1;
+  VGX_CHECK(r1 - r0 + 1 <= TD_MAX_ROWS, "TTBAR mode 2: the scales span more than %d Q^2 rows", TD_MAX_ROWS);
+  const int asub = subgrid_of(pdf->h_aq2, pdf->a_off, pdf->a_nq, pdf->a_nsub, mu2_lo);
+  VGX_CHECK(asub >= 0 && asub == subgrid_of(pdf->h_aq2, pdf->a_off, pdf->a_nq, pdf->a_nsub, mu2_hi),
+            "TTBAR mode 2: the scales [m_t^2, s/4] must lie in one alpha_s subgrid");
+  VGX_CHECK(pdf->a_nq[asub] <= TD_MAX_ALPHAS, "TTBAR mode 2: alpha_s subgrid has more than %d knots", TD_MAX_ALPHAS);
+  t.L0 = log(1.0 / tau0);
+  t.lns4 = log(s / 4.0);
+  t.pref = (float)(2.0 * conv / (32.0 * M_PI * s));
+  t.v32 = pdf->v32;
+  t.fstride = pdf->fstride;
+  t.lx = pdf->lx;
+  t.n_x = pdf->n_x;
+  int i0 = 0;
+  while (i0 < pdf->n_x - 2 && pdf->h_x[i0 + 1] <= tau0) ++i0;
+  t.ix0 = i0 >= 2 ? i0 - 2 : 0;
+  if (pdf->n_x - t.ix0 < 4) t.ix0 = pdf->n_x - 4;
+  t.nxs = pdf->n_x - t.ix0;
+  t.lq2 = pdf->lq2 + pdf->q_off[sub];
+  t.q_glob = pdf->q_off[sub];
+  t.nq = nq;
+  t.r0 = r0;
+  t.R = r1 - r0 + 1;
+  t.a_lq2 = pdf->a_lq2 + pdf->a_off[asub];
+  t.a_val = pdf->a_val + pdf->a_off[asub];
+  t.a_nq = pdf->a_nq[asub];
+  return VGX_OK;
+}
+
 // Build the device-side integrand parameters from the user's parameters.
 vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
   const int d = c->dim;
@@ -348,7 +420,12 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
       const double s = rs * rs;
       const double tau0 = 4.0 * mt * mt / s;
       const double mode = c->n_params >= 5 ? c->params[4] : 0.0;
-      VGX_CHECK(mode == 0.0 || mode == 1.0, "TTBAR mode must be 0 (full stencil) or 1 (fixed-scale contraction)");
+      VGX_CHECK(mode == 0.0 || mode == 1.0 || mode == 2.0,
+                "TTBAR mode must be 0 (full stencil), 1 (fixed-scale contraction) or 2 (scale per event)");
+      if (mode == 2.0) {
+        v->tt_dyn = 1;
+        return setup_ttbar_dynamic(v->ttd, c->pdf, rs, mt, conv);
+      }
       TTbarConst& t = v->tt;
       VGX_TRY(setup_pdf_rows(t.pdf, c->pdf, mt * mt, tau0, mode == 1.0, "TTBAR"));
       t.L0 = log(1.0 / tau0);
@@ -438,6 +515,11 @@ template <int D, class Src, bool HIST>
 vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
   if (v->kind == VGX_TTBAR) {
     if constexpr (D == 3) {
+      if (v->tt_dyn) {
+        TTbarDyn f{};
+        f.c = v->ttd;
+        return launch_iter_f<3, TTbarDyn, Src, HIST>(v, n, f, src);
+      }
       TTbar f{};
       f.c = v->tt;
       return launch_iter_f<3, TTbar, Src, HIST>(v, n, f, src);
@@ -500,6 +582,11 @@ template <int D>
 vgx_status launch_sample_d(vgx_vegas* v, int64_t first, int64_t n, int32_t it, double* u, double* g) {
   if (v->kind == VGX_TTBAR) {
     if constexpr (D == 3) {
+      if (v->tt_dyn) {
+        TTbarDyn f{};
+        f.c = v->ttd;
+        return launch_sample_f<3, TTbarDyn>(v, first, n, it, f, u, g);
+      }
       TTbar f{};
       f.c = v->tt;
       return launch_sample_f<3, TTbar>(v, first, n, it, f, u, g);

@@ -9,6 +9,7 @@
 #include "ttbar.h"
 #include "drellyan.h"
 #include "singletop.h"
+#include "ttbar_dyn.h"
 
 namespace vgx {
 
@@ -181,6 +182,8 @@ struct vgx_vegas {
   vgx::TTbarConst tt{};
   vgx::DYConst dy{};
   vgx::STConst st{};
+  vgx::TTDynConst ttd{};  // TTBAR mode 2 (scale set per event)
+  int tt_dyn = 0;
   int max_wg = 0;
   int pstride = 0;
   double* edges = nullptr;          // [dim][nb+1]

@@ -83,6 +83,8 @@ for _name, _res, _args in [
     ("pdf_interp", _S, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     ("pdf_out_of_range", _S, [_vp, _vp, C.POINTER(_i64)]),
     ("pdf_bounds", _S, [_vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64)]),
+    ("pdf_set_alphas", _S, [_vp, _i32, C.POINTER(_f64), C.POINTER(_f64), _vp]),
+    ("pdf_alphas", _S, [_vp, _i64, _vp, _vp, _vp]),
     ("pdf_destroy", None, [_vp]),
     ("vegas_create", _S, [C.POINTER(VegasCfg), _vp, C.POINTER(_vp)]),
     ("vegas_iterate", _S, [_vp, _i64, _i32, C.POINTER(IterResult)]),
@@ -215,6 +217,27 @@ def pdf_bounds(pdf):
     v = [_f64() for _ in range(4)]
     _check(_c["pdf_bounds"](pdf, *[C.byref(t) for t in v]), "pdf_bounds")
     return tuple(t.value for t in v)
+
+
+def pdf_set_alphas(pdf, q2_knots, alphas, stream=None):
+    """q2_knots: host (n,) ascending, a repeated knot starting a new subgrid
+    (or a list of per-subgrid arrays, concatenated here); alphas likewise."""
+    if isinstance(q2_knots, (list, tuple)):
+        q2_knots = np.concatenate([np.asarray(q, dtype=np.float64) for q in q2_knots])
+        alphas = np.concatenate([np.asarray(a, dtype=np.float64) for a in alphas])
+    q = np.ascontiguousarray(q2_knots, dtype=np.float64)
+    a = np.ascontiguousarray(alphas, dtype=np.float64)
+    if q.shape != a.shape:
+        raise ValueError("q2_knots and alphas differ in length")
+    _check(_c["pdf_set_alphas"](pdf, q.size, _hptr(q, _f64), _hptr(a, _f64), _stream(stream)), "pdf_set_alphas")
+
+
+def pdf_alphas(pdf, q2, out, stream=None):
+    import torch
+    n = q2.numel()
+    _check(_c["pdf_alphas"](pdf, n, _dptr(q2, torch.float64, n, "q2"), _dptr(out, torch.float64, n, "out"),
+                            _stream(stream)), "pdf_alphas")
+    return out
 
 
 def pdf_destroy(pdf):

@@ -158,3 +158,91 @@ def test_full_size_iteration_matches_oracle(vgx, pdf_ctx, c1_grid):
     assert r["s1"] == pytest.approx(math.fsum(parts1), rel=1e-5)
     assert r["s2"] == pytest.approx(math.fsum(parts2), rel=2e-5)
     assert np.allclose(h, hist, rtol=2e-5, atol=1e-6 * hist.sum() / 3)
+
+
+# --- scale set per event (mode 2): mu^2 = s_hat/4, alpha_s(mu) from the table
+
+
+def make_dyn(vgx, pdf_ctx, c1_grid, seed=C2["seed"]):
+    from synth import synthetic_alphas
+    table = synthetic_alphas(c1_grid)
+    vgx.pdf_set_alphas(pdf_ctx, table.q2_knots, table.values)
+    params = np.concatenate([PARAMS, [2.0]])
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], seed, 0, vgx.F32, params, pdf=pdf_ctx)
+    return v, table
+
+
+def near_knot_dyn(grid, x):
+    """Events within 1e-6 (relative) of an x knot or of a Q^2 knot at their
+    scale: the FP32 cell search may pick the neighbouring cell there."""
+    bad = near_knot(grid, x)
+    k = ttbar.phase_space(x, C2["sqrt_s"], C2["m_top"])
+    qk = np.concatenate(grid.q2_knots)
+    mu2 = k["shat"] / 4
+    i = np.clip(np.searchsorted(qk, mu2), 1, len(qk) - 1)
+    d = np.minimum(np.abs(mu2 - qk[i - 1]), np.abs(mu2 - qk[i])) / mu2
+    return bad | (d < 1e-6)
+
+
+@pytest.mark.parametrize("grid_kind", ["uniform", "adapted"])
+def test_dynamic_scale_per_event(vgx, pdf_ctx, c1_grid, grid_kind):
+    import torch
+    print(f"ttbar mode 2 per-event, {grid_kind} grid", flush=True)
+    v, table = make_dyn(vgx, pdf_ctx, c1_grid)
+    try:
+        if grid_kind == "adapted":
+            for it in range(3):
+                vgx.vegas_iterate(v, 200_000, it)
+                vgx.vegas_refine(v)
+        e = vgx.vegas_get_grid(v, 3, C2["n_bins"])
+        n = 50_000
+        g = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.vegas_sample(v, 0, n, 9, g=g)
+        got = g.cpu().numpy()
+    finally:
+        vgx.vegas_destroy(v)
+    u = sample_uniforms(C2["seed"], 0, 9, np.arange(n, dtype=np.uint64), 3)
+    x, jac, _ = ov.vegas_map(u, e)
+    ref = ttbar.integrand_dynamic(x, c1_grid, table, C2["sqrt_s"], C2["m_top"], C2["gev2_to_pb"]) * jac
+    keep = ~near_knot_dyn(c1_grid, x)
+    assert keep.sum() > 0.999 * n
+    err = np.abs(got - ref)
+    rel = err / np.abs(ref)
+    ok = (rel <= 1e-5) | (err <= 1e-7 * np.mean(np.abs(ref)))
+    assert ok[keep].all(), f"p99 rel {np.percentile(rel[keep], 99):.2e}, worst {rel[keep][~ok[keep]].max():.2e}"
+    assert np.mean(rel[keep] > 1e-5) < 5e-3
+
+
+def test_dynamic_scale_iteration_and_quadrature(vgx, pdf_ctx, c1_grid):
+    """One 2e5 iteration against the oracle's sums, then ten iterations of 1e6
+    against the quadrature with alpha_s and PDFs at mu^2 = s_hat/4."""
+    print("ttbar mode 2 sums and 10 x 1e6 vs quadrature", flush=True)
+    from tests.test_oracle_ttbar import dynamic_scale_quadrature
+    v, table = make_dyn(vgx, pdf_ctx, c1_grid)
+    try:
+        n = 200_000
+        r = vgx.vegas_iterate(v, n, 0)
+        vgx.vegas_refine(v)
+        for it in range(1, 10):
+            vgx.vegas_iterate(v, 1_000_000, it)
+            vgx.vegas_refine(v)
+        res = vgx.vegas_result(v)
+    finally:
+        vgx.vegas_destroy(v)
+    u = sample_uniforms(C2["seed"], 0, 0, np.arange(n, dtype=np.uint64), 3)
+    x, jac, _ = ov.vegas_map(u, ov.uniform_grid(3, C2["n_bins"]))
+    w = ttbar.integrand_dynamic(x, c1_grid, table, C2["sqrt_s"], C2["m_top"], C2["gev2_to_pb"]) * jac
+    assert r["s1"] == pytest.approx(math.fsum(w), rel=1e-5)
+    assert r["s2"] == pytest.approx(math.fsum(w * w), rel=2e-5)
+    total = dynamic_scale_quadrature(c1_grid, table)
+    assert abs(res["mean"] - total) < 4 * res["sigma"] + 2e-5 * total
+    assert res["sigma"] / res["mean"] < 2e-3
+
+
+def test_dynamic_scale_needs_alphas(vgx, c1_grid):
+    pdf = vgx.pdf_create(c1_grid.x_knots, c1_grid.q2_knots, c1_grid.xf)
+    try:
+        with pytest.raises(vgx.VgxError):
+            vgx.vegas_create(vgx.TTBAR, 3, 50, 1.5, 1, 0, vgx.F32, np.concatenate([PARAMS, [2.0]]), pdf=pdf)
+    finally:
+        vgx.pdf_destroy(pdf)

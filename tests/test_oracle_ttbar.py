@@ -111,15 +111,11 @@ def test_hadronic_cross_section_vegas_vs_quadrature():
     assert 50.0 < total < 5000.0
 
 
-def test_dynamic_scale_hadronic_cross_section_vs_quadrature():
-    """mu^2 = s_hat/4 per event with running alpha_s: VEGAS on the oracle
-    integrand against 2-d quadrature of the closed-form partonic cross
-    sections, each evaluated with alpha_s and the PDFs at its own scale."""
+def dynamic_scale_quadrature(grid, table):
+    """2-d quadrature of the closed-form partonic cross sections, each with
+    alpha_s and the PDFs at its own scale mu^2 = s_hat/4 (pb)."""
     from oracle.alphas import interp as alphas_interp
     from oracle.pdf import interp
-    from synth import synthetic_alphas
-    grid = synthetic_pdf_grid()
-    table = synthetic_alphas(grid)
     s = C2["sqrt_s"] ** 2
     tau0 = 4 * MT * MT / s
     n = 100
@@ -141,6 +137,17 @@ def test_dynamic_scale_hadronic_cross_section_vs_quadrature():
         qq = sum(f1[I[q]] * f2[I[-q]] + f1[I[-q]] * f2[I[q]] for q in (1, 2, 3, 4, 5))
         lum = (gg * ttbar.sigma_hat_gg(sh, MT, a_s) + qq * ttbar.sigma_hat_qq(sh, MT, a_s)) / tau
         total += w1 * jt * ly * np.sum(ww * lum) * C2["gev2_to_pb"]
+    return total
+
+
+def test_dynamic_scale_hadronic_cross_section_vs_quadrature():
+    """mu^2 = s_hat/4 per event with running alpha_s: VEGAS on the oracle
+    integrand against 2-d quadrature of the closed-form partonic cross
+    sections, each evaluated with alpha_s and the PDFs at its own scale."""
+    from synth import synthetic_alphas
+    grid = synthetic_pdf_grid()
+    table = synthetic_alphas(grid)
+    total = dynamic_scale_quadrature(grid, table)
     f = lambda u: ttbar.integrand_dynamic(u, grid, table, C2["sqrt_s"], MT, C2["gev2_to_pb"])
     res = vegas.run(f, 3, 50, 1.5, 5, 40000, seed=C2["seed"])
     assert abs(res["mean"] - total) < 4 * res["sigma"]
