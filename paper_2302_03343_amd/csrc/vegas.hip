@@ -108,6 +108,10 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   F ff = f;
   if constexpr (F::kStage) ff.stage(extra);
   __syncthreads();
+  // The epilogue rebuilds the thread index from the wave index (uniform, so
+  // a scalar register) and the lane (mbcnt), so that no vector register has
+  // to carry it across the sample loop.
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   Comp c1, c2;
   double p1 = 0.0, p2 = 0.0;
@@ -138,17 +142,18 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
 
   __shared__ double red[4][BLOCK / 64];
   const double v0 = wave_sum(c1.s), v1 = wave_sum(c1.c), v2 = wave_sum(c2.s), v3 = wave_sum(c2.c);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int tid = wv * 64 + lane;
   if (lane == 0) { red[0][wv] = v0; red[1][wv] = v1; red[2][wv] = v2; red[3][wv] = v3; }
   __syncthreads();
   double* row = partials + (size_t)blockIdx.x * a.pstride;
-  if (threadIdx.x < 4) {
+  if (tid < 4) {
     double s = 0.0;
-    for (int k = 0; k < BLOCK / 64; ++k) s += red[threadIdx.x][k];
-    row[threadIdx.x] = s;
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[tid][k];
+    row[tid] = s;
   }
   if (HIST)
-    for (int k = threadIdx.x; k < D * nb; k += BLOCK) row[4 + k] = sh[k];
+    for (int k = tid; k < D * nb; k += BLOCK) row[4 + k] = sh[k];
 }
 
 // ---------------------------------------------------------------------------
