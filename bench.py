@@ -79,8 +79,10 @@ def measured_traffic(events_per_launch):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    # the GPU's clocks take some 100 steps of sustained load (about 25 ms) to
+    # settle; a short warm-up times the ramp instead of the kernel
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--events", type=int, default=None, help="events per iteration (default 1e7)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-flow", action="store_true", help="skip the flow comparison")

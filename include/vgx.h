@@ -247,7 +247,8 @@ void* vegas_stream(vgx_vegas* v);
 
 /* Kernel timing (for measurement): when enabled, HIP events on the
  * context's stream bracket every fused sampling kernel (recording does not
- * synchronise); vegas_kernel_time (sync) returns the summed milliseconds and
+ * synchronise; the events carry no system-scope fence, so they add no cache
+ * write-back); vegas_kernel_time (sync) returns the summed milliseconds and
  * the number of launches since timing was enabled. */
 vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable);
 vgx_status vegas_kernel_time(vgx_vegas* v, double* ms_host, int64_t* launches_host);

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchItem* __restric
     if (col >= 4 && col < ncols) it.hist[col - 4] = t.value();
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  if (blockIdx.x == 0 && threadIdx.x < 64)
     finalize_record(ss[0][0] + ss[0][1], ss[0][2] + ss[0][3], it.n, it.rec, it.k_rec, it.comb);
 }
 

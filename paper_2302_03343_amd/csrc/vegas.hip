@@ -158,48 +158,66 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
 
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of the partial rows.  Workgroup b owns the 8 columns
-// 8b .. 8b+7; its 128 row groups sum the rows r = g, g+128, ... with
-// compensation and are then combined in group order.  Workgroup 0 (which
-// owns S1 and S2) turns (S1, S2, n) into the iteration record and updates
-// the combination.
+// 8b .. 8b+7.  Thread (g, c) of its 128 row groups sums rows g, g+128, ...
+// of column c with compensation, after issuing all of its loads (at most
+// RMAXR); the groups are then merged in a fixed order: across the 8 groups
+// of a wave by shuffles, then across the 16 waves through LDS.  Workgroup 0
+// (which owns S1 and S2) turns (S1, S2, n) into the iteration record and
+// updates the combination.
 // ---------------------------------------------------------------------------
 constexpr int RBLOCK = 1024;
 constexpr int RCOLS = 8;
 constexpr int RGROUPS = RBLOCK / RCOLS;
+constexpr int RMAXR = 16;
+constexpr int RMAXROWS = RGROUPS * RMAXR;
 
 __global__ __launch_bounds__(RBLOCK) void k_reduce(const double* __restrict__ partials, int rows, int pstride,
                                                    int ncols, double* __restrict__ hist_out, int64_t n,
                                                    IterRecord* __restrict__ rec, int k_rec, Combined* __restrict__ comb) {
-  __shared__ double ss[RGROUPS][RCOLS], sc[RGROUPS][RCOLS];
+  __shared__ double ss[RBLOCK / 64][RCOLS], sc[RBLOCK / 64][RCOLS];
+  __shared__ double tot[RCOLS];
   const int cl = threadIdx.x % RCOLS, grp = threadIdx.x / RCOLS;
   const int col = blockIdx.x * RCOLS + cl;
   Comp acc;
-  if (col < ncols)
-    for (int r = grp; r < rows; r += RGROUPS) acc.add(partials[(size_t)r * pstride + col]);
-  ss[grp][cl] = acc.s;
-  sc[grp][cl] = acc.c;
-  __syncthreads();
-  // pairwise merge of the row groups' compensated sums, in a fixed tree
-  for (int h = RGROUPS / 2; h > 0; h >>= 1) {
-    if (grp < h) {
-      Comp t;
-      t.s = ss[grp][cl];
-      t.c = sc[grp][cl];
-      t.add(ss[grp + h][cl]);
-      t.c += sc[grp + h][cl];
-      ss[grp][cl] = t.s;
-      sc[grp][cl] = t.c;
+  if (col < ncols) {
+    double v[RMAXR];
+#pragma unroll
+    for (int q = 0; q < RMAXR; ++q) {
+      const int r = grp + q * RGROUPS;
+      v[q] = r < rows ? partials[(size_t)r * pstride + col] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RMAXR; ++q)
+      if (grp + q * RGROUPS < rows) acc.add(v[q]);
   }
+  // lanes l and l^8, l^16, l^32 hold the same column
+#pragma unroll
+  for (int m = RCOLS; m < 64; m <<= 1) {
+    const double os = __shfl_xor(acc.s, m, 64), oc = __shfl_xor(acc.c, m, 64);
+    acc.add(os);
+    acc.c += oc;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane < RCOLS) {
+    ss[wv][lane] = acc.s;
+    sc[wv][lane] = acc.c;
+  }
+  __syncthreads();
   if (threadIdx.x < RCOLS) {
-    const double v = ss[0][cl] + sc[0][cl];
-    ss[0][cl] = v;
+    Comp t;
+    t.s = ss[0][cl];
+    t.c = sc[0][cl];
+    for (int k = 1; k < RBLOCK / 64; ++k) {
+      t.add(ss[k][cl]);
+      t.c += sc[k][cl];
+    }
+    const double v = t.value();
+    tot[cl] = v;
     if (col >= 4 && col < ncols) hist_out[col - 4] = v;
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    finalize_record(ss[0][0] + ss[0][1], ss[0][2] + ss[0][3], n, rec, k_rec, comb);
+  if (blockIdx.x == 0 && threadIdx.x < 64)
+    finalize_record(tot[0] + tot[1], tot[2] + tot[3], n, rec, k_rec, comb);
 }
 
 __global__ __launch_bounds__(64) void k_refine(double* __restrict__ edges, const double* __restrict__ hist, int nb,
@@ -698,6 +716,7 @@ vgx_status launch_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t it, dou
 }
 
 vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n) {
+  VGX_CHECK(rows >= 1 && rows <= RMAXROWS, "reduce: %d partial rows (1..%d)", rows, RMAXROWS);
   const int blocks = (ncols + RCOLS - 1) / RCOLS;
   hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(RBLOCK), 0, v->stream, v->partials, rows, v->pstride, ncols,
                      v->hist, n, v->rec, v->n_rec, v->comb);
@@ -748,6 +767,7 @@ extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_veg
   vgx_status s = prepare_params(v, c);
   if (s != VGX_OK) { delete v; return s; }
   v->max_wg = device_cus() * (uses_pdf(c->kind) ? hadronic_blocks_per_cu(v) : 8);
+  v->max_wg = v->max_wg < RMAXROWS ? v->max_wg : RMAXROWS;  // rows one reduction takes
   v->pstride = 4 + v->dim * v->nb;
   const size_t ne = (size_t)v->dim * (v->nb + 1);
   do {
@@ -903,7 +923,10 @@ extern "C" void* vegas_stream(vgx_vegas* v) { return v ? (void*)v->stream : null
 extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
   VGX_CHECK(v, "vegas_set_timing: null context");
   if (enable && !v->ev[0]) {
-    for (int k = 0; k < 2 * vgx_vegas::kTimerPairs; ++k) VGX_HIP(hipEventCreate(&v->ev[k]));
+    // the events only time: no system-scope fence (cache write-back and
+    // invalidation) at each record, which would slow the work they bracket
+    for (int k = 0; k < 2 * vgx_vegas::kTimerPairs; ++k)
+      VGX_HIP(hipEventCreateWithFlags(&v->ev[k], hipEventDisableSystemFence));
   }
   v->timing = enable != 0;
   v->t_pending = 0;

@@ -52,13 +52,28 @@ __device__ __forceinline__ double grid_map(const double (&u)[D], const double* s
   return jac;
 }
 
+// Butterfly merge of compensated sums over the 64 lanes of a wave, in a fixed
+// order (partner distance 1, 2, 4, ..., 32).
+__device__ __forceinline__ Comp wave_merge(Comp a) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const double os = __shfl_xor(a.s, m, 64), oc = __shfl_xor(a.c, m, 64);
+    a.add(os);
+    a.c += oc;
+  }
+  return a;
+}
+
 // Estimate of one iteration from its compensated sums, stored as record
 // k_rec, then the inverse-variance combination of the finite records
 // 0..k_rec with chi^2/dof:  E = S1/n, var(E) = max(S2/n - E^2, 0)/(n-1);
 // E_bar = S^2 sum E_i/S_i^2, 1/S^2 = sum 1/S_i^2,
 // chi^2/dof = sum (E_i - E_bar)^2/S_i^2/(M-1).  A zero variance makes that
-// estimate exact (sigma 0).  Single-thread device code.
+// estimate exact (sigma 0).  Called by the 64 lanes of one wave, which split
+// the records (lane l takes l, l+64, ...) so that the cost per iteration does
+// not grow with the number of stored estimates; lane 0 writes the results.
 __device__ inline void finalize_record(double s1, double s2, int64_t n, IterRecord* rec, int k_rec, Combined* comb) {
+  const int lane = threadIdx.x & 63;
   IterRecord r;
   r.s1 = s1;
   r.s2 = s2;
@@ -68,38 +83,58 @@ __device__ inline void finalize_record(double s1, double s2, int64_t n, IterReco
   r.var = n > 1 ? (m2 > 0.0 ? m2 : 0.0) / (double)(n - 1) : 0.0;
   r.finite = isfinite(r.mean) && isfinite(r.var);
   r.pad = 0;
-  rec[k_rec] = r;
-  Combined c{0.0, 0.0, 0.0, 0, 0};
-  int zero_var = -1;
-  int used = 0;
-  for (int k = 0; k <= k_rec; ++k) {
-    if (!rec[k].finite) continue;
+  if (lane == 0) rec[k_rec] = r;
+  // record k_rec is taken from registers: the other lanes must not read
+  // the store lane 0 has just issued
+  auto mean_var = [&](int k, double& mean, double& var) -> bool {
+    if (k == k_rec) { mean = r.mean; var = r.var; return r.finite; }
+    mean = rec[k].mean;
+    var = rec[k].var;
+    return rec[k].finite;
+  };
+  int used = 0, zero_var = MAX_RECORDS;
+  Comp wsum, msum;
+  for (int k = lane; k <= k_rec; k += 64) {
+    double mean, var;
+    if (!mean_var(k, mean, var)) continue;
     ++used;
-    if (rec[k].var == 0.0 && zero_var < 0) zero_var = k;
-  }
-  if (zero_var >= 0) {
-    c.mean = rec[zero_var].mean;
-  } else if (used > 0) {
-    Comp wsum, msum;
-    for (int k = 0; k <= k_rec; ++k) {
-      if (!rec[k].finite) continue;
-      wsum.add(1.0 / rec[k].var);
-      msum.add(rec[k].mean / rec[k].var);
+    if (var == 0.0) {
+      zero_var = k < zero_var ? k : zero_var;
+    } else {
+      wsum.add(1.0 / var);
+      msum.add(mean / var);
     }
-    c.mean = msum.value() / wsum.value();
-    c.sigma = sqrt(1.0 / wsum.value());
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    used += __shfl_xor(used, m, 64);
+    const int o = __shfl_xor(zero_var, m, 64);
+    zero_var = o < zero_var ? o : zero_var;
+  }
+  Combined c{0.0, 0.0, 0.0, used, 0};
+  if (zero_var < MAX_RECORDS) {
+    double mean, var;
+    mean_var(zero_var, mean, var);
+    c.mean = mean;
+  } else if (used > 0) {
+    wsum = wave_merge(wsum);
+    msum = wave_merge(msum);
+    // lane 0's combination is the one written; every lane uses it
+    c.mean = __shfl(msum.value() / wsum.value(), 0, 64);
+    c.sigma = sqrt(1.0 / __shfl(wsum.value(), 0, 64));
     if (used > 1) {
       Comp chi;
-      for (int k = 0; k <= k_rec; ++k) {
-        if (!rec[k].finite) continue;
-        const double dd = rec[k].mean - c.mean;
-        chi.add(dd * dd / rec[k].var);
+      for (int k = lane; k <= k_rec; k += 64) {
+        double mean, var;
+        if (!mean_var(k, mean, var)) continue;
+        const double dd = mean - c.mean;
+        chi.add(dd * dd / var);
       }
+      chi = wave_merge(chi);
       c.chi2_dof = chi.value() / (double)(used - 1);
     }
   }
-  c.n_used = used;
-  *comb = c;
+  if (lane == 0) *comb = c;
 }
 
 // Lepage's refinement of one dimension, by one 64-thread workgroup:

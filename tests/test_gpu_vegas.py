@@ -257,3 +257,71 @@ def test_invalid_arguments_raise(vgx):
             vgx.vegas_iterate(v, 1, 0)
     finally:
         vgx.vegas_destroy(v)
+
+
+def test_combination_over_many_records(vgx):
+    """More stored estimates than lanes in a wave, and a zero-variance
+    estimate in the middle of the run (index 70)."""
+    import torch
+    print("combination over 82 records", flush=True)
+    dim, nb = 2, 30
+    v = make(vgx, GAUSS, dim, nb, params=gauss_params(dim, 0.5, 0.01))
+    try:
+        for it in range(70):
+            vgx.vegas_iterate_async(v, 20_000, it)
+            vgx.vegas_refine(v)
+        res = vgx.vegas_result(v)
+        per = vgx.vegas_results(v)
+        assert len(per) == 70 and res["n_used"] == 70
+        assert all(p["var"] > 0.0 for p in per)
+        m, s, c = ov.combine([p["mean"] for p in per], [p["var"] for p in per])
+        assert res["mean"] == pytest.approx(m, rel=1e-14)
+        assert res["sigma"] == pytest.approx(s, rel=1e-13)
+        assert res["chi2_dof"] == pytest.approx(c, rel=1e-10)
+        # points far from the peak: every weight underflows to 0 -> var 0
+        y = torch.full((dim, 1000), 0.999, dtype=torch.float64, device="cuda")
+        r = vgx.vegas_iterate_points(v, y, None)
+        assert r["s1"] == 0.0 and r["var"] == 0.0
+        for it in range(70, 81):
+            vgx.vegas_iterate_async(v, 20_000, it)
+            vgx.vegas_refine(v)
+        res = vgx.vegas_result(v)
+        per = vgx.vegas_results(v)
+        assert len(per) == 82 and per[70]["var"] == 0.0
+        m, s, c = ov.combine([p["mean"] for p in per], [p["var"] for p in per])
+        assert (m, s, c) == (0.0, 0.0, 0.0)
+        assert (res["mean"], res["sigma"], res["chi2_dof"], res["n_used"]) == (0.0, 0.0, 0.0, 82)
+    finally:
+        vgx.vegas_destroy(v)
+
+
+def test_run_to_run_agreement(vgx):
+    """Two identical runs: an iteration's sums on a given grid are
+    reproduced bit for bit (per-thread sums, fixed-order reductions); the
+    histograms are accumulated with LDS atomics whose order varies between
+    runs, so they and the refined grids agree to rounding only."""
+    print("run-to-run agreement, gauss 3-d", flush=True)
+    dim, nb = 3, 50
+    runs = []
+    for _ in range(2):
+        v = make(vgx, GAUSS, dim, nb, seed=11, params=gauss_params(dim, 0.4, 0.1))
+        try:
+            hists, grids = [], []
+            for it in range(4):
+                vgx.vegas_iterate(v, 300_000, it)
+                hists.append(vgx.vegas_get_hist(v, dim, nb))
+                vgx.vegas_refine(v)
+                grids.append(vgx.vegas_get_grid(v, dim, nb))
+            runs.append((vgx.vegas_results(v), hists, grids, vgx.vegas_result(v)))
+        finally:
+            vgx.vegas_destroy(v)
+    (ra, ha, ga, ca), (rb, hb, gb, cb) = runs
+    assert (ra[0]["s1"], ra[0]["s2"]) == (rb[0]["s1"], rb[0]["s2"])
+    for a, b in zip(ra, rb):
+        assert a["mean"] == pytest.approx(b["mean"], rel=1e-12)
+        assert a["var"] == pytest.approx(b["var"], rel=1e-10)
+    for a, b in zip(ha, hb):
+        assert np.allclose(a, b, rtol=1e-12, atol=0.0)
+    for a, b in zip(ga, gb):
+        assert np.max(np.abs(a - b)) < 1e-13
+    assert ca["mean"] == pytest.approx(cb["mean"], rel=1e-12)
