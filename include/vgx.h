@@ -101,6 +101,8 @@ enum {
                          VGX_TTBAR                                          */
 };
 enum { VGX_F64 = 0, VGX_F32 = 1 };   /* integrand / output precision          */
+/* PDF / alpha_s behaviour outside the grid (pdf_set_extrapolation) */
+enum { VGX_EXTRAP_ERROR = 0, VGX_EXTRAP_FREEZE = 1, VGX_EXTRAP_CONTINUE = 2 };
 
 #define VGX_MAX_DIM 12
 #define VGX_MAX_BINS 256
@@ -133,8 +135,11 @@ vgx_status pdf_create(const vgx_pdf_desc* desc, void* stream, vgx_pdf** out);
  *   out_dev       : device [n_flav][n] of that type.
  * Log-bicubic where the 4x4 stencil exists in both axes, bilinear
  * otherwise; subgrid chosen with the upper one winning at a threshold.
- * Queries outside the grid produce NaN in all flavours and are counted
- * (see pdf_out_of_range).  n = 0 is a no-op. */
+ * Queries outside the grid follow the context's extrapolation mode
+ * (pdf_set_extrapolation); those it gives no value (every such query in
+ * VGX_EXTRAP_ERROR; x > x_max, x <= 0, Q^2 <= 0 or non-finite points in the
+ * others) produce NaN in all flavours and are counted (pdf_out_of_range).
+ * n = 0 is a no-op. */
 vgx_status pdf_interp(const vgx_pdf* pdf, int64_t n, const double* x_dev, const double* q2_dev,
                       int32_t out_dtype, void* out_dev, void* stream);
 
@@ -142,6 +147,29 @@ vgx_status pdf_interp(const vgx_pdf* pdf, int64_t n, const double* x_dev, const 
  * this function (sync on `stream`); resets the counter.  Returns VGX_ERANGE
  * if the count is non-zero. */
 vgx_status pdf_out_of_range(vgx_pdf* pdf, void* stream, int64_t* count_host);
+
+/* Behaviour outside the grid for pdf_interp and pdf_alphas (thesis PDF
+ * chapter, LHAPDF extrapolation paragraphs and the alpha_s paragraph):
+ *   VGX_EXTRAP_ERROR    (default) no value: NaN, counted.
+ *   VGX_EXTRAP_FREEZE   the value at the nearest grid point (x, Q^2 clamped
+ *                       to the grid's ranges); alpha_s: its lowest-knot value.
+ *   VGX_EXTRAP_CONTINUE the legacy continuation: below x_min a straight line
+ *                       in ln x through the values at the two lowest x knots
+ *                       (through ln xf when both exceed 1e-3, else through xf);
+ *                       above Q^2_max the same in ln Q^2 through the top two
+ *                       knots; below Q^2_min xf = G0 r^((gamma-1) r + 1),
+ *                       r = Q^2/Q^2_min, G0 = xf(x, Q^2_min), gamma =
+ *                       d ln xf/d ln Q^2 at Q^2_min from the grid just above
+ *                       it; x rule first where both are outside; no value
+ *                       above x_max.  alpha_s below its lowest knot: the
+ *                       straight-line rule in ln Q^2 through the two lowest
+ *                       knots.
+ * alpha_s above its top knot is the top value in every mode.  The fused
+ * integrands never query outside the grid (their ranges are checked when a
+ * context is created), so the mode does not affect them.  VGX_EINVAL on an
+ * unknown mode, or for CONTINUE on a grid with fewer than two x knots or two
+ * Q^2 knots in its lowest subgrid. */
+vgx_status pdf_set_extrapolation(vgx_pdf* pdf, int32_t mode);
 
 /* Grid limits in x and Q^2. */
 vgx_status pdf_bounds(const vgx_pdf* pdf, double* xmin, double* xmax, double* q2min, double* q2max);
@@ -160,8 +188,9 @@ vgx_status pdf_set_alphas(vgx_pdf* pdf, int32_t n, const double* q2_knots, const
 /* alpha_s at n scales (async): cubic Hermite in ln Q^2 with secant-average
  * slopes on interior cells of the subgrid holding Q^2 (the upper subgrid at a
  * threshold), linear on a subgrid's first and last cells, the top value
- * above the last knot, NaN below the first (the thesis's rule there is
- * garbled; read as out of range).
+ * above the last knot; below the first knot as the context's extrapolation
+ * mode says (NaN by default; the thesis's rule there is garbled and read as
+ * the straight-line continuation); NaN for Q^2 <= 0 or non-finite.
  *   q2_dev  : device [n] FP64;  out_dev : device [n] FP64.
  * VGX_EINVAL if no table is attached.  n = 0 is a no-op. */
 vgx_status pdf_alphas(const vgx_pdf* pdf, int64_t n, const double* q2_dev, double* out_dev, void* stream);

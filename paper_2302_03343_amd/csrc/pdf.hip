@@ -16,6 +16,7 @@
 #include "pdf_internal.h"
 
 #include <math.h>
+#include <type_traits>
 #include <stdlib.h>
 
 namespace vgx {
@@ -55,10 +56,127 @@ __device__ __forceinline__ int find_cell(const double* a, int n, double key) {
   return lo;
 }
 
+// ---------------------------------------------------------------------------
+// Outside the grid (thesis PDF chapter, LHAPDF extrapolation paragraphs).
+// FREEZE interpolates at the nearest grid point.  CONTINUE is the legacy
+// continuation, one flavour at a time (the path is rare, registers matter):
+//   low x:   straight line in ln x through the values at x_0 and x_1 at the
+//            query's Q^2 -- through ln xf when both exceed 1e-3, else xf;
+//   high Q^2: the same in ln Q^2 through the top subgrid's last two rows;
+//   low Q^2: xf = G0 r^((gamma - 1) r + 1), r = Q^2/Q^2_min, with gamma the
+//            logarithmic derivative d ln xf/d ln Q^2 at Q^2_min of what the
+//            grid gives just above it (lowest bilinear cell, or its low-x
+//            continuation), which keeps ln xf C^1 across Q^2_min;
+//   both outside: x rule first, on the rows the Q^2 rule reads.
+// Rows are read with their edge cells' rule: linear in ln x.
+// ---------------------------------------------------------------------------
+constexpr double kPositive = 1e-3;
+
+// Fraction t of the line through (0, y0), (1, y1): in ln y when both
+// values exceed 1e-3, else in y.
+__device__ __forceinline__ double continue_line(double t, double y0, double y1) {
+  if (y0 > kPositive && y1 > kPositive) {
+    const double l0 = log(y0);
+    return exp(l0 + t * (log(y1) - l0));
+  }
+  return y0 + t * (y1 - y0);
+}
+
+template <typename ValT>
+__device__ __forceinline__ double node_val(const ValT* vals, int n_x, int nf, int row, int ix, int f) {
+  return (double)vals[((int64_t)row * n_x + ix) * nf + f];
+}
+
+// Flavour f on global row `row` at ln x = a (cell i, x_0 <= x), linear in a;
+// below x_0 (i < 0) the low-x line through the row's first two nodes.
+template <typename ValT>
+__device__ double row_value(const ValT* vals, const double* slx, int n_x, int nf, int row, int i, double a, int f) {
+  if (i < 0)
+    return continue_line((a - slx[0]) / (slx[1] - slx[0]), node_val(vals, n_x, nf, row, 0, f),
+                         node_val(vals, n_x, nf, row, 1, f));
+  const double t = (a - slx[i]) / (slx[i + 1] - slx[i]);
+  const double v0 = node_val(vals, n_x, nf, row, i, f), v1 = node_val(vals, n_x, nf, row, i + 1, f);
+  return v0 + t * (v1 - v0);
+}
+
+// The interpolator's value for flavour f in cell (i, j) of subgrid s at
+// (a, b) = (ln x, ln Q^2): the same weights and summation order as the
+// all-flavour loop of k_pdf_interp.
+template <typename ValT>
+__device__ double cell_value(const PdfKernelArgs& g, const ValT* vals, const double* slx, const double* slq2, int nf,
+                             int s, int i, int j, double a, double b, int f) {
+  const int nq = g.nq[s];
+  const double* lq = slq2 + g.q_off[s];
+  const ValT* V = vals + (int64_t)g.q_off[s] * g.n_x * nf;
+  double acc = 0.0;
+  if (i >= 1 && i <= g.n_x - 3 && j >= 1 && j <= nq - 3) {
+    const double ha = slx[i + 1] - slx[i];
+    const double hb = lq[j + 1] - lq[j];
+    double cx[4], cq[4];
+    hermite_weights((a - slx[i]) / ha, ha / (slx[i] - slx[i - 1]), ha / (slx[i + 2] - slx[i + 1]), cx);
+    hermite_weights((b - lq[j]) / hb, hb / (lq[j] - lq[j - 1]), hb / (lq[j + 2] - lq[j + 1]), cq);
+    for (int r = 0; r < 4; ++r)
+      for (int k = 0; k < 4; ++k)
+        acc = fma(cq[r] * cx[k], (double)V[((int64_t)(j - 1 + r) * g.n_x + (i - 1 + k)) * nf + f], acc);
+  } else {
+    const double ta = (a - slx[i]) / (slx[i + 1] - slx[i]);
+    const double tb = (b - lq[j]) / (lq[j + 1] - lq[j]);
+    const double w[4] = {(1.0 - ta) * (1.0 - tb), ta * (1.0 - tb), (1.0 - ta) * tb, ta * tb};
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 2; ++k)
+        acc = fma(w[2 * r + k], (double)V[((int64_t)(j + r) * g.n_x + (i + k)) * nf + f], acc);
+  }
+  return acc;
+}
+
+// CONTINUE value of flavour f at a point outside the grid with 0 < x <= x_max
+// and Q^2 > 0; s = subgrid holding Q^2 (or -1), i = x cell (-1 below x_0).
+template <typename ValT>
+__device__ double continue_value(const PdfKernelArgs& g, const ValT* vals, const double* sx, const double* slx,
+                                 const double* sq2, const double* slq2, int nf, int s, int i, double x, double q2,
+                                 int f) {
+  const double a = log(x), b = log(q2);
+  if (s >= 0) {  // low x only: the interpolator at (x_0, Q^2) and (x_1, Q^2)
+    const int j = find_cell(sq2 + g.q_off[s], g.nq[s], q2);
+    const int i1 = g.n_x > 2 ? 1 : 0;
+    const double f0 = cell_value(g, vals, slx, slq2, nf, s, 0, j, slx[0], b, f);
+    const double f1 = cell_value(g, vals, slx, slq2, nf, s, i1, j, slx[1], b, f);
+    return continue_line((a - slx[0]) / (slx[1] - slx[0]), f0, f1);
+  }
+  if (q2 > g.q2_hi[g.n_sub - 1]) {  // high Q^2: the top subgrid's last two rows
+    const int r1 = g.q_off[g.n_sub] - 1, r0 = r1 - 1;
+    const double g0 = row_value(vals, slx, g.n_x, nf, r0, i, a, f);
+    const double g1 = row_value(vals, slx, g.n_x, nf, r1, i, a, f);
+    return continue_line((b - slq2[r0]) / (slq2[r1] - slq2[r0]), g0, g1);
+  }
+  // low Q^2: the lowest subgrid's first two rows (global rows 0 and 1)
+  const double db = slq2[1] - slq2[0];
+  double G0, gamma;
+  if (i >= 0) {
+    G0 = row_value(vals, slx, g.n_x, nf, 0, i, a, f);
+    if (G0 == 0.0) return 0.0;
+    gamma = (row_value(vals, slx, g.n_x, nf, 1, i, a, f) - G0) / (db * G0);
+  } else {
+    const double f0 = node_val(vals, g.n_x, nf, 0, 0, f), f1 = node_val(vals, g.n_x, nf, 0, 1, f);
+    const double d0 = (node_val(vals, g.n_x, nf, 1, 0, f) - f0) / db;
+    const double d1 = (node_val(vals, g.n_x, nf, 1, 1, f) - f1) / db;
+    const double t = (a - slx[0]) / (slx[1] - slx[0]);
+    G0 = continue_line(t, f0, f1);
+    if (G0 == 0.0) return 0.0;
+    gamma = (f0 > kPositive && f1 > kPositive) ? (1.0 - t) * d0 / f0 + t * d1 / f1
+                                               : ((1.0 - t) * d0 + t * d1) / G0;
+  }
+  const double r = q2 / sq2[0];
+  return G0 * exp(((gamma - 1.0) * r + 1.0) * (b - slq2[0]));
+}
+
 // NF > 0: compile-time flavour count; NF == 0: runtime count (<= VGX_MAX_FLAV).
 // ValT: node-value type read from memory (FP64 grid, or its FP32 copy for
-// FP32 outputs); arithmetic is FP64 in both cases.
-template <typename OutT, typename ValT, int NF>
+// FP32 outputs); arithmetic is FP64 in both cases.  MODE (VGX_EXTRAP_*) is a
+// template parameter so that the default ERROR kernel carries no code of the
+// other modes: a run-time mode test in the loop changed how the compiler
+// scheduled the stencil gathers (fewer in flight, 1.5x slower).
+template <typename OutT, typename ValT, int NF, int MODE>
 __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, const double* __restrict__ qx,
                                                      const double* __restrict__ qq2,
                                                      const double* __restrict__ kx, const double* __restrict__ klx,
@@ -79,14 +197,23 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
   const int nf = NF > 0 ? NF : g.n_flav;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
-    const double x = qx[q];
-    const double q2 = qq2[q];
+    double x = qx[q];
+    double q2 = qq2[q];
+    if constexpr (MODE == VGX_EXTRAP_FREEZE) {  // the nearest grid point
+      if (x > 0.0 && q2 > 0.0 && isfinite(x) && isfinite(q2)) {
+        x = fmin(fmax(x, sx[0]), sx[g.n_x - 1]);
+        q2 = fmin(fmax(q2, g.q2_lo[0]), g.q2_hi[g.n_sub - 1]);
+      }
+    }
     int s = -1;
     for (int k = 0; k < g.n_sub; ++k) {
       const bool last = (k == g.n_sub - 1);
       if (q2 >= g.q2_lo[k] && (q2 < g.q2_hi[k] || (last && q2 <= g.q2_hi[k]))) s = k;
     }
     if (s < 0 || !(x >= sx[0] && x <= sx[g.n_x - 1])) {
+      if constexpr (MODE == VGX_EXTRAP_CONTINUE) {  // k_pdf_continue writes these
+        if (x > 0.0 && q2 > 0.0 && isfinite(x) && isfinite(q2) && x <= sx[g.n_x - 1]) continue;
+      }
       for (int f = 0; f < nf; ++f) out[(int64_t)f * n + q] = (OutT)NAN;
       atomicAdd(oor, 1ull);
       continue;
@@ -140,16 +267,49 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
   }
 }
 
+// Second pass of a CONTINUE-mode call: the queries outside the grid that
+// k_pdf_interp skipped.  A separate kernel, because inlined into the
+// interpolation loop the FP64 exp/log of the continuation raise its
+// register count (their constants are hoisted out of the loop); the rescan
+// reads 16 bytes per query.  Knots are read from global memory: few queries
+// take this path.
+template <typename OutT, typename ValT>
+__global__ __launch_bounds__(256) void k_pdf_continue(PdfKernelArgs g, int64_t n, const double* __restrict__ qx,
+                                                      const double* __restrict__ qq2, const double* __restrict__ kx,
+                                                      const double* __restrict__ klx, const double* __restrict__ kq2,
+                                                      const double* __restrict__ klq2, const ValT* __restrict__ vals,
+                                                      OutT* __restrict__ out) {
+  const double xlo = kx[0], xhi = kx[g.n_x - 1];
+  const double qlo = g.q2_lo[0], qhi = g.q2_hi[g.n_sub - 1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double x = qx[q], q2 = qq2[q];
+    const bool valid = x > 0.0 && q2 > 0.0 && isfinite(x) && isfinite(q2) && x <= xhi;
+    if (!valid || (x >= xlo && q2 >= qlo && q2 <= qhi)) continue;
+    int s = -1;
+    for (int k = 0; k < g.n_sub; ++k) {
+      const bool last = (k == g.n_sub - 1);
+      if (q2 >= g.q2_lo[k] && (q2 < g.q2_hi[k] || (last && q2 <= g.q2_hi[k]))) s = k;
+    }
+    const int i = x >= xlo ? find_cell(kx, g.n_x, x) : -1;
+    for (int f = 0; f < g.n_flav; ++f)
+      out[(int64_t)f * n + q] = (OutT)continue_value(g, vals, kx, klx, kq2, klq2, g.n_flav, s, i, x, q2, f);
+  }
+}
+
 // alpha_s(Q): log-cubic interpolation on the table's subgrids (thesis PDF
 // chapter, alpha_s paragraphs): cubic Hermite in ln Q^2 with secant-average
 // slopes on interior cells, linear on a subgrid's edge cells, the top value
-// above the last knot, NaN below the first.
+// above the last knot.  Below the first knot: NaN (ERROR), the first value
+// (FREEZE), or the low-x line rule in ln Q^2 through the two lowest knots
+// (CONTINUE).  Non-positive or non-finite Q^2: NaN.
 struct AlphasArgs {
   int n_sub;
   int nq[VGX_MAX_SUB];
   int off[VGX_MAX_SUB + 1];
   double q2_lo[VGX_MAX_SUB], q2_hi[VGX_MAX_SUB];
   double top;
+  int mode;
 };
 
 __global__ __launch_bounds__(256) void k_alphas(AlphasArgs g, int64_t n, const double* __restrict__ qq2,
@@ -164,7 +324,14 @@ __global__ __launch_bounds__(256) void k_alphas(AlphasArgs g, int64_t n, const d
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
     const double q2 = qq2[q];
+    if (!(q2 > 0.0 && isfinite(q2))) { out[q] = (double)NAN; continue; }
     if (q2 > g.q2_hi[g.n_sub - 1]) { out[q] = g.top; continue; }
+    if (q2 < g.q2_lo[0]) {
+      out[q] = g.mode == VGX_EXTRAP_FREEZE     ? sv[0]
+               : g.mode == VGX_EXTRAP_CONTINUE ? continue_line((log(q2) - sl[0]) / (sl[1] - sl[0]), sv[0], sv[1])
+                                               : (double)NAN;
+      continue;
+    }
     int s = -1;
     for (int k = 0; k < g.n_sub; ++k) {
       const bool last = (k == g.n_sub - 1);
@@ -310,22 +477,37 @@ extern "C" vgx_status pdf_interp(const vgx_pdf* p, int64_t n, const double* x_de
   const size_t lds = sizeof(double) * (2 * (size_t)p->n_x + 2 * (size_t)p->q_off[p->n_sub]);
   hipStream_t st = (hipStream_t)stream;
   const bool f11 = p->n_flav == 11;
-  if (out_dtype == VGX_F64) {
-    if (f11)
-      hipLaunchKernelGGL((k_pdf_interp<double, double, 11>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
-                         p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
-    else
-      hipLaunchKernelGGL((k_pdf_interp<double, double, 0>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
-                         p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
-  } else {
-    if (f11)
-      hipLaunchKernelGGL((k_pdf_interp<float, float, 11>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
-                         p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
-    else
-      hipLaunchKernelGGL((k_pdf_interp<float, float, 0>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
-                         p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
-  }
+  auto launch = [&](auto mode_tag) {
+    constexpr int M = decltype(mode_tag)::value;
+    if (out_dtype == VGX_F64) {
+      if (f11)
+        hipLaunchKernelGGL((k_pdf_interp<double, double, 11, M>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                           p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
+      else
+        hipLaunchKernelGGL((k_pdf_interp<double, double, 0, M>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                           p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
+    } else {
+      if (f11)
+        hipLaunchKernelGGL((k_pdf_interp<float, float, 11, M>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                           p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
+      else
+        hipLaunchKernelGGL((k_pdf_interp<float, float, 0, M>), dim3(grid), dim3(block), lds, st, g, n, x_dev, q2_dev,
+                           p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
+    }
+  };
+  if (p->extrap == VGX_EXTRAP_FREEZE) launch(std::integral_constant<int, VGX_EXTRAP_FREEZE>{});
+  else if (p->extrap == VGX_EXTRAP_CONTINUE) launch(std::integral_constant<int, VGX_EXTRAP_CONTINUE>{});
+  else launch(std::integral_constant<int, VGX_EXTRAP_ERROR>{});
   VGX_HIP(hipGetLastError());
+  if (p->extrap == VGX_EXTRAP_CONTINUE) {
+    if (out_dtype == VGX_F64)
+      hipLaunchKernelGGL((k_pdf_continue<double, double>), dim3(grid), dim3(block), 0, st, g, n, x_dev, q2_dev, p->x,
+                         p->lx, p->q2, p->lq2, p->v64, (double*)out_dev);
+    else
+      hipLaunchKernelGGL((k_pdf_continue<float, float>), dim3(grid), dim3(block), 0, st, g, n, x_dev, q2_dev, p->x,
+                         p->lx, p->q2, p->lq2, p->v32, (float*)out_dev);
+    VGX_HIP(hipGetLastError());
+  }
   return VGX_OK;
 }
 
@@ -339,6 +521,16 @@ extern "C" vgx_status pdf_out_of_range(vgx_pdf* p, void* stream, int64_t* count)
   VGX_HIP(hipStreamSynchronize(st));
   *count = (int64_t)c;
   return c ? VGX_ERANGE : VGX_OK;
+}
+
+extern "C" vgx_status pdf_set_extrapolation(vgx_pdf* p, int32_t mode) {
+  VGX_CHECK(p, "pdf_set_extrapolation: null context");
+  VGX_CHECK(mode == VGX_EXTRAP_ERROR || mode == VGX_EXTRAP_FREEZE || mode == VGX_EXTRAP_CONTINUE,
+            "pdf_set_extrapolation: bad mode %d", mode);
+  VGX_CHECK(mode != VGX_EXTRAP_CONTINUE || (p->n_x >= 2 && p->nq[0] >= 2),
+            "pdf_set_extrapolation: continuation needs two x knots and two Q^2 knots in the lowest subgrid");
+  p->extrap = mode;
+  return VGX_OK;
 }
 
 extern "C" vgx_status pdf_bounds(const vgx_pdf* p, double* xmin, double* xmax, double* q2min, double* q2max) {
@@ -420,6 +612,7 @@ extern "C" vgx_status pdf_alphas(const vgx_pdf* p, int64_t n, const double* q2_d
   }
   g.off[p->a_nsub] = p->a_off[p->a_nsub];
   g.top = p->h_aval[p->a_off[p->a_nsub] - 1];
+  g.mode = p->extrap;
   const int block = 256;
   const int64_t want = (n + block - 1) / block;
   const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);

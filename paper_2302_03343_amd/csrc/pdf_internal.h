@@ -11,6 +11,7 @@ struct vgx_pdf {
   int device = 0;
   int n_x = 0, n_sub = 0, n_flav = 0;
   int fstride = 0;                    // node stride (= n_flav)
+  int extrap = VGX_EXTRAP_ERROR;      // behaviour outside the grid (pdf_interp, pdf_alphas)
   int nq[VGX_MAX_SUB] = {0};
   int q_off[VGX_MAX_SUB + 1] = {0};   // knot offset of each subgrid
   // host copies (knots only; values stay on the device)

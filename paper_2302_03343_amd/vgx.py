@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ERANGE", 5:
                 6: "EFALLBACK", 7: "ESTATE"}
 GAUSS, GENZ_OSC, GENZ_PEAK, TTBAR, DRELLYAN, SINGLETOP = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
+EXTRAP_ERROR, EXTRAP_FREEZE, EXTRAP_CONTINUE = 0, 1, 2
 MAX_DIM, MAX_BINS = 12, 256
 
 
@@ -83,6 +84,7 @@ for _name, _res, _args in [
     ("pdf_interp", _S, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     ("pdf_out_of_range", _S, [_vp, _vp, C.POINTER(_i64)]),
     ("pdf_bounds", _S, [_vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64)]),
+    ("pdf_set_extrapolation", _S, [_vp, _i32]),
     ("pdf_set_alphas", _S, [_vp, _i32, C.POINTER(_f64), C.POINTER(_f64), _vp]),
     ("pdf_alphas", _S, [_vp, _i64, _vp, _vp, _vp]),
     ("pdf_destroy", None, [_vp]),
@@ -217,6 +219,10 @@ def pdf_bounds(pdf):
     v = [_f64() for _ in range(4)]
     _check(_c["pdf_bounds"](pdf, *[C.byref(t) for t in v]), "pdf_bounds")
     return tuple(t.value for t in v)
+
+
+def pdf_set_extrapolation(pdf, mode):
+    _check(_c["pdf_set_extrapolation"](pdf, int(mode)), "pdf_set_extrapolation")
 
 
 def pdf_set_alphas(pdf, q2_knots, alphas, stream=None):
