@@ -106,6 +106,7 @@ enum { VGX_EXTRAP_ERROR = 0, VGX_EXTRAP_FREEZE = 1, VGX_EXTRAP_CONTINUE = 2 };
 
 #define VGX_MAX_DIM 12
 #define VGX_MAX_BINS 256
+#define VGX_MAX_PART 10
 
 /* ------------------------------------------------------------------------ */
 /* PDF grids (LHAPDF-style, thesis PDF chapter)                              */
@@ -283,6 +284,45 @@ vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable);
 vgx_status vegas_kernel_time(vgx_vegas* v, double* ms_host, int64_t* launches_host);
 
 void vegas_destroy(vgx_vegas* v);
+
+/* ------------------------------------------------------------------------ */
+/* Event generation (thesis MC chapter: RAMBO, acceptance-rejection; MadFlow  */
+/* chapter: phase-space generator, unweighted event exporter)                */
+/* ------------------------------------------------------------------------ */
+
+/* RAMBO phase-space points for a total momentum P = (sqrt_s, 0, 0, 0) (async).
+ *   n_part     : final-state particles, 2 .. VGX_MAX_PART.
+ *   masses     : host [n_part], >= 0, sum < sqrt_s; all zero: massless RAMBO
+ *                (flat weight w0), else the massive variant (weight w0 w_m,
+ *                3-momenta rescaled by the xi that restores energy
+ *                conservation).
+ *   seed, stream_id (< 2^24), iteration : Philox-4x32-10 key and counter
+ *                fields; event e draws the uniforms of sample `first + e` of
+ *                the VEGAS kernels' convention (block i for particle i).
+ *   mom_dev    : device [4][n_part][n_events] FP64 (E, px, py, pz) in GeV,
+ *                structure of arrays: component c of particle i of event e at
+ *                (c * n_part + i) * n_events + e.
+ *   w_dev      : device [n_events] FP64 phase-space weights, GeV^(2 n_part - 4)
+ *                with the measure (2 pi)^4 delta^4(P - sum p) prod d^3p/((2 pi)^3 2E).
+ * n_events = 0 is a no-op.  VGX_EINVAL on bad sizes, masses or sqrt_s. */
+vgx_status rambo_generate(int32_t n_part, const double* masses, double sqrt_s, uint64_t seed, uint32_t stream_id,
+                          uint32_t iteration, int64_t first, int64_t n_events, double* mom_dev, double* w_dev,
+                          void* stream);
+
+/* Acceptance-rejection unweighting (sync: returns the count).  Event e is
+ * kept when w_e > r_e w_max, r_e the first uniform of sample e for (seed,
+ * stream_id, iteration) -- use a stream or iteration the weights' own
+ * sampling did not.
+ *   w_dev      : device [n] FP64 weights; NaN and w <= 0 are never kept.
+ *   w_max      : > 0: the bound to use (efficiency w/w_max); 0: the largest
+ *                weight of the sample, found on the device.
+ *   idx_dev    : device [n] int64; the kept indices in ascending order fill
+ *                its first *n_kept entries.
+ *   w_max_used : host, may be NULL: the bound used.
+ * Allocates a small stream-ordered scratch (about n/512 bytes).  n = 0 is a
+ * no-op. */
+vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
+                    uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched integration: many contexts, one persistent launch per iteration    */

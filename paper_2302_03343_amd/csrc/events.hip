@@ -1,0 +1,351 @@
+// Event generation: RAMBO phase-space points and acceptance-rejection
+// unweighting.
+//
+// Thesis: MC chapter (RAMBO subsection, acceptance-rejection paragraph) and
+// the MadFlow chapter (vectorised RAMBO phase-space generator; unweighted
+// event exporter: keep an event when its weight exceeds a uniform number times
+// the sample's largest weight).
+//
+// RAMBO: one event per thread, the n momenta in registers (n is a template
+// parameter, 2..VGX_MAX_PART); outputs structure-of-arrays [4][n][N] so that
+// every store of a wave is contiguous.  Uniforms: Philox-4x32-10 with the
+// counter of sample e of the VEGAS kernels (low and high words of e, the
+// iteration, stream << 8 | block), block i giving particle i's four numbers.
+// Massive momenta: xi by Newton's method from xi0 = sqrt(1 - (sum m/sqrt s)^2),
+// where the (convex) constraint is >= 0, so the iterates decrease
+// monotonically to the root; the loop ends when they stop decreasing.
+//
+// Unweighting: w_max by a max over the positive weights (non-negative
+// doubles order like their bit patterns, so an integer atomicMax is exact);
+// then kept indices in ascending order by a three-pass compaction: per-block
+// counts, one exclusive scan, and a scatter that regenerates each event's
+// uniform and ranks the kept events with wave ballots.
+#include "common.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace vgx {
+
+constexpr int RB_BLOCK = 256;
+
+struct RamboArgs {
+  int64_t n_events, first;
+  double sqrt_s, w0, sum_m;
+  double m[VGX_MAX_PART];
+  uint32_t k0, k1, sid, it;
+};
+
+template <int N, bool MASSIVE>
+__global__ __launch_bounds__(RB_BLOCK) void k_rambo(RamboArgs a, double* __restrict__ mom, double* __restrict__ wout) {
+  const int64_t stride = (int64_t)gridDim.x * RB_BLOCK;
+  const double s = a.sqrt_s * a.sqrt_s;
+  for (int64_t e = (int64_t)blockIdx.x * RB_BLOCK + threadIdx.x; e < a.n_events; e += stride) {
+    const uint64_t idx = (uint64_t)(a.first + e);
+    double q[N][4];
+    double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0, Q3 = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const u32x4 r = philox4x32_10((uint32_t)idx, (uint32_t)(idx >> 32), a.it, (a.sid << 8) | (uint32_t)i, a.k0, a.k1);
+      const double c = 2.0 * word_to_unit(r.x) - 1.0;
+      const double phi = 2.0 * M_PI * word_to_unit(r.y);
+      const double e0 = -log(word_to_unit(r.z) * word_to_unit(r.w));
+      const double st = sqrt(1.0 - c * c);
+      double sn, cs;
+      sincos(phi, &sn, &cs);
+      q[i][0] = e0;
+      q[i][1] = e0 * st * cs;
+      q[i][2] = e0 * st * sn;
+      q[i][3] = e0 * c;
+      Q0 += q[i][0];
+      Q1 += q[i][1];
+      Q2 += q[i][2];
+      Q3 += q[i][3];
+    }
+    // boost and scale onto P = (sqrt s, 0): p = x H_b(q)
+    const double M = sqrt(Q0 * Q0 - Q1 * Q1 - Q2 * Q2 - Q3 * Q3);
+    const double b1 = -Q1 / M, b2 = -Q2 / M, b3 = -Q3 / M;
+    const double x = a.sqrt_s / M, gam = Q0 / M, aa = 1.0 / (1.0 + gam);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double bq = b1 * q[i][1] + b2 * q[i][2] + b3 * q[i][3];
+      const double q0 = q[i][0];
+      q[i][0] = x * (gam * q0 + bq);
+      q[i][1] = x * (q[i][1] + b1 * q0 + aa * bq * b1);
+      q[i][2] = x * (q[i][2] + b2 * q0 + aa * bq * b2);
+      q[i][3] = x * (q[i][3] + b3 * q0 + aa * bq * b3);
+    }
+    double w = a.w0;
+    if constexpr (MASSIVE) {
+      // sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt s
+      const double t = a.sum_m / a.sqrt_s;
+      double xi = sqrt(1.0 - t * t);
+      for (int iter = 0; iter < 64; ++iter) {
+        double f = -a.sqrt_s, fp = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const double xe = xi * q[i][0];
+          const double k0 = sqrt(a.m[i] * a.m[i] + xe * xe);
+          f += k0;
+          fp += xe * q[i][0] / k0;
+        }
+        const double nx = xi - f / fp;
+        if (!(nx < xi)) break;
+        xi = nx;
+      }
+      double sk = 0.0, pr = 1.0, sk2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const double kabs = xi * q[i][0];  // |k_i| = xi |p_i| = xi p_i^0 (p_i massless)
+        const double k0 = sqrt(a.m[i] * a.m[i] + kabs * kabs);
+        sk += kabs;
+        pr *= kabs / k0;
+        sk2 += kabs * kabs / k0;
+        q[i][0] = k0;
+        q[i][1] *= xi;
+        q[i][2] *= xi;
+        q[i][3] *= xi;
+      }
+      w = a.w0 * (pow(s, (double)(2 - N)) * pow(sk, (double)(2 * N - 3)) * pr / sk2);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) mom[((int64_t)c * N + i) * a.n_events + e] = q[i][c];
+    wout[e] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Unweighting
+// ---------------------------------------------------------------------------
+constexpr int UW_BLOCK = 256;
+constexpr int UW_ROUNDS = 16;
+constexpr int UW_CHUNK = UW_BLOCK * UW_ROUNDS;  // events per block, ranked in order
+
+__global__ __launch_bounds__(UW_BLOCK) void k_uw_max(int64_t n, const double* __restrict__ w,
+                                                     unsigned long long* __restrict__ out_bits) {
+  __shared__ double red[UW_BLOCK / 64];
+  double m = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * UW_BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * UW_BLOCK + threadIdx.x; i < n; i += stride) {
+    const double v = w[i];
+    m = v > m ? v : m;  // NaN and non-positive weights never win
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < UW_BLOCK / 64; ++k) m = red[k] > m ? red[k] : m;
+    atomicMax(out_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+struct UwArgs {
+  int64_t n;
+  double w_max;  // > 0: given; else read from w_max_bits
+  uint32_t k0, k1, sid, it;
+};
+
+__device__ __forceinline__ bool uw_keep(const UwArgs& a, const double* w, int64_t i, double wmax) {
+  const u32x4 r = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), a.it, a.sid << 8, a.k0, a.k1);
+  return w[i] > word_to_unit(r.x) * wmax;
+}
+
+__device__ __forceinline__ double uw_wmax(const UwArgs& a, const unsigned long long* bits) {
+  return a.w_max > 0.0 ? a.w_max : __longlong_as_double((long long)*bits);
+}
+
+__global__ __launch_bounds__(UW_BLOCK) void k_uw_count(UwArgs a, const double* __restrict__ w,
+                                                       const unsigned long long* __restrict__ bits,
+                                                       int64_t* __restrict__ counts) {
+  __shared__ int red[UW_BLOCK / 64];
+  const double wmax = uw_wmax(a, bits);
+  const int64_t base = (int64_t)blockIdx.x * UW_CHUNK;
+  int c = 0;
+  for (int r = 0; r < UW_ROUNDS; ++r) {
+    const int64_t i = base + r * UW_BLOCK + threadIdx.x;
+    if (i < a.n) c += uw_keep(a, w, i, wmax) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < UW_BLOCK / 64; ++k) t += red[k];
+    counts[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of the block counts in place (one workgroup of 1024), the
+// total in counts[nb].
+__global__ __launch_bounds__(1024) void k_uw_scan(int64_t nb, int64_t* __restrict__ counts) {
+  __shared__ int64_t part[1024 / 64];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nb ? counts[i] : 0;
+    int64_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) part[wv] = incl;
+    __syncthreads();
+    int64_t before = carry;
+    for (int k = 0; k < wv; ++k) before += part[k];
+    if (i < nb) counts[i] = before + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = before + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[nb] = carry;
+}
+
+__global__ __launch_bounds__(UW_BLOCK) void k_uw_scatter(UwArgs a, const double* __restrict__ w,
+                                                         const unsigned long long* __restrict__ bits,
+                                                         const int64_t* __restrict__ offsets,
+                                                         int64_t* __restrict__ idx_out) {
+  __shared__ int wsum[UW_BLOCK / 64];
+  const double wmax = uw_wmax(a, bits);
+  const int64_t base = (int64_t)blockIdx.x * UW_CHUNK;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t pos = offsets[blockIdx.x];
+  for (int r = 0; r < UW_ROUNDS; ++r) {
+    const int64_t i = base + r * UW_BLOCK + threadIdx.x;
+    const bool keep = i < a.n && uw_keep(a, w, i, wmax);
+    const unsigned long long mask = __ballot(keep);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    if (lane == 0) wsum[wv] = __popcll(mask);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < UW_BLOCK / 64; ++k) {
+      before += k < wv ? wsum[k] : 0;
+      total += wsum[k];
+    }
+    if (keep) idx_out[pos + before + rank] = i;
+    pos += total;
+    __syncthreads();
+  }
+}
+
+template <int N>
+void launch_rambo(const RamboArgs& a, bool massive, int grid, hipStream_t st, double* mom, double* w) {
+  if (massive)
+    hipLaunchKernelGGL((k_rambo<N, true>), dim3(grid), dim3(RB_BLOCK), 0, st, a, mom, w);
+  else
+    hipLaunchKernelGGL((k_rambo<N, false>), dim3(grid), dim3(RB_BLOCK), 0, st, a, mom, w);
+}
+
+}  // namespace vgx
+
+using namespace vgx;
+
+extern "C" vgx_status rambo_generate(int32_t n_part, const double* masses, double sqrt_s, uint64_t seed,
+                                     uint32_t stream_id, uint32_t iteration, int64_t first, int64_t n_events,
+                                     double* mom_dev, double* w_dev, void* stream) {
+  VGX_CHECK(n_part >= 2 && n_part <= VGX_MAX_PART, "rambo_generate: n_part %d out of 2..%d", n_part, VGX_MAX_PART);
+  VGX_CHECK(masses, "rambo_generate: null masses");
+  VGX_CHECK(sqrt_s > 0.0 && isfinite(sqrt_s), "rambo_generate: sqrt_s must be positive and finite");
+  VGX_CHECK(stream_id < (1u << 24), "rambo_generate: stream_id must be < 2^24");
+  VGX_CHECK(first >= 0 && n_events >= 0, "rambo_generate: negative first or n_events");
+  RamboArgs a{};
+  a.n_events = n_events;
+  a.first = first;
+  a.sqrt_s = sqrt_s;
+  bool massive = false;
+  for (int i = 0; i < n_part; ++i) {
+    VGX_CHECK(masses[i] >= 0.0 && isfinite(masses[i]), "rambo_generate: mass %d must be >= 0 and finite", i);
+    a.m[i] = masses[i];
+    a.sum_m += masses[i];
+    massive = massive || masses[i] > 0.0;
+  }
+  VGX_CHECK(a.sum_m < sqrt_s, "rambo_generate: the masses (sum %g) do not fit in sqrt_s = %g", a.sum_m, sqrt_s);
+  if (n_events == 0) return VGX_OK;
+  VGX_CHECK(mom_dev && w_dev, "rambo_generate: null device pointer");
+  const int n = n_part;
+  const double s = sqrt_s * sqrt_s;
+  // w0 = (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / (Gamma(n) Gamma(n-1))
+  a.w0 = pow(2.0 * M_PI, 4.0 - 3.0 * n) * pow(M_PI / 2.0, n - 1.0) * pow(s, n - 2.0) / (tgamma((double)n) * tgamma(n - 1.0));
+  a.k0 = (uint32_t)seed;
+  a.k1 = (uint32_t)(seed >> 32);
+  a.sid = stream_id;
+  a.it = iteration;
+  const int64_t want = (n_events + RB_BLOCK - 1) / RB_BLOCK;
+  const int grid = (int)(want < (int64_t)device_cus() * 16 ? want : (int64_t)device_cus() * 16);
+  hipStream_t st = (hipStream_t)stream;
+  switch (n_part) {
+    case 2: launch_rambo<2>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 3: launch_rambo<3>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 4: launch_rambo<4>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 5: launch_rambo<5>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 6: launch_rambo<6>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 7: launch_rambo<7>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 8: launch_rambo<8>(a, massive, grid, st, mom_dev, w_dev); break;
+    case 9: launch_rambo<9>(a, massive, grid, st, mom_dev, w_dev); break;
+    default: launch_rambo<10>(a, massive, grid, st, mom_dev, w_dev); break;
+  }
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
+                               uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used,
+                               void* stream) {
+  VGX_CHECK(n >= 0, "unweight: n < 0");
+  VGX_CHECK(n_kept, "unweight: null n_kept");
+  VGX_CHECK(stream_id < (1u << 24), "unweight: stream_id must be < 2^24");
+  VGX_CHECK(!(w_max < 0.0) && !isnan(w_max), "unweight: w_max must be >= 0 (0: the sample's maximum)");
+  *n_kept = 0;
+  if (n == 0) {
+    if (w_max_used) *w_max_used = w_max;
+    return VGX_OK;
+  }
+  VGX_CHECK(w_dev && idx_dev, "unweight: null device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb = (n + UW_CHUNK - 1) / UW_CHUNK;
+  VGX_CHECK(nb < (int64_t)1 << 31, "unweight: n too large");
+  // scratch: the max's bit pattern, then nb + 1 counts (stream-ordered)
+  void* scratch = nullptr;
+  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) + sizeof(int64_t) * (nb + 1), st));
+  unsigned long long* bits = (unsigned long long*)scratch;
+  int64_t* counts = (int64_t*)(bits + 1);
+  UwArgs a{n, w_max, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id, iteration};
+  hipError_t e = hipMemsetAsync(bits, 0, sizeof(unsigned long long), st);
+  if (e == hipSuccess && !(w_max > 0.0)) {
+    const int64_t want = (n + UW_BLOCK - 1) / UW_BLOCK;
+    const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
+    hipLaunchKernelGGL(k_uw_max, dim3(grid), dim3(UW_BLOCK), 0, st, n, w_dev, bits);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_uw_count, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts);
+    hipLaunchKernelGGL(k_uw_scan, dim3(1), dim3(1024), 0, st, nb, counts);
+    hipLaunchKernelGGL(k_uw_scatter, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts, idx_dev);
+    e = hipGetLastError();
+  }
+  int64_t total = 0;
+  unsigned long long wb = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, counts + nb, sizeof(total), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&wb, bits, sizeof(wb), hipMemcpyDeviceToHost, st);
+  hipError_t ef = hipFreeAsync(scratch, st);
+  if (e == hipSuccess) e = ef;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "unweight", __FILE__, __LINE__);
+  *n_kept = total;
+  if (w_max_used) {
+    double wm;
+    memcpy(&wm, &wb, sizeof(wm));
+    *w_max_used = w_max > 0.0 ? w_max : wm;
+  }
+  return VGX_OK;
+}

@@ -88,6 +88,8 @@ for _name, _res, _args in [
     ("pdf_set_alphas", _S, [_vp, _i32, C.POINTER(_f64), C.POINTER(_f64), _vp]),
     ("pdf_alphas", _S, [_vp, _i64, _vp, _vp, _vp]),
     ("pdf_destroy", None, [_vp]),
+    ("rambo_generate", _S, [_i32, C.POINTER(_f64), _f64, _u64, _u32, _u32, _i64, _i64, _vp, _vp, _vp]),
+    ("unweight", _S, [_i64, _vp, _f64, _u64, _u32, _u32, _vp, C.POINTER(_i64), C.POINTER(_f64), _vp]),
     ("vegas_create", _S, [C.POINTER(VegasCfg), _vp, C.POINTER(_vp)]),
     ("vegas_iterate", _S, [_vp, _i64, _i32, C.POINTER(IterResult)]),
     ("vegas_iterate_async", _S, [_vp, _i64, _i32]),
@@ -248,6 +250,31 @@ def pdf_alphas(pdf, q2, out, stream=None):
 
 def pdf_destroy(pdf):
     _c["pdf_destroy"](pdf)
+
+
+# ---------------------------------------------------------------------------
+# Event generation
+# ---------------------------------------------------------------------------
+def rambo_generate(masses, sqrt_s, seed, stream_id, iteration, first, mom, w, stream=None):
+    """masses: host (n,); mom: CUDA float64 (4, n, N); w: CUDA float64 (N,)."""
+    import torch
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    n_ev = w.numel()
+    _check(_c["rambo_generate"](m.size, _hptr(m, _f64), float(sqrt_s), int(seed), int(stream_id), int(iteration),
+                                int(first), n_ev, _dptr(mom, torch.float64, 4 * m.size * n_ev, "mom"),
+                                _dptr(w, torch.float64, n_ev, "w"), _stream(stream)), "rambo_generate")
+    return mom, w
+
+
+def unweight(w, seed, stream_id, iteration, idx, w_max=0.0, stream=None):
+    """Kept event indices (ascending) into idx[:n_kept]; returns (n_kept, w_max_used)."""
+    import torch
+    n = w.numel()
+    k, wm = _i64(), _f64()
+    _check(_c["unweight"](n, _dptr(w, torch.float64, n, "w"), float(w_max), int(seed), int(stream_id),
+                          int(iteration), _dptr(idx, torch.int64, n, "idx"), C.byref(k), C.byref(wm),
+                          _stream(stream)), "unweight")
+    return int(k.value), float(wm.value)
 
 
 # ---------------------------------------------------------------------------
