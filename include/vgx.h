@@ -324,6 +324,65 @@ vgx_status rambo_generate(int32_t n_part, const double* masses, double sqrt_s, u
 vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
                     uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used, void* stream);
 
+/* Asynchronous LHE 3.0 export (thesis MadFlow chapter, unweighted event
+ * exporter: events written as Les Houches Event records by a CPU thread
+ * separate from the device work).  A writer owns a file and one thread;
+ * batches are queued and written in the order they were queued. */
+typedef struct vgx_lhe vgx_lhe;
+
+typedef struct {            /* the <init> block (Les Houches accord)          */
+  int32_t beam_id[2];       /* IDBMUP: PDG codes of the beams                 */
+  double beam_energy[2];    /* EBMUP (GeV)                                    */
+  int32_t pdf_group[2];     /* PDFGUP                                         */
+  int32_t pdf_set[2];       /* PDFSUP                                         */
+  int32_t weight_mode;      /* IDWTUP (3: unweighted events, weight +XWGTUP)  */
+  double xsec, xsec_err;    /* XSECUP, XERRUP (pb)                            */
+  double xmax;              /* XMAXUP                                         */
+  int32_t proc_id;          /* LPRUP                                          */
+} vgx_lhe_init;
+
+typedef struct {            /* per-batch event-line fields                    */
+  double sqrt_s;            /* partonic centre-of-mass energy (GeV): the two
+                               incoming partons are massless along +z and -z
+                               with energy sqrt_s/2 each                      */
+  double weight;            /* XWGTUP                                         */
+  double scale;             /* SCALUP (GeV)                                   */
+  double aqed, aqcd;        /* AQEDUP, AQCDUP                                 */
+  int32_t proc_id;          /* IDPRUP                                         */
+} vgx_lhe_event_info;
+
+/* Open `path` for writing and write the header and <init> block (sync).
+ * VGX_EINVAL if the file cannot be written. */
+vgx_status lhe_open(const char* path, const vgx_lhe_init* init, vgx_lhe** out);
+
+/* Queue the kept events of a batch (async on `stream`; never synchronises
+ * it).  mom_dev is a rambo_generate output [4][n_part][n_total]; idx_dev
+ * (device [n_kept] int64, e.g. from unweight; NULL: events 0..n_kept-1) lists
+ * the events to write.  The events are gathered on the device into a stream-
+ * ordered scratch, copied to a pooled pinned host buffer, and formatted by
+ * the writer thread once the copy has completed; device buffers may be reused
+ * as soon as later work on `stream` is ordered after this call.
+ *   pdg_in  : host [2] PDG codes of the incoming partons.
+ *   pdg_out : host [n_part] PDG codes; masses: host [n_part] (PUP5, GeV).
+ * Particle lines carry colour 0 0 (not computed) and helicity 9 (unknown).
+ * Momenta are written with 17 significant digits (exact round trip). */
+vgx_status lhe_write_events(vgx_lhe* w, int32_t n_part, const int32_t* pdg_in, const int32_t* pdg_out,
+                            const double* masses, const vgx_lhe_event_info* info, int64_t n_total,
+                            const double* mom_dev, const int64_t* idx_dev, int64_t n_kept, void* stream);
+
+/* Queue n events from host memory: mom_host [n][n_part][4] (E, px, py, pz),
+ * copied before the call returns. */
+vgx_status lhe_write_events_host(vgx_lhe* w, int32_t n_part, const int32_t* pdg_in, const int32_t* pdg_out,
+                                 const double* masses, const vgx_lhe_event_info* info, int64_t n,
+                                 const double* mom_host);
+
+/* Wait until every queued event is written (sync); *written = events written
+ * so far (may be NULL). */
+vgx_status lhe_flush(vgx_lhe* w, int64_t* written);
+
+/* Write the queue out, close the document and the file, free the writer. */
+vgx_status lhe_close(vgx_lhe* w);
+
 /* ------------------------------------------------------------------------ */
 /* Batched integration: many contexts, one persistent launch per iteration    */
 /* ------------------------------------------------------------------------ */

@@ -76,6 +76,16 @@ def _sig(name, res, *args):
 
 
 _S = C.c_int  # vgx_status
+
+
+class LheInit(C.Structure):
+    _fields_ = [("beam_id", _i32 * 2), ("beam_energy", _f64 * 2), ("pdf_group", _i32 * 2), ("pdf_set", _i32 * 2),
+                ("weight_mode", _i32), ("xsec", _f64), ("xsec_err", _f64), ("xmax", _f64), ("proc_id", _i32)]
+
+
+class LheEventInfo(C.Structure):
+    _fields_ = [("sqrt_s", _f64), ("weight", _f64), ("scale", _f64), ("aqed", _f64), ("aqcd", _f64),
+                ("proc_id", _i32)]
 _c = {}
 for _name, _res, _args in [
     ("vgx_last_error", C.c_char_p, []),
@@ -90,6 +100,13 @@ for _name, _res, _args in [
     ("pdf_destroy", None, [_vp]),
     ("rambo_generate", _S, [_i32, C.POINTER(_f64), _f64, _u64, _u32, _u32, _i64, _i64, _vp, _vp, _vp]),
     ("unweight", _S, [_i64, _vp, _f64, _u64, _u32, _u32, _vp, C.POINTER(_i64), C.POINTER(_f64), _vp]),
+    ("lhe_open", _S, [C.c_char_p, C.POINTER(LheInit), C.POINTER(_vp)]),
+    ("lhe_write_events", _S, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_f64), C.POINTER(LheEventInfo),
+                              _i64, _vp, _vp, _i64, _vp]),
+    ("lhe_write_events_host", _S, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_f64),
+                                   C.POINTER(LheEventInfo), _i64, C.POINTER(_f64)]),
+    ("lhe_flush", _S, [_vp, C.POINTER(_i64)]),
+    ("lhe_close", _S, [_vp]),
     ("vegas_create", _S, [C.POINTER(VegasCfg), _vp, C.POINTER(_vp)]),
     ("vegas_iterate", _S, [_vp, _i64, _i32, C.POINTER(IterResult)]),
     ("vegas_iterate_async", _S, [_vp, _i64, _i32]),
@@ -264,6 +281,87 @@ def rambo_generate(masses, sqrt_s, seed, stream_id, iteration, first, mom, w, st
                                 int(first), n_ev, _dptr(mom, torch.float64, 4 * m.size * n_ev, "mom"),
                                 _dptr(w, torch.float64, n_ev, "w"), _stream(stream)), "rambo_generate")
     return mom, w
+
+
+def lhe_open(path, beam_id=(2212, 2212), beam_energy=(6500.0, 6500.0), pdf_group=(0, 0), pdf_set=(-1, -1),
+             weight_mode=3, xsec=0.0, xsec_err=0.0, xmax=1.0, proc_id=1):
+    ini = LheInit((_i32 * 2)(*beam_id), (_f64 * 2)(*beam_energy), (_i32 * 2)(*pdf_group), (_i32 * 2)(*pdf_set),
+                  weight_mode, xsec, xsec_err, xmax, proc_id)
+    h = _vp()
+    _check(_c["lhe_open"](os.fsencode(path), C.byref(ini), C.byref(h)), "lhe_open")
+    return h
+
+
+def _lhe_meta(pdg_in, pdg_out, masses, sqrt_s, weight, scale, aqed, aqcd, proc_id):
+    pi = np.ascontiguousarray(pdg_in, dtype=np.int32)
+    po = np.ascontiguousarray(pdg_out, dtype=np.int32)
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    if pi.size != 2 or po.size != m.size:
+        raise ValueError("pdg_in needs 2 codes and pdg_out one per mass")
+    return pi, po, m, LheEventInfo(sqrt_s, weight, scale, aqed, aqcd, proc_id)
+
+
+def lhe_write_events(h, mom, idx, n_kept, pdg_in, pdg_out, masses, sqrt_s, weight=1.0, scale=0.0, aqed=0.0,
+                     aqcd=0.0, proc_id=1, stream=None):
+    """Queue events idx[:n_kept] (idx None: 0..n_kept-1) of a rambo_generate
+    output mom (4, n, N)."""
+    import torch
+    pi, po, m, info = _lhe_meta(pdg_in, pdg_out, masses, sqrt_s, weight, scale, aqed, aqcd, proc_id)
+    n_total = mom.shape[2]
+    _check(_c["lhe_write_events"](h, po.size, _hptr(pi, _i32), _hptr(po, _i32), _hptr(m, _f64), C.byref(info),
+                                  n_total, _dptr(mom, torch.float64, 4 * po.size * n_total, "mom"),
+                                  _dptr(idx, torch.int64, n_kept, "idx"), int(n_kept), _stream(stream)),
+           "lhe_write_events")
+
+
+def lhe_write_events_host(h, mom, pdg_in, pdg_out, masses, sqrt_s, weight=1.0, scale=0.0, aqed=0.0, aqcd=0.0,
+                          proc_id=1):
+    """Queue events from host memory: mom (N, n, 4) (E, px, py, pz)."""
+    pi, po, m, info = _lhe_meta(pdg_in, pdg_out, masses, sqrt_s, weight, scale, aqed, aqcd, proc_id)
+    a = np.ascontiguousarray(mom, dtype=np.float64)
+    if a.ndim != 3 or a.shape[1] != po.size or a.shape[2] != 4:
+        raise ValueError("mom must be (N, n_part, 4)")
+    _check(_c["lhe_write_events_host"](h, po.size, _hptr(pi, _i32), _hptr(po, _i32), _hptr(m, _f64), C.byref(info),
+                                       a.shape[0], _hptr(a, _f64)), "lhe_write_events_host")
+
+
+def lhe_flush(h):
+    n = _i64()
+    _check(_c["lhe_flush"](h, C.byref(n)), "lhe_flush")
+    return int(n.value)
+
+
+def lhe_close(h):
+    _check(_c["lhe_close"](h), "lhe_close")
+
+
+class LheWriter:
+    """Context manager over lhe_open / lhe_write_events / lhe_close; the
+    library's own thread formats and writes the records."""
+
+    def __init__(self, path, **init):
+        self._h = lhe_open(path, **init)
+
+    def write(self, mom, idx, n_kept, *args, **kw):
+        lhe_write_events(self._h, mom, idx, n_kept, *args, **kw)
+
+    def write_host(self, mom, *args, **kw):
+        lhe_write_events_host(self._h, mom, *args, **kw)
+
+    def flush(self):
+        return lhe_flush(self._h)
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            lhe_close(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
 
 def unweight(w, seed, stream_id, iteration, idx, w_max=0.0, stream=None):
