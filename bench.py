@@ -440,6 +440,47 @@ def extra_batch(vgx):
             vgx.vegas_destroy(c)
 
 
+def extra_events(vgx):
+    """Event generation: RAMBO (1e7 events, 4 particles, massless and massive),
+    unweighting of the massive weights, and the LHE writer's rate on 2e5 kept
+    events (formatting and writing by its thread, timed to the flush)."""
+    import os
+    import tempfile
+    import torch
+    n = 10_000_000
+    out = {}
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    mom = torch.empty((4, 4, n), dtype=torch.float64, device="cuda")
+    for name, masses in (("rambo_massless_4", [0.0] * 4), ("rambo_massive_4", [173.0, 173.0, 4.7, 0.0])):
+        fn = lambda: vgx.rambo_generate(masses, 1500.0, 21, 1, 0, 0, mom, w)
+        fn()
+        ms = cuda_timed(fn)
+        byt = n * (4 * 4 + 1) * 8
+        out[name] = {"events_per_s": n / (ms * 1e-3), "ms": ms, "written_GBps": byt / (ms * 1e-3) / 1e9,
+                     "bytes_per_event": (4 * 4 + 1) * 8}
+    idx = torch.empty(n, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for r in range(reps):
+        k, wm = vgx.unweight(w, 21, 2, r, idx)
+    dt = (time.perf_counter() - t0) / reps
+    out["unweight_1e7"] = {"events_per_s": n / dt, "ms_including_sync": dt * 1e3, "kept": k,
+                           "efficiency": k / n}
+    m = 200_000
+    with tempfile.TemporaryDirectory() as d:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with vgx.LheWriter(os.path.join(d, "ev.lhe")) as lw:
+            lw.write(mom, None, m, [21, 21], [6, -6, 5, 21], [173.0, 173.0, 4.7, 0.0], 1500.0)
+            t_queue = time.perf_counter() - t0
+            lw.flush()
+        dt = time.perf_counter() - t0
+        size = os.path.getsize(os.path.join(d, "ev.lhe"))
+    out["lhe_export_2e5"] = {"events_per_s": m / dt, "MB_per_s": size / dt / 1e6, "queue_call_ms": t_queue * 1e3}
+    return out
+
+
 def main():
     args = parse()
     if args.copy_reference:
@@ -552,7 +593,7 @@ def main():
                          "drell_yan_1e7": extra_drellyan(vgx, pdf, n),
                          "single_top_s_1e7": extra_singletop(vgx, pdf, n),
                          "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
-                         "batched_64": extra_batch(vgx)}
+                         "batched_64": extra_batch(vgx), "events": extra_events(vgx)}
     if not args.no_cpu:
         n_cpu = 4_000_000
         eps, secs = cpu_baseline(grid, n_cpu)
