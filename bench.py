@@ -440,6 +440,35 @@ def extra_batch(vgx):
             vgx.vegas_destroy(c)
 
 
+def extra_members(vgx, grid):
+    """Multi-member PDF evaluation: all 11 flavours of N_rep members at the
+    2415 points of C7, FP64 outputs (kernel time from HIP events, median of
+    5, and the wall time of one synchronous call)."""
+    import torch
+    from synth import C7, fk_points, synthetic_pdf_replicas
+    x, q2 = fk_points(C7)
+    xt, qt = torch.from_numpy(x).cuda(), torch.from_numpy(q2).cuda()
+    members = synthetic_pdf_replicas(grid, max(C7["n_rep"]), C7["eps"], C7["seed"])
+    out = {}
+    for n_rep in C7["n_rep"]:
+        ctx = vgx.pdf_create_set(grid.x_knots, grid.q2_knots, members[:n_rep])
+        try:
+            res = torch.empty((n_rep, 11, x.size), dtype=torch.float64, device="cuda")
+            fn = lambda: vgx.pdf_interp_members(ctx, xt, qt, res)
+            fn()
+            ms = cuda_timed(fn)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            evals = n_rep * x.size * 11
+            out[str(n_rep)] = {"kernel_ms": ms, "wall_ms": wall * 1e3, "flavour_evals_per_s": evals / (ms * 1e-3)}
+        finally:
+            vgx.pdf_destroy(ctx)
+    return out
+
+
 def extra_events(vgx):
     """Event generation: RAMBO (1e7 events, 4 particles, massless and massive),
     unweighting of the massive weights, and the LHE writer's rate on 2e5 kept
@@ -593,7 +622,8 @@ def main():
                          "drell_yan_1e7": extra_drellyan(vgx, pdf, n),
                          "single_top_s_1e7": extra_singletop(vgx, pdf, n),
                          "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
-                         "batched_64": extra_batch(vgx), "events": extra_events(vgx)}
+                         "batched_64": extra_batch(vgx), "events": extra_events(vgx),
+                         "pdf_members_fk_2415": extra_members(vgx, grid)}
     if not args.no_cpu:
         n_cpu = 4_000_000
         eps, secs = cpu_baseline(grid, n_cpu)

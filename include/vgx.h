@@ -130,6 +130,13 @@ typedef struct {
  * freed after the call.  VGX_EINVAL on malformed knots. */
 vgx_status pdf_create(const vgx_pdf_desc* desc, void* stream, vgx_pdf** out);
 
+/* A PDF set: n_members grids sharing the descriptor's knots (thesis PDF
+ * chapter, multi-member evaluation: all members of a set loaded at once).
+ * desc->xf holds n_members consecutive member blocks, each laid out as for
+ * pdf_create.  pdf_interp, pdf_alphas and the fused integrands use member 0;
+ * pdf_interp_members evaluates every member.  1 <= n_members <= 65535. */
+vgx_status pdf_create_set(const vgx_pdf_desc* desc, int32_t n_members, void* stream, vgx_pdf** out);
+
 /* xf for every flavour at n points (async).
  *   x_dev, q2_dev : device [n] FP64 query points.
  *   out_dtype     : VGX_F64 or VGX_F32.
@@ -143,6 +150,17 @@ vgx_status pdf_create(const vgx_pdf_desc* desc, void* stream, vgx_pdf** out);
  * n = 0 is a no-op. */
 vgx_status pdf_interp(const vgx_pdf* pdf, int64_t n, const double* x_dev, const double* q2_dev,
                       int32_t out_dtype, void* out_dev, void* stream);
+
+/* Every flavour of every member of a PDF set at n points (async).
+ *   out_dev : device [n_members][n_flav][n] of out_dtype.
+ * Same interpolation as pdf_interp; points outside the grid give NaN in all
+ * members and are counted once (pdf_out_of_range) whatever the extrapolation
+ * mode.  n = 0 is a no-op. */
+vgx_status pdf_interp_members(const vgx_pdf* pdf, int64_t n, const double* x_dev, const double* q2_dev,
+                              int32_t out_dtype, void* out_dev, void* stream);
+
+/* Flavours per member and members of a PDF context (either may be NULL). */
+vgx_status pdf_shape(const vgx_pdf* pdf, int32_t* n_flav, int32_t* n_members);
 
 /* Number of out-of-grid queries seen by pdf_interp since the last call of
  * this function (sync on `stream`); resets the counter.  Returns VGX_ERANGE

@@ -267,6 +267,98 @@ __global__ __launch_bounds__(256) void k_pdf_interp(PdfKernelArgs g, int64_t n, 
   }
 }
 
+// Several members of a PDF set at the same points (the thesis's multi-member
+// evaluation for FastKernel-type convolutions): blockIdx.y is the member, so
+// a wave takes 64 consecutive points of one member and its stores are
+// contiguous; a set of N_rep members at a few thousand points still fills the
+// chip.  The stencil code is that of k_pdf_interp (same weights, same order of
+// summation); it is a kernel of its own so that the tuned single-member
+// kernel keeps its instruction schedule.  Outside the grid: NaN (counted once
+// per point, by member 0), whatever the context's extrapolation mode.
+template <typename OutT, typename ValT, int NF>
+__global__ __launch_bounds__(256) void k_pdf_members(PdfKernelArgs g, int64_t n, int64_t member_stride,
+                                                     const double* __restrict__ qx, const double* __restrict__ qq2,
+                                                     const double* __restrict__ kx, const double* __restrict__ klx,
+                                                     const double* __restrict__ kq2, const double* __restrict__ klq2,
+                                                     const ValT* __restrict__ vals, OutT* __restrict__ out,
+                                                     unsigned long long* __restrict__ oor) {
+  constexpr int NFM = NF > 0 ? NF : VGX_MAX_FLAV;
+  extern __shared__ double lds[];
+  double* sx = lds;
+  double* slx = sx + g.n_x;
+  const int nqt = g.q_off[g.n_sub];
+  double* sq2 = slx + g.n_x;
+  double* slq2 = sq2 + nqt;
+  for (int k = threadIdx.x; k < g.n_x; k += blockDim.x) { sx[k] = kx[k]; slx[k] = klx[k]; }
+  for (int k = threadIdx.x; k < nqt; k += blockDim.x) { sq2[k] = kq2[k]; slq2[k] = klq2[k]; }
+  __syncthreads();
+  const int nf = NF > 0 ? NF : g.n_flav;
+  const int m = blockIdx.y;
+  const ValT* Vm = vals + (int64_t)m * member_stride;
+  OutT* om = out + (int64_t)m * nf * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double x = qx[q];
+    const double q2 = qq2[q];
+    int s = -1;
+    for (int k = 0; k < g.n_sub; ++k) {
+      const bool last = (k == g.n_sub - 1);
+      if (q2 >= g.q2_lo[k] && (q2 < g.q2_hi[k] || (last && q2 <= g.q2_hi[k]))) s = k;
+    }
+    if (s < 0 || !(x >= sx[0] && x <= sx[g.n_x - 1])) {
+      for (int f = 0; f < nf; ++f) om[(int64_t)f * n + q] = (OutT)NAN;
+      if (m == 0) atomicAdd(oor, 1ull);
+      continue;
+    }
+    const int nq = g.nq[s];
+    const double* lq = slq2 + g.q_off[s];
+    const int i = find_cell(sx, g.n_x, x);
+    const int j = find_cell(sq2 + g.q_off[s], nq, q2);
+    const double a = log(x), b = log(q2);
+    const ValT* V = Vm + (int64_t)g.q_off[s] * g.n_x * nf;
+    double acc[NFM];
+#pragma unroll
+    for (int f = 0; f < NFM; ++f) acc[f] = 0.0;
+    if (i >= 1 && i <= g.n_x - 3 && j >= 1 && j <= nq - 3) {
+      const double ha = slx[i + 1] - slx[i];
+      const double hb = lq[j + 1] - lq[j];
+      double cx[4], cq[4];
+      hermite_weights((a - slx[i]) / ha, ha / (slx[i] - slx[i - 1]), ha / (slx[i + 2] - slx[i + 1]), cx);
+      hermite_weights((b - lq[j]) / hb, hb / (lq[j] - lq[j - 1]), hb / (lq[j + 2] - lq[j + 1]), cq);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const ValT* row = V + ((int64_t)(j - 1 + r) * g.n_x + (i - 1)) * nf;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double w = cq[r] * cx[k];
+          const ValT* node = row + k * nf;
+#pragma unroll
+          for (int f = 0; f < NFM; ++f)
+            if (f < nf) acc[f] = fma(w, (double)node[f], acc[f]);
+        }
+      }
+    } else {
+      const double ta = (a - slx[i]) / (slx[i + 1] - slx[i]);
+      const double tb = (b - lq[j]) / (lq[j + 1] - lq[j]);
+      const double w[4] = {(1.0 - ta) * (1.0 - tb), ta * (1.0 - tb), (1.0 - ta) * tb, ta * tb};
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const ValT* row = V + ((int64_t)(j + r) * g.n_x + i) * nf;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const ValT* node = row + k * nf;
+#pragma unroll
+          for (int f = 0; f < NFM; ++f)
+            if (f < nf) acc[f] = fma(w[2 * r + k], (double)node[f], acc[f]);
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NFM; ++f)
+      if (f < nf) om[(int64_t)f * n + q] = (OutT)acc[f];
+  }
+}
+
 // Second pass of a CONTINUE-mode call: the queries outside the grid that
 // k_pdf_interp skipped.  A separate kernel, because inlined into the
 // interpolation loop the FP64 exp/log of the continuation raise its
@@ -367,8 +459,13 @@ __global__ __launch_bounds__(256) void k_alphas(AlphasArgs g, int64_t n, const d
 using namespace vgx;
 
 extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** out) {
+  return pdf_create_set(d, 1, stream, out);
+}
+
+extern "C" vgx_status pdf_create_set(const vgx_pdf_desc* d, int32_t n_members, void* stream, vgx_pdf** out) {
   VGX_CHECK(d && out, "pdf_create: null argument");
   *out = nullptr;
+  VGX_CHECK(n_members >= 1 && n_members <= 65535, "pdf_create_set: n_members %d out of 1..65535", n_members);
   VGX_CHECK(d->n_x >= 2 && d->n_sub >= 1 && d->n_sub <= VGX_MAX_SUB && d->n_flav >= 1 &&
                 d->n_flav <= VGX_MAX_FLAV,
             "pdf_create: bad sizes n_x=%d n_sub=%d n_flav=%d", d->n_x, d->n_sub, d->n_flav);
@@ -381,6 +478,7 @@ extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** 
   p->n_x = d->n_x;
   p->n_sub = d->n_sub;
   p->n_flav = d->n_flav;
+  p->n_members = n_members;
   p->fstride = d->n_flav;  // nodes stored densely (padding to 16 bytes measured slower)
   int tot = 0;
   for (int s = 0; s < d->n_sub; ++s) {
@@ -405,7 +503,8 @@ extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** 
   }
   hipStream_t st = (hipStream_t)stream;
   hipGetDevice(&p->device);
-  const size_t nvals = (size_t)tot * p->n_x * p->n_flav;
+  const size_t nmem = (size_t)tot * p->n_x * p->n_flav;  // values of one member
+  const size_t nvals = nmem * (size_t)n_members;
   p->h_x = (double*)malloc(sizeof(double) * p->n_x);
   p->h_q2 = (double*)malloc(sizeof(double) * tot);
   double* lx = (double*)malloc(sizeof(double) * p->n_x);
@@ -419,16 +518,17 @@ extern "C" vgx_status pdf_create(const vgx_pdf_desc* d, void* stream, vgx_pdf** 
   }
   for (int k = 0; k < p->n_x; ++k) { p->h_x[k] = d->x_knots[k]; lx[k] = log(d->x_knots[k]); }
   for (int k = 0; k < tot; ++k) { p->h_q2[k] = d->q2_knots[k]; lq[k] = log(d->q2_knots[k]); }
-  // re-layout [sub][flav][iq][ix] -> [iq_total][ix][flav]
+  // re-layout each member's [sub][flav][iq][ix] -> [member][iq_total][ix][flav]
   size_t src = 0;
-  for (int s = 0; s < p->n_sub; ++s)
-    for (int f = 0; f < p->n_flav; ++f)
-      for (int iq = 0; iq < p->nq[s]; ++iq)
-        for (int ix = 0; ix < p->n_x; ++ix, ++src) {
-          const size_t dst = ((size_t)(p->q_off[s] + iq) * p->n_x + ix) * p->n_flav + f;
-          v[dst] = d->xf[src];
-          v32[dst] = (float)d->xf[src];
-        }
+  for (int m = 0; m < n_members; ++m)
+    for (int s = 0; s < p->n_sub; ++s)
+      for (int f = 0; f < p->n_flav; ++f)
+        for (int iq = 0; iq < p->nq[s]; ++iq)
+          for (int ix = 0; ix < p->n_x; ++ix, ++src) {
+            const size_t dst = nmem * m + ((size_t)(p->q_off[s] + iq) * p->n_x + ix) * p->n_flav + f;
+            v[dst] = d->xf[src];
+            v32[dst] = (float)d->xf[src];
+          }
   vgx_status st_ = VGX_OK;
   do {
     if ((st_ = dev_alloc((void**)&p->x, sizeof(double) * p->n_x)) != VGX_OK) break;
@@ -508,6 +608,58 @@ extern "C" vgx_status pdf_interp(const vgx_pdf* p, int64_t n, const double* x_de
                          p->lx, p->q2, p->lq2, p->v32, (float*)out_dev);
     VGX_HIP(hipGetLastError());
   }
+  return VGX_OK;
+}
+
+extern "C" vgx_status pdf_interp_members(const vgx_pdf* p, int64_t n, const double* x_dev, const double* q2_dev,
+                                         int32_t out_dtype, void* out_dev, void* stream) {
+  VGX_CHECK(p, "pdf_interp_members: null context");
+  VGX_CHECK(n >= 0, "pdf_interp_members: n < 0");
+  VGX_CHECK(out_dtype == VGX_F64 || out_dtype == VGX_F32, "pdf_interp_members: bad out_dtype %d", out_dtype);
+  if (n == 0) return VGX_OK;
+  VGX_CHECK(x_dev && q2_dev && out_dev, "pdf_interp_members: null device pointer");
+  PdfKernelArgs g{};
+  g.n_x = p->n_x; g.n_sub = p->n_sub; g.n_flav = p->n_flav;
+  for (int s = 0; s < p->n_sub; ++s) {
+    g.nq[s] = p->nq[s];
+    g.q_off[s] = p->q_off[s];
+    g.q2_lo[s] = p->h_q2[p->q_off[s]];
+    g.q2_hi[s] = p->h_q2[p->q_off[s] + p->nq[s] - 1];
+  }
+  g.q_off[p->n_sub] = p->q_off[p->n_sub];
+  const int64_t stride = (int64_t)p->q_off[p->n_sub] * p->n_x * p->n_flav;
+  const int block = 256;
+  // blocks per member: enough to cover the points, the chip filled across members
+  const int64_t want = (n + block - 1) / block;
+  int64_t cap = (int64_t)device_cus() * 8 / p->n_members;
+  cap = cap < 1 ? 1 : cap;
+  const dim3 grid((unsigned)(want < cap ? want : cap), (unsigned)p->n_members);
+  const size_t lds = sizeof(double) * (2 * (size_t)p->n_x + 2 * (size_t)p->q_off[p->n_sub]);
+  hipStream_t st = (hipStream_t)stream;
+  const bool f11 = p->n_flav == 11;
+  if (out_dtype == VGX_F64) {
+    if (f11)
+      hipLaunchKernelGGL((k_pdf_members<double, double, 11>), grid, dim3(block), lds, st, g, n, stride, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
+    else
+      hipLaunchKernelGGL((k_pdf_members<double, double, 0>), grid, dim3(block), lds, st, g, n, stride, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v64, (double*)out_dev, p->oor);
+  } else {
+    if (f11)
+      hipLaunchKernelGGL((k_pdf_members<float, float, 11>), grid, dim3(block), lds, st, g, n, stride, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
+    else
+      hipLaunchKernelGGL((k_pdf_members<float, float, 0>), grid, dim3(block), lds, st, g, n, stride, x_dev, q2_dev,
+                         p->x, p->lx, p->q2, p->lq2, p->v32, (float*)out_dev, p->oor);
+  }
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+extern "C" vgx_status pdf_shape(const vgx_pdf* p, int32_t* n_flav, int32_t* n_members) {
+  VGX_CHECK(p, "pdf_shape: null context");
+  if (n_flav) *n_flav = p->n_flav;
+  if (n_members) *n_members = p->n_members;
   return VGX_OK;
 }
 

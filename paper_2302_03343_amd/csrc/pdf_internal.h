@@ -10,6 +10,7 @@
 struct vgx_pdf {
   int device = 0;
   int n_x = 0, n_sub = 0, n_flav = 0;
+  int n_members = 1;                  // members of a PDF set (shared knots), member-major values
   int fstride = 0;                    // node stride (= n_flav)
   int extrap = VGX_EXTRAP_ERROR;      // behaviour outside the grid (pdf_interp, pdf_alphas)
   int nq[VGX_MAX_SUB] = {0};
@@ -22,7 +23,8 @@ struct vgx_pdf {
   double* lx = nullptr;               // [n_x]            ln x knots
   double* q2 = nullptr;               // [total q]        Q^2 knots
   double* lq2 = nullptr;              // [total q]        ln Q^2 knots
-  double* v64 = nullptr;              // [total q][n_x][fstride]  node values (FP64)
+  double* v64 = nullptr;              // [member][total q][n_x][fstride]  node values (FP64); member 0
+                                      // is what pdf_interp and the fused integrands read
   float* v32 = nullptr;               // same, FP32 copy
   unsigned long long* oor = nullptr;  // out-of-range counter
   // alpha_s(Q) table (optional; pdf_set_alphas): knots on the Q^2 line split

@@ -92,6 +92,9 @@ for _name, _res, _args in [
     ("vgx_version", C.c_char_p, []),
     ("pdf_create", _S, [C.POINTER(PdfDesc), _vp, C.POINTER(_vp)]),
     ("pdf_interp", _S, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
+    ("pdf_create_set", _S, [C.POINTER(PdfDesc), _i32, _vp, C.POINTER(_vp)]),
+    ("pdf_interp_members", _S, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
+    ("pdf_shape", _S, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
     ("pdf_out_of_range", _S, [_vp, _vp, C.POINTER(_i64)]),
     ("pdf_bounds", _S, [_vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64)]),
     ("pdf_set_extrapolation", _S, [_vp, _i32]),
@@ -215,14 +218,50 @@ def pdf_create(x_knots, q2_knots, xf, stream=None):
     return h
 
 
+def pdf_create_set(x_knots, q2_knots, xf_members, stream=None):
+    """A PDF set: xf_members is a list (one per member) of xf lists as for
+    pdf_create; all members share the knots."""
+    x = np.ascontiguousarray(x_knots, dtype=np.float64)
+    nq = np.ascontiguousarray([len(q) for q in q2_knots], dtype=np.int32)
+    q2 = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.float64) for q in q2_knots]))
+    vals = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.float64).ravel()
+                                                for member in xf_members for v in member]))
+    n_flav = int(np.asarray(xf_members[0][0]).shape[0])
+    d = PdfDesc(len(x), len(nq), n_flav, _hptr(x, _f64), _hptr(nq, _i32), _hptr(q2, _f64), _hptr(vals, _f64))
+    h = _vp()
+    _check(_c["pdf_create_set"](C.byref(d), len(xf_members), _stream(stream), C.byref(h)), "pdf_create_set")
+    return h
+
+
+def pdf_shape(pdf):
+    nf, nm = _i32(), _i32()
+    _check(_c["pdf_shape"](pdf, C.byref(nf), C.byref(nm)), "pdf_shape")
+    return int(nf.value), int(nm.value)
+
+
 def pdf_interp(pdf, x, q2, out, out_dtype=None, stream=None):
     import torch
     n = x.numel()
     if out_dtype is None:
         out_dtype = F64 if out.dtype == torch.float64 else F32
     want = torch.float64 if out_dtype == F64 else torch.float32
+    nf, _ = pdf_shape(pdf)
     _check(_c["pdf_interp"](pdf, n, _dptr(x, torch.float64, n, "x"), _dptr(q2, torch.float64, n, "q2"), out_dtype,
-                            _dptr(out, want, None, "out"), _stream(stream)), "pdf_interp")
+                            _dptr(out, want, nf * n, "out"), _stream(stream)), "pdf_interp")
+    return out
+
+
+def pdf_interp_members(pdf, x, q2, out, out_dtype=None, stream=None):
+    """out: CUDA (n_members, n_flav, n)."""
+    import torch
+    n = x.numel()
+    if out_dtype is None:
+        out_dtype = F64 if out.dtype == torch.float64 else F32
+    want = torch.float64 if out_dtype == F64 else torch.float32
+    nf, nm = pdf_shape(pdf)
+    _check(_c["pdf_interp_members"](pdf, n, _dptr(x, torch.float64, n, "x"), _dptr(q2, torch.float64, n, "q2"),
+                                    out_dtype, _dptr(out, want, nm * nf * n, "out"), _stream(stream)),
+           "pdf_interp_members")
     return out
 
 

@@ -7,6 +7,8 @@ C3  64 independent integrals of uneven dimension and sample count, batched.
 C4  coupling-flow proposal trained on VEGAS samples, compared with VEGAS.
 C5  LO Drell-Yan (gamma*/Z -> l+ l-) at sqrt(s) = 13 TeV on the C2 path.
 C6  LO s-channel single top (u dbar -> t bbar) at sqrt(s) = 8 TeV on the C2 path.
+C7  multi-member PDF evaluation: N_rep members of a synthetic set, all 11
+    flavours at 2415 x points of a FastKernel-type grid.
 """
 
 # Flavour order of every PDF array: PDG ids -5..-1, gluon (21), 1..5.
@@ -85,4 +87,16 @@ C6 = dict(
     seed=6, stream=0,
     sqrt_s=8000.0, m_top=173.2, m_w=80.385, gamma_w=2.085, sw2=0.2312, alpha_em=1.0 / 128.0,
     gev2_to_pb=3.893793721e8,
+)
+
+# Multi-member evaluation (the thesis's FastKernel-type benchmark: 11
+# flavours of N_rep members at 2415 x points).  The thesis gives neither the
+# scale nor the x distribution: the points sit at Q0 = 1.65 GeV (a typical
+# fitting scale, inside the charm subgrid of C1), x log-spaced in [1e-7, 0.9].
+# Members: C1's grid times a smooth seeded factor 1 + eps (a + b ln x / ln 1e-9)
+# per member and flavour (a, b standard normal), so zero nodes stay zero.
+C7 = dict(
+    name="pdf-members-fk-2415",
+    n_points=2415, q=1.65, x_lo=1e-7, x_hi=0.9,
+    n_rep=(10, 50, 100, 200, 300, 400), eps=0.05, seed=7,
 )

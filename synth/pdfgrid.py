@@ -133,3 +133,17 @@ def momentum_sum_at_q0(grid):
         A0, a0, b0, c = grid.params[pid]
         tot += A0 * (beta_fn(a0 + 1.0, b0 + 1.0) + c * beta_fn(a0 + 1.5, b0 + 1.0))
     return tot
+
+
+def synthetic_pdf_replicas(grid, n_rep, eps, seed):
+    """n_rep members (lists of per-subgrid (n_flav, n_q, n_x) arrays) around
+    `grid`: member m = grid times 1 + eps (a + b ln x / ln 1e-9), with (a, b)
+    standard normal per member and flavour, shared by all subgrids."""
+    rng = np.random.default_rng(seed)
+    L = np.log(grid.x_knots) / np.log(1e-9)
+    members = []
+    for _ in range(n_rep):
+        ab = rng.standard_normal((len(FLAVOURS), 2))
+        fac = 1.0 + eps * (ab[:, 0:1] + ab[:, 1:2] * L[None, :])  # (n_flav, n_x)
+        members.append([v * fac[:, None, :] for v in grid.xf])
+    return members

@@ -21,3 +21,9 @@ def pdf_queries(n, seed=None, cfg=C1, q_min=None, q_max=None, x_min=None, x_max=
     q2 = np.exp(2.0 * lq)
     q2 = np.clip(q2, q_min ** 2, q_max ** 2)
     return x, q2
+
+
+def fk_points(cfg):
+    """The C7 points: x log-spaced in [x_lo, x_hi], all at Q^2 = q^2."""
+    x = np.exp(np.linspace(np.log(cfg["x_lo"]), np.log(cfg["x_hi"]), cfg["n_points"]))
+    return x, np.full(cfg["n_points"], cfg["q"] ** 2)

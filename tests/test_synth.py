@@ -50,3 +50,21 @@ def test_he_init_segments():
     assert p.dtype == np.float32 and p.size == 448
     assert np.all(p[256:] == 0.0)
     assert abs(np.std(p[:256]) - np.sqrt(2 / 4)) < 0.15
+
+
+def test_pdf_replicas():
+    from synth import C7, synthetic_pdf_replicas, fk_points
+    g = synthetic_pdf_grid()
+    a = synthetic_pdf_replicas(g, 4, C7["eps"], C7["seed"])
+    b = synthetic_pdf_replicas(g, 4, C7["eps"], C7["seed"])
+    assert len(a) == 4 and all(len(m) == len(g.xf) for m in a)
+    for ma, mb in zip(a, b):
+        for va, vb, v0 in zip(ma, mb, g.xf):
+            assert np.array_equal(va, vb) and va.shape == v0.shape
+            assert np.array_equal(va == 0.0, v0 == 0.0)  # zeros stay zeros
+            nz = v0 != 0.0
+            assert np.all(np.abs(va[nz] / v0[nz] - 1.0) < 0.5)
+    assert not np.array_equal(a[0][2], a[1][2])
+    x, q2 = fk_points(C7)
+    assert x.size == 2415 and np.all(np.diff(x) > 0) and np.all(q2 == 1.65 ** 2)
+    assert g.q2_knots[1][0] < q2[0] < g.q2_knots[1][-1]
