@@ -293,6 +293,9 @@ vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double* y_dev, co
 /* Stream the context enqueues on. */
 void* vegas_stream(vgx_vegas* v);
 
+/* Dimension and bins per dimension of a context (either may be NULL). */
+vgx_status vegas_shape(const vgx_vegas* v, int32_t* dim, int32_t* n_bins);
+
 /* Kernel timing (for measurement): when enabled, HIP events on the
  * context's stream bracket every fused sampling kernel (recording does not
  * synchronise; the events carry no system-scope fence, so they add no cache
@@ -433,6 +436,9 @@ typedef struct vgx_flow vgx_flow;
  * b1 [H], W2 [H][H], b2 [H], W3 [|B| K][H], b3 [|B| K] (row-major).
  * Supported: dim 2..VGX_MAX_DIM, n_bins = 32, hidden = 64, n_layers 1..8. */
 int64_t flow_num_params(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden);
+
+/* Dimension and parameter count of a flow (either may be NULL). */
+vgx_status flow_shape(const vgx_flow* f, int32_t* dim, int64_t* n_params);
 
 /* Parameter segments of a flow, in the flat order (host-only, no device
  * work): for each segment its kind (0 = hidden weight matrix, 1 = hidden

@@ -1331,6 +1331,13 @@ extern "C" int64_t flow_num_params(int32_t dim, int32_t n_layers, int32_t n_bins
   return np;
 }
 
+extern "C" vgx_status flow_shape(const vgx_flow* f, int32_t* dim, int64_t* n_params) {
+  VGX_CHECK(f, "flow_shape: null flow");
+  if (dim) *dim = f->dim;
+  if (n_params) *n_params = f->n_par;
+  return VGX_OK;
+}
+
 extern "C" vgx_status flow_param_layout(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden,
                                        int32_t* kind, int32_t* fan_in, int64_t* size, int32_t cap, int32_t* n_seg) {
   VGX_CHECK(n_seg, "flow_param_layout: null n_seg");

@@ -920,6 +920,13 @@ extern "C" vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double
 
 extern "C" void* vegas_stream(vgx_vegas* v) { return v ? (void*)v->stream : nullptr; }
 
+extern "C" vgx_status vegas_shape(const vgx_vegas* v, int32_t* dim, int32_t* n_bins) {
+  VGX_CHECK(v, "vegas_shape: null context");
+  if (dim) *dim = v->dim;
+  if (n_bins) *n_bins = v->nb;
+  return VGX_OK;
+}
+
 extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
   VGX_CHECK(v, "vegas_set_timing: null context");
   if (enable && !v->ev[0]) {

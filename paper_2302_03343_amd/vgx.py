@@ -123,6 +123,7 @@ for _name, _res, _args in [
     ("vegas_sample", _S, [_vp, _i64, _i64, _i32, _vp, _vp]),
     ("vegas_iterate_points", _S, [_vp, _i64, _vp, _vp, C.POINTER(IterResult)]),
     ("vegas_stream", _vp, [_vp]),
+    ("vegas_shape", _S, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
     ("vegas_set_timing", _S, [_vp, _i32]),
     ("vegas_kernel_time", _S, [_vp, C.POINTER(_f64), C.POINTER(_i64)]),
     ("vegas_destroy", None, [_vp]),
@@ -140,6 +141,7 @@ _optional("batch_iterate", _S, _vp, _i32, C.POINTER(IterResult))
 _optional("batch_config", _S, _vp, C.POINTER(_i32), C.POINTER(_i32))
 _optional("batch_destroy", None, _vp)
 _optional("flow_num_params", _i64, _i32, _i32, _i32, _i32)
+_optional("flow_shape", _S, _vp, C.POINTER(_i32), C.POINTER(_i64))
 _optional("flow_param_layout", _S, _i32, _i32, _i32, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i64), _i32,
           C.POINTER(_i32))
 _optional("flow_create", _S, _i32, _i32, _i32, _i32, C.POINTER(_f32), _i64, _vp, C.POINTER(_vp))
@@ -476,9 +478,16 @@ def vegas_get_hist(v, dim, n_bins):
     return h
 
 
+def vegas_shape(v):
+    d, nb = _i32(), _i32()
+    _check(_c["vegas_shape"](v, C.byref(d), C.byref(nb)), "vegas_shape")
+    return int(d.value), int(nb.value)
+
+
 def vegas_sample(v, first, n, iteration, u=None, g=None):
     import torch
-    _check(_c["vegas_sample"](v, first, n, iteration, _dptr(u, torch.float64, None, "u"),
+    dim, _ = vegas_shape(v)
+    _check(_c["vegas_sample"](v, first, n, iteration, _dptr(u, torch.float64, dim * n if u is not None else None, "u"),
                               _dptr(g, torch.float64, n if g is not None else None, "g")), "vegas_sample")
 
 
@@ -486,7 +495,8 @@ def vegas_iterate_points(v, y, logq=None, allow_numeric=False):
     import torch
     n = y.shape[-1]
     r = IterResult()
-    st = _c["vegas_iterate_points"](v, n, _dptr(y, torch.float64, None, "y"),
+    dim, _ = vegas_shape(v)
+    st = _c["vegas_iterate_points"](v, n, _dptr(y, torch.float64, dim * n, "y"),
                                     _dptr(logq, torch.float64, n if logq is not None else None, "logq"),
                                     C.byref(r))
     if not (allow_numeric and st == VGX_ENUMERIC):
@@ -569,16 +579,25 @@ def flow_create(dim, params, n_layers=4, n_bins=32, hidden=64, stream=None):
     return h
 
 
+def flow_shape(f):
+    d, npar = _i32(), _i64()
+    _check(_c["flow_shape"](f, C.byref(d), C.byref(npar)), "flow_shape")
+    return int(d.value), int(npar.value)
+
+
 def flow_sample(f, n, seed, stream_id, iteration, y, logq, stream=None):
     import torch
-    _check(_c["flow_sample"](f, n, seed, stream_id, iteration, _dptr(y, torch.float64, None, "y"),
+    dim, _ = flow_shape(f)
+    _check(_c["flow_sample"](f, n, seed, stream_id, iteration, _dptr(y, torch.float64, dim * n, "y"),
                              _dptr(logq, torch.float64, n, "logq"), _stream(stream)), "flow_sample")
 
 
 def flow_density(f, y, logq, u=None, stream=None):
     import torch
     n = y.shape[-1]
-    _check(_c["flow_density"](f, n, _dptr(y, torch.float64, None, "y"), _dptr(u, torch.float64, None, "u"),
+    dim, _ = flow_shape(f)
+    _check(_c["flow_density"](f, n, _dptr(y, torch.float64, dim * n, "y"),
+                              _dptr(u, torch.float64, dim * n if u is not None else None, "u"),
                               _dptr(logq, torch.float64, n, "logq"), _stream(stream)), "flow_density")
 
 
@@ -587,7 +606,8 @@ def flow_loss_grad(f, y, g, n_params=None):
     n = y.shape[-1]
     loss = _f64()
     grad = np.empty(n_params, dtype=np.float32) if n_params else None
-    _check(_c["flow_loss_grad"](f, n, _dptr(y, torch.float64, None, "y"), _dptr(g, torch.float64, n, "g"),
+    dim, _ = flow_shape(f)
+    _check(_c["flow_loss_grad"](f, n, _dptr(y, torch.float64, dim * n, "y"), _dptr(g, torch.float64, n, "g"),
                                 C.byref(loss), _hptr(grad, _f32) if grad is not None else None), "flow_loss_grad")
     return loss.value, grad
 
@@ -596,7 +616,8 @@ def flow_train_step(f, y, g, lr, sync=True, allow_fallback=False):
     import torch
     n = y.shape[-1]
     loss = _f64()
-    st = _c["flow_train_step"](f, n, _dptr(y, torch.float64, None, "y"), _dptr(g, torch.float64, n, "g"), lr,
+    dim, _ = flow_shape(f)
+    st = _c["flow_train_step"](f, n, _dptr(y, torch.float64, dim * n, "y"), _dptr(g, torch.float64, n, "g"), lr,
                                C.byref(loss) if sync else None)
     if not (allow_fallback and st == VGX_EFALLBACK):
         _check(st, "flow_train_step")
@@ -605,7 +626,8 @@ def flow_train_step(f, y, g, lr, sync=True, allow_fallback=False):
 
 def flow_adam(f, grad, lr):
     import torch
-    _check(_c["flow_adam"](f, _dptr(grad, torch.float32, None, "grad"), lr), "flow_adam")
+    _, n_par = flow_shape(f)
+    _check(_c["flow_adam"](f, _dptr(grad, torch.float32, n_par, "grad"), lr), "flow_adam")
 
 
 def flow_get_params(f, n_params):

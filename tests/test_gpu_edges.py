@@ -103,3 +103,32 @@ def test_flow_ragged_batches_are_prefix_consistent(vgx, dim):
             assert torch.equal(ln, ld[:n])
     finally:
         vgx.flow_destroy(f)
+
+
+def test_binding_rejects_short_buffers(vgx):
+    """Device buffers shorter than the call needs are refused in the binding,
+    before any kernel can write or read past them."""
+    import torch
+    from synth.batch import GAUSS
+    from synth import he_init_segments
+    v = vgx.vegas_create(GAUSS, 3, 20, 1.5, 1, 0, vgx.F64, np.array([0.5] * 3 + [0.1] * 3))
+    try:
+        assert vgx.vegas_shape(v) == (3, 20)
+        with pytest.raises(ValueError):
+            vgx.vegas_sample(v, 0, 100, 0, u=torch.empty((2, 100), dtype=torch.float64, device="cuda"))
+        with pytest.raises(ValueError):
+            vgx.vegas_iterate_points(v, torch.empty((2, 100), dtype=torch.float64, device="cuda"))
+    finally:
+        vgx.vegas_destroy(v)
+    segs = vgx.flow_param_layout(3)
+    f = vgx.flow_create(3, he_init_segments(segs, seed=1))
+    try:
+        dim, n_par = vgx.flow_shape(f)
+        assert dim == 3 and n_par == sum(s[2] for s in segs)
+        with pytest.raises(ValueError):
+            vgx.flow_sample(f, 100, 1, 0, 0, torch.empty((2, 100), dtype=torch.float64, device="cuda"),
+                            torch.empty(100, dtype=torch.float64, device="cuda"))
+        with pytest.raises(ValueError):
+            vgx.flow_adam(f, torch.zeros(n_par - 1, dtype=torch.float32, device="cuda"), 1e-3)
+    finally:
+        vgx.flow_destroy(f)
