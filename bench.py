@@ -233,11 +233,13 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
                    train_batch=batch, flow_batches=k, flow_events=flow_events, mean=res["mean"], sigma=res["sigma"],
                    reached=bool(res["sigma"] <= target * abs(res["mean"])), loss_first=losses[0],
                    loss_last=losses[-1])
-        if last_vegas and last_flow:
-            # relative variance per sample of the weights (n var(E) / E^2)
-            out["rel_var_per_sample_vegas"] = last_vegas["var"] * last_vegas["n"] / last_vegas["mean"] ** 2
-            out["rel_var_per_sample_flow"] = last_flow["var"] * last_flow["n"] / last_flow["mean"] ** 2
-        # sampling cost per event of each sampler
+        # --- after the timed pipeline: the samplers compared per sample and
+        # per unit of time.  relvar = n var(E) / E^2 of the weights.
+        rv = lambda r: r["var"] * r["n"] / r["mean"] ** 2
+        out["rel_var_per_sample_vegas_uniform_grid"] = rv(last_vegas) if last_vegas else None
+        if last_flow:
+            out["rel_var_per_sample_flow"] = rv(last_flow)
+        # cost per event of the flow: sampling and evaluating its points
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         vgx.flow_sample(f, n_flow, seed, 6, 0, y, lq)
@@ -245,6 +247,25 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
         e1.record()
         e1.synchronize()
         out["flow_ns_per_event"] = e0.elapsed_time(e1) * 1e6 / n_flow
+        # the identity-initialised flow draws the VEGAS map's own points: one
+        # fused iteration on the grid the flow was trained on measures it (a
+        # fresh context, so the pipeline's combination is untouched)
+        v2 = vgx.vegas_create(kind, dim, 50, 1.5, seed + 1, 0, prec, params, pdf=pdf)
+        try:
+            vgx.vegas_set_grid(v2, vgx.vegas_get_grid(v, dim, 50))
+            vgx.vegas_set_timing(v2, True)
+            vgx.vegas_iterate_async(v2, n_flow, 0)
+            km, launches = vgx.vegas_kernel_time(v2)
+            r2 = vgx.vegas_results(v2)[0]
+        finally:
+            vgx.vegas_destroy(v2)
+        out["rel_var_per_sample_vegas_refined_grid"] = rv(r2)
+        out["vegas_ns_per_event"] = km / launches * 1e6 / n_flow
+        if last_flow:
+            out["gain_trained_vs_identity_flow"] = rv(r2) / rv(last_flow)
+            # sigma reached in equal wall time (training excluded), flow / VEGAS
+            out["equal_wall_time_sigma_ratio_flow_over_vegas"] = math.sqrt(
+                rv(last_flow) * out["flow_ns_per_event"] / (rv(r2) * out["vegas_ns_per_event"]))
         return out
     finally:
         vgx.flow_destroy(f)
