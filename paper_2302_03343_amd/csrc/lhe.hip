@@ -9,6 +9,9 @@
 // The caller's stream is never synchronised.  Pinned buffers are pooled and
 // reused; they are released by lhe_close.
 //
+// Formatting: std::to_chars (17 significant digits), a batch split over up
+// to eight threads and written in order.
+//
 // Record layout (Les Houches accord, LHE 3.0): an <init> block with the beams
 // and one process; per event a line NUP IDPRUP XWGTUP SCALUP AQEDUP AQCDUP and
 // one line per particle: IDUP ISTUP MOTHUP1 MOTHUP2 ICOLUP1 ICOLUP2 PUP1..PUP5
@@ -19,6 +22,8 @@
 // digits, so FP64 values read back exactly.
 #include "common.h"
 
+#include <algorithm>
+#include <charconv>
 #include <condition_variable>
 #include <deque>
 #include <math.h>
@@ -84,26 +89,78 @@ struct vgx_lhe {
 
 namespace {
 
+// " <v>" with 17 significant digits (the text of printf's %.16e)
+inline void put_d(std::string& out, double v) {
+  char b[40];
+  const auto r = std::to_chars(b, b + sizeof b, v, std::chars_format::scientific, 16);
+  out.push_back(' ');
+  out.append(b, r.ptr);
+}
+
+inline void put_i(std::string& out, long long v) {
+  char b[24];
+  const auto r = std::to_chars(b, b + sizeof b, v);
+  out.push_back(' ');
+  out.append(b, r.ptr);
+}
+
+void put_particle(std::string& out, int pdg, int status, int m1, int m2, double px, double py, double pz, double e,
+                  double mass) {
+  put_i(out, pdg);
+  put_i(out, status);
+  put_i(out, m1);
+  put_i(out, m2);
+  out.append(" 0 0");
+  put_d(out, px);
+  put_d(out, py);
+  put_d(out, pz);
+  put_d(out, e);
+  put_d(out, mass);
+  out.append(" 0 9\n");
+}
+
 void put_event(std::string& out, const Job& J, int64_t j) {
-  char line[512];
-  const int nup = 2 + J.n_part;
-  snprintf(line, sizeof line, "<event>\n %d %d %.16e %.16e %.16e %.16e\n", nup, J.proc, J.weight, J.scale, J.aqed,
-           J.aqcd);
-  out += line;
+  out.append("<event>\n");
+  put_i(out, 2 + J.n_part);
+  put_i(out, J.proc);
+  put_d(out, J.weight);
+  put_d(out, J.scale);
+  put_d(out, J.aqed);
+  put_d(out, J.aqcd);
+  out.push_back('\n');
   const double h = 0.5 * J.sqrt_s;
-  for (int k = 0; k < 2; ++k) {
-    snprintf(line, sizeof line, " %d -1 0 0 0 0 %.16e %.16e %.16e %.16e %.16e 0 9\n", J.pdg_in[k], 0.0, 0.0,
-             k == 0 ? h : -h, h, 0.0);
-    out += line;
-  }
+  put_particle(out, J.pdg_in[0], -1, 0, 0, 0.0, 0.0, h, h, 0.0);
+  put_particle(out, J.pdg_in[1], -1, 0, 0, 0.0, 0.0, -h, h, 0.0);
   const double* p = J.host + (size_t)j * J.n_part * 4;
   for (int i = 0; i < J.n_part; ++i) {
     const double* v = p + 4 * i;
-    snprintf(line, sizeof line, " %d 1 1 2 0 0 %.16e %.16e %.16e %.16e %.16e 0 9\n", J.pdg_out[i], v[1], v[2], v[3],
-             v[0], J.masses[i]);
-    out += line;
+    put_particle(out, J.pdg_out[i], 1, 1, 2, v[1], v[2], v[3], v[0], J.masses[i]);
   }
-  out += "</event>\n";
+  out.append("</event>\n");
+}
+
+// Format a batch: contiguous slices of events on up to kFormatThreads
+// threads, written in order.
+constexpr int kFormatThreads = 8;
+constexpr int64_t kEventsPerThread = 4096;
+
+bool format_and_write(const Job& J, FILE* f) {
+  const int64_t want = (J.n + kEventsPerThread - 1) / kEventsPerThread;
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int T = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min(kFormatThreads, hw)));
+  std::vector<std::string> parts(T);
+  auto work = [&](int t) {
+    const int64_t lo = J.n * t / T, hi = J.n * (t + 1) / T;
+    parts[t].reserve((size_t)(hi - lo) * (size_t)(J.n_part + 4) * 110);
+    for (int64_t j = lo; j < hi; ++j) put_event(parts[t], J, j);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < T; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
+  for (const std::string& s : parts)
+    if (fwrite(s.data(), 1, s.size(), f) != s.size()) return false;
+  return true;
 }
 
 void writer_loop(vgx_lhe* h) {
@@ -118,12 +175,7 @@ void writer_loop(vgx_lhe* h) {
     }
     bool ok = true;
     if (J.ready) ok = hipEventSynchronize(J.ready) == hipSuccess;
-    std::string out;
-    if (ok) {
-      out.reserve((size_t)J.n * (size_t)(J.n_part + 4) * 120);
-      for (int64_t j = 0; j < J.n; ++j) put_event(out, J, j);
-      ok = fwrite(out.data(), 1, out.size(), h->f) == out.size();
-    }
+    if (ok) ok = format_and_write(J, h->f);
     std::lock_guard<std::mutex> lk(h->mu);
     if (!ok && !h->error) {
       h->error = 1;
