@@ -48,11 +48,10 @@ __global__ __launch_bounds__(RB_BLOCK) void k_rambo(RamboArgs a, double* __restr
     for (int i = 0; i < N; ++i) {
       const u32x4 r = philox4x32_10((uint32_t)idx, (uint32_t)(idx >> 32), a.it, (a.sid << 8) | (uint32_t)i, a.k0, a.k1);
       const double c = 2.0 * word_to_unit(r.x) - 1.0;
-      const double phi = 2.0 * M_PI * word_to_unit(r.y);
       const double e0 = -log(word_to_unit(r.z) * word_to_unit(r.w));
       const double st = sqrt(1.0 - c * c);
       double sn, cs;
-      sincos(phi, &sn, &cs);
+      sincospi(2.0 * word_to_unit(r.y), &sn, &cs);  // phi = 2 pi u, without a reduction modulo 2 pi
       q[i][0] = e0;
       q[i][1] = e0 * st * cs;
       q[i][2] = e0 * st * sn;
