@@ -326,3 +326,34 @@ def test_full_batch_gradient_matches_oracle(vgx):
         assert cos > 0.995
     finally:
         vgx.flow_destroy(f)
+
+
+def test_training_is_bit_reproducible(vgx):
+    """Every reduction of a training step has a fixed order (tiles within a
+    workgroup in wave order, workgroup partials in a fixed tree), so two
+    identical trainings end with identical parameters, bit for bit."""
+    import torch
+    from synth import he_init_segments
+    from synth.batch import GAUSS
+    print("flow training bit-reproducible", flush=True)
+    dim, n = 3, 50_000
+    segs = vgx.flow_param_layout(dim)
+    n_par = sum(s[2] for s in segs)
+    prm = np.concatenate([np.full(dim, 0.4), np.full(dim, 0.12)])
+    finals = []
+    for _ in range(2):
+        v = vgx.vegas_create(GAUSS, dim, 50, 1.5, 3, 0, vgx.F64, prm)
+        f = vgx.flow_create(dim, he_init_segments(segs, seed=9))
+        try:
+            u = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+            g = torch.empty(n, dtype=torch.float64, device="cuda")
+            losses = []
+            for s in range(8):
+                vgx.vegas_sample(v, 0, n, 100 + s, u=u, g=g)
+                losses.append(vgx.flow_train_step(f, u, g, 1e-3))
+            finals.append((losses, vgx.flow_get_params(f, n_par)))
+        finally:
+            vgx.flow_destroy(f)
+            vgx.vegas_destroy(v)
+    assert finals[0][0] == finals[1][0]
+    assert np.array_equal(finals[0][1], finals[1][1])
