@@ -47,7 +47,15 @@ struct VegasArgs {
   const double* edges;
   int nb;
   int pstride;   // doubles per workgroup partial row
+  int hcopies;   // histogram copies in LDS: one per wave, or 1 (shared)
 };
+
+// Histogram copies a workgroup keeps in LDS: one per wave when they fit in
+// 16 KB (each wave's atomics then meet only its own lanes, and the copies are
+// summed in wave order), else one shared by all waves.
+__host__ __device__ inline int hist_copies(int D, int nb) {
+  return (BLOCK / 64) * D * nb * (int)sizeof(double) <= 16384 ? BLOCK / 64 : 1;
+}
 
 // ---------------------------------------------------------------------------
 // Sample sources
@@ -75,9 +83,9 @@ struct PointsSrc {
 };
 
 // Offset (in doubles, even: 16-byte aligned) of the integrand tables after
-// the edges [D][nb+1] and, with histograms, [D][nb].
+// the edges [D][nb+1] and, with histograms, [copies][D][nb].
 __host__ __device__ inline int lds_table_offset(int D, int nb, bool hist) {
-  const int n = D * (nb + 1) + (hist ? D * nb : 0);
+  const int n = D * (nb + 1) + (hist ? hist_copies(D, nb) * D * nb : 0);
   return (n + 1) & ~1;
 }
 
@@ -104,7 +112,7 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   float* extra = (float*)(lds + lds_table_offset(D, nb, HIST));
   for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
   if (HIST)
-    for (int k = threadIdx.x; k < D * nb; k += BLOCK) sh[k] = 0.0;
+    for (int k = threadIdx.x; k < a.hcopies * D * nb; k += BLOCK) sh[k] = 0.0;
   F ff = f;
   if constexpr (F::kStage) ff.stage(extra);
   __syncthreads();
@@ -112,6 +120,7 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   // a scalar register) and the lane (mbcnt), so that no vector register has
   // to carry it across the sample loop.
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* hw = sh + (a.hcopies > 1 ? wv * D * nb : 0);  // this wave's histogram
 
   Comp c1, c2;
   double p1 = 0.0, p2 = 0.0;
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
     }
     if (HIST) {
 #pragma unroll
-      for (int j = 0; j < D; ++j) atomicAdd(&sh[j * nb + idx[j]], w2);
+      for (int j = 0; j < D; ++j) atomicAdd(&hw[j * nb + idx[j]], w2);
     }
   }
   c1.add(p1);
@@ -153,7 +162,11 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
     row[tid] = s;
   }
   if (HIST)
-    for (int k = tid; k < D * nb; k += BLOCK) row[4 + k] = sh[k];
+    for (int k = tid; k < D * nb; k += BLOCK) {
+      double h = sh[k];
+      for (int c = 1; c < a.hcopies; ++c) h += sh[c * D * nb + k];  // wave order
+      row[4 + k] = h;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -525,7 +538,7 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
 // Launch helpers dispatching on (kind, prec, D).
 template <int D, class F, class Src, bool HIST>
 vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb)};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST) + extra_lds_bytes(v);
   hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
@@ -592,7 +605,7 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
 
 template <int D, class F>
 vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, const F& f, double* u, double* g) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb)};
   PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false) + extra_lds_bytes(v);
