@@ -127,7 +127,12 @@ typedef struct {
 } vgx_pdf_desc;
 
 /* Copy a grid to the device (sync).  The descriptor's host arrays may be
- * freed after the call.  VGX_EINVAL on malformed knots. */
+ * freed after the call.  VGX_EINVAL on malformed knots, on a value that is
+ * not finite or beyond the FP32 range (the FP32-output path reads an FP32
+ * copy), and when 16 (n_x + total Q^2 knots) + 2048 s bytes exceed 64 KiB,
+ * s = max(9, n_flav) rounded up to odd (the knots and per-query slots the
+ * interpolation kernel keeps in LDS: up to 2688 knots in all for 11
+ * flavours, 2944 for one). */
 vgx_status pdf_create(const vgx_pdf_desc* desc, void* stream, vgx_pdf** out);
 
 /* A PDF set: n_members grids sharing the descriptor's knots (thesis PDF
