@@ -11,10 +11,12 @@
 //   * work is cut into tiles of T consecutive samples of one integral; the
 //     tiles of all integrals form one index space, integral i owning the
 //     range [tile0_i, tile0_i + ntiles_i);
-//   * a persistent grid (a few workgroups per CU) pops tile indices from an
-//     atomic counter, so integrals with 1e4 and 1e7 samples load-balance
-//     across the 256 CUs; a workgroup re-stages the grid edges in LDS only
-//     when the integral changes between its tiles;
+//   * a persistent grid (as many workgroups as can be resident at once)
+//     pops tile indices from an atomic counter, so integrals with 1e4 and
+//     1e7 samples load-balance across the 256 CUs; a workgroup re-stages the
+//     grid edges in LDS only when the integral changes between its tiles;
+//   * the tile's histogram is kept in up to four LDS copies (lane l adds into
+//     copy l mod copies) and summed in copy order;
 //   * every tile writes its own partial row (S1, S2 compensated, histogram),
 //     so the reduction kernel sums each integral's rows in tile order: the
 //     result does not depend on which workgroup took which tile;
@@ -30,6 +32,7 @@
 #include "integrands.h"
 #include "vegas_internal.h"
 
+#include <algorithm>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -38,6 +41,18 @@
 namespace vgx {
 
 constexpr int BB_MAX = 256;  // launch bound of the persistent kernel
+// Copies of a tile's LDS histogram (1, 2 or 4 per batch, as many as fit in
+// kCopiesLds with the edges): lane l adds into copy l mod copies, so lanes of
+// one atomic instruction that fall into the same bin mostly hit different
+// addresses (LDS atomics on one address serialise); a copy is D nb + 1
+// doubles so that a bin's copies fall on different banks.  The copies are
+// summed in copy order when the tile's row is written.
+constexpr int kMaxHistCopies = 4;
+constexpr size_t kCopiesLds = 48 * 1024;
+__host__ __device__ inline int hist_stride(int dim, int nb) { return dim * nb + 1; }
+__host__ __device__ inline size_t batch_lds_bytes(int dim, int nb, int copies) {
+  return sizeof(double) * ((size_t)dim * (nb + 1) + (size_t)copies * hist_stride(dim, nb));
+}
 
 struct BatchItem {
   int kind, prec, dim, nb;
@@ -110,7 +125,8 @@ __global__ void k_batch_begin(BatchState* st) {
 }
 
 __global__ __launch_bounds__(BB_MAX) void k_batch(const BatchItem* __restrict__ items, int count, int64_t total_tiles,
-                                                 int tile, BatchState* __restrict__ st, double* __restrict__ partials) {
+                                                 int tile, int copies, BatchState* __restrict__ st,
+                                                 double* __restrict__ partials) {
   extern __shared__ double lds[];
   __shared__ int64_t s_tile;
   __shared__ int s_item;
@@ -141,25 +157,27 @@ __global__ __launch_bounds__(BB_MAX) void k_batch(const BatchItem* __restrict__ 
       cur = k;
     }
     sh = se + ne;
-    for (int q = threadIdx.x; q < it.dim * it.nb; q += blockDim.x) sh[q] = 0.0;
+    const int hs = hist_stride(it.dim, it.nb);
+    for (int q = threadIdx.x; q < copies * hs; q += blockDim.x) sh[q] = 0.0;
     __syncthreads();
     const int64_t lt = t - it.tile0;
     const int64_t s0 = lt * tile;
     const int64_t s1 = (s0 + tile < it.n) ? s0 + tile : it.n;
     Comp c1, c2;
+    double* shl = sh + (threadIdx.x & (copies - 1)) * hs;  // this lane's histogram copy
     switch (it.dim) {
-      case 1: run_tile_d<1>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 2: run_tile_d<2>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 3: run_tile_d<3>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 4: run_tile_d<4>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 5: run_tile_d<5>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 6: run_tile_d<6>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 7: run_tile_d<7>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 8: run_tile_d<8>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 9: run_tile_d<9>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 10: run_tile_d<10>(it, se, sh, s0, s1, iter, c1, c2); break;
-      case 11: run_tile_d<11>(it, se, sh, s0, s1, iter, c1, c2); break;
-      default: run_tile_d<12>(it, se, sh, s0, s1, iter, c1, c2); break;
+      case 1: run_tile_d<1>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 2: run_tile_d<2>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 3: run_tile_d<3>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 4: run_tile_d<4>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 5: run_tile_d<5>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 6: run_tile_d<6>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 7: run_tile_d<7>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 8: run_tile_d<8>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 9: run_tile_d<9>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 10: run_tile_d<10>(it, se, shl, s0, s1, iter, c1, c2); break;
+      case 11: run_tile_d<11>(it, se, shl, s0, s1, iter, c1, c2); break;
+      default: run_tile_d<12>(it, se, shl, s0, s1, iter, c1, c2); break;
     }
     const double v0 = wave_sum(c1.s), v1 = wave_sum(c1.c), v2 = wave_sum(c2.s), v3 = wave_sum(c2.c);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -171,7 +189,11 @@ __global__ __launch_bounds__(BB_MAX) void k_batch(const BatchItem* __restrict__ 
       for (int q = 0; q < nw; ++q) s += red[threadIdx.x][q];
       row[threadIdx.x] = s;
     }
-    for (int q = threadIdx.x; q < it.dim * it.nb; q += blockDim.x) row[4 + q] = sh[q];
+    for (int q = threadIdx.x; q < it.dim * it.nb; q += blockDim.x) {
+      double h = sh[q];
+      for (int c = 1; c < copies; ++c) h += sh[c * hs + q];
+      row[4 + q] = h;
+    }
     __syncthreads();  // LDS histogram and s_tile are reused by the next tile
   }
 }
@@ -226,6 +248,7 @@ struct vgx_batch {
   double* partials = nullptr;
   size_t part_cap = 0;               // doubles
   int tile = 0, block = 0, grid = 0;
+  int copies = 1;                    // LDS histogram copies per workgroup
   int64_t total_tiles = 0;
   size_t lds = 0;
   int max_cols = 0;
@@ -265,13 +288,25 @@ vgx_status upload_items(vgx_batch* b, hipStream_t st) {
 vgx_status enqueue_iteration(vgx_batch* b, hipStream_t st, bool refine) {
   hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, st, b->d_state);
   hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(b->block), b->lds, st, b->d_items, b->count, b->total_tiles,
-                     b->tile, b->d_state, b->partials);
+                     b->tile, b->copies, b->d_state, b->partials);
   if (refine) {
     hipLaunchKernelGGL(k_batch_reduce, dim3((b->max_cols + 63) / 64, b->count), dim3(256), 0, st, b->d_items,
                        b->partials);
     hipLaunchKernelGGL(k_batch_refine, dim3(VGX_MAX_DIM, b->count), dim3(64), 0, st, b->d_items, b->d_state);
   }
   VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+// Block size of the persistent kernel and a grid of as many workgroups as
+// can be resident at once (the kernel's occupancy at that block size): more
+// would only start once the tile queue is empty.
+vgx_status set_block(vgx_batch* b, int block) {
+  int per_cu = 0;
+  VGX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch), block,
+                                                       b->lds));
+  b->block = block;
+  b->grid = device_cus() * (per_cu > 0 ? per_cu : 1);
   return VGX_OK;
 }
 
@@ -283,8 +318,7 @@ vgx_status autotune(vgx_batch* b, int fixed_tile, int fixed_block) {
   int best_t = fixed_tile > 0 ? fixed_tile : 8192, best_b = fixed_block > 0 ? fixed_block : 256;
   if (fixed_tile > 0 && fixed_block > 0) {
     layout(b, fixed_tile);
-    b->block = fixed_block;
-    return VGX_OK;
+    return set_block(b, fixed_block);
   }
   hipEvent_t e0, e1;
   VGX_HIP(hipEventCreate(&e0));
@@ -295,7 +329,7 @@ vgx_status autotune(vgx_batch* b, int fixed_tile, int fixed_block) {
     for (int bl : blocks) {
       if (fixed_block > 0 && bl != fixed_block) continue;
       layout(b, ti);
-      b->block = bl;
+      VGX_TRY(set_block(b, bl));
       VGX_TRY(upload_items(b, b->stream));
       float ms_best = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
@@ -313,8 +347,7 @@ vgx_status autotune(vgx_batch* b, int fixed_tile, int fixed_block) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   layout(b, best_t);
-  b->block = best_b;
-  return VGX_OK;
+  return set_block(b, best_b);
 }
 
 }  // namespace
@@ -343,7 +376,7 @@ extern "C" vgx_status batch_create(vgx_vegas* const* ctxs, int32_t count, const 
   b->ctx.assign(ctxs, ctxs + count);
   b->n.assign(n_samples, n_samples + count);
   b->items.resize(count);
-  size_t max_lds = 0;
+  size_t max_lds[3] = {0, 0, 0};  // workgroup LDS with 1, 2, 4 histogram copies
   for (int k = 0; k < count; ++k) {
     const vgx_vegas* c = ctxs[k];
     BatchItem it{};
@@ -363,12 +396,11 @@ extern "C" vgx_status batch_create(vgx_vegas* const* ctxs, int32_t count, const 
     it.comb = c->comb;
     it.prm = c->prm;
     b->items[k] = it;
-    const size_t l = sizeof(double) * ((size_t)c->dim * (c->nb + 1) + (size_t)c->dim * c->nb);
-    max_lds = l > max_lds ? l : max_lds;
+    for (int q = 0; q < 3; ++q) max_lds[q] = std::max(max_lds[q], batch_lds_bytes(c->dim, c->nb, 1 << q));
     b->max_cols = it.pstride > b->max_cols ? it.pstride : b->max_cols;
   }
-  b->lds = max_lds;
-  b->grid = device_cus() * 4;
+  b->copies = max_lds[2] <= kCopiesLds ? 4 : (max_lds[1] <= kCopiesLds ? 2 : 1);
+  b->lds = max_lds[b->copies == 4 ? 2 : b->copies - 1];
   vgx_status s = VGX_OK;
   do {
     b->part_cap = partial_doubles(b, tile > 0 ? tile : 2048);
