@@ -76,6 +76,38 @@ def measured_traffic(events_per_launch):
         return None
 
 
+EXTRA_NAMES = ("ttbar_fixed_scale_contraction", "ttbar_dynamic_scale", "drell_yan_1e7", "single_top_s_1e7",
+               "pdf_interp_1e8", "vegas_gauss4_f64", "batched_64", "events", "pdf_members_fk_2415")
+
+
+def extras_table(vgx, pdf, grid, params, n):
+    """The extra workloads by name, each a function of no arguments."""
+    return {"ttbar_fixed_scale_contraction": lambda: extra_ttbar_contracted(vgx, pdf, params, n),
+            "ttbar_dynamic_scale": lambda: extra_ttbar_dynamic(vgx, pdf, grid, params, n),
+            "drell_yan_1e7": lambda: extra_drellyan(vgx, pdf, n),
+            "single_top_s_1e7": lambda: extra_singletop(vgx, pdf, n),
+            "pdf_interp_1e8": lambda: extra_pdf(vgx, pdf),
+            "vegas_gauss4_f64": lambda: extra_gauss(vgx),
+            "batched_64": lambda: extra_batch(vgx),
+            "events": lambda: extra_events(vgx),
+            "pdf_members_fk_2415": lambda: extra_members(vgx, grid)}
+
+
+def one_extra(name, n_events):
+    """One extra workload alone (for profiling its kernels)."""
+    import numpy as np
+    from paper_2302_03343_amd import vgx
+    from synth import C2, synthetic_pdf_grid
+    grid = synthetic_pdf_grid()
+    pdf = vgx.pdf_create(grid.x_knots, grid.q2_knots, grid.xf)
+    params = np.array([C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]])
+    try:
+        res = extras_table(vgx, pdf, grid, params, n_events or C2["n_per_iter"])[name]()
+        print(json.dumps({"workload": name, name: res}), flush=True)
+    finally:
+        vgx.pdf_destroy(pdf)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +123,8 @@ def parse():
                          "batched integrals) as extra fields")
     ap.add_argument("--pdf-only", action="store_true",
                     help="only the PDF interpolation workload (1e8 queries, FP64 and FP32 outputs); one JSON line")
+    ap.add_argument("--extra", choices=EXTRA_NAMES, default=None,
+                    help="only the named extra workload (for profiling its kernels); one JSON line")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 2 GiB device copy (reference for scaling HBM counters) and exit")
     return ap.parse_args()
@@ -539,6 +573,9 @@ def main():
     if args.pdf_only:
         pdf_only()
         return
+    if args.extra:
+        one_extra(args.extra, args.events)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -638,13 +675,7 @@ def main():
                                batch=C4["batch"], lr=C4["lr"], n_flow=10_000_000, seed=C4["seed"])
             out["time_to_1e-4"]["gauss8"] = {"vegas": gv, "flow": gf}
     if args.extras:
-        out["extras"] = {"ttbar_fixed_scale_contraction": extra_ttbar_contracted(vgx, pdf, params, n),
-                         "ttbar_dynamic_scale": extra_ttbar_dynamic(vgx, pdf, grid, params, n),
-                         "drell_yan_1e7": extra_drellyan(vgx, pdf, n),
-                         "single_top_s_1e7": extra_singletop(vgx, pdf, n),
-                         "pdf_interp_1e8": extra_pdf(vgx, pdf), "vegas_gauss4_f64": extra_gauss(vgx),
-                         "batched_64": extra_batch(vgx), "events": extra_events(vgx),
-                         "pdf_members_fk_2415": extra_members(vgx, grid)}
+        out["extras"] = {k: f() for k, f in extras_table(vgx, pdf, grid, params, n).items()}
     if not args.no_cpu:
         n_cpu = 4_000_000
         eps, secs = cpu_baseline(grid, n_cpu)
