@@ -50,14 +50,18 @@ struct PdfRowsConst {
   int q_off;        // global knot offset of the subgrid
   double lmu2;      // ln mu^2
   int contract;     // 1: Q^2 direction contracted once per workgroup
+  // set on the host from the knots (kernel arguments, so scalar registers):
+  float qh[4];      // Q-row weights at mu^2: cubic Hermite on rows 0..3 (four rows), or linear on rows 0, 1
+  float ql[4];      // linear Q weights on the cell (j, j + 1): the bilinear rule's rows
+  float a0, inv_da; // cell guess for knots uniform in ln x: first staged ln x, 1 / spacing
+  int uniform;      // 1 when the staged ln x knots are uniform to 1e-3 of a spacing
 };
 
 // LDS footprint in floats for nxs staged x nodes: node values, padded to a
 // multiple of 4 nodes, [4][nxs/4][11][4 rows] (16-byte aligned float4 per
-// node and flavour), ln x knots, inverse spacings, Q weights and the
-// cell-guess constants.
+// node and flavour), ln x knots and inverse spacings.
 __host__ __device__ inline int pdf_rows_lds_floats(int nxs) {
-  return ((nxs + 3) & ~3) * 4 * TT_NF + 2 * nxs + 16;
+  return ((nxs + 3) & ~3) * 4 * TT_NF + 2 * nxs;
 }
 
 struct PdfRows {
@@ -67,8 +71,6 @@ struct PdfRows {
   int nq4;          // staged nodes per residue class mod 4
   float* sa;        // LDS ln x knots [nxs]
   float* sinv;      // LDS 1/(a_{k+1} - a_k) [nxs]
-  float* qw;        // LDS [0..3] Q-row Hermite weights, [4] bilinear t_b, [5] a_0, [6] 1/da, [7] uniform flag,
-                    // [8..11] linear Q-row weights of the bilinear fallback
 
   __device__ void stage(float* lds) {
     float* Fs = lds;
@@ -77,7 +79,6 @@ struct PdfRows {
     nq4 = (nxs + 3) >> 2;
     sa = Fs + nq4 * 4 * 4 * TT_NF;
     sinv = sa + nxs;
-    qw = sinv + nxs;
     const int nr = c.n_rows;
     const int tot = nq4 * 4 * TT_NF * 4;
     const double* lx = c.lx + c.ix0;
@@ -91,47 +92,6 @@ struct PdfRows {
     for (int k = threadIdx.x; k < nxs; k += blockDim.x) {
       sa[k] = (float)lx[k];
       sinv[k] = k + 1 < nxs ? (float)(1.0 / (lx[k + 1] - lx[k])) : 0.0f;
-    }
-    if (threadIdx.x == 0) {
-      // weights of the Q rows at mu^2 (FP64 setup, FP32 storage)
-      const double* lq = c.lq2 + c.q_off;
-      const int j = c.j_local;
-      const double hb = lq[j + 1] - lq[j];
-      const double t = (c.lmu2 - lq[j]) / hb;
-      if (c.n_rows == 4) {
-        const double rm = hb / (lq[j] - lq[j - 1]), rp = hb / (lq[j + 2] - lq[j + 1]);
-        const double t2 = t * t, t3 = t2 * t;
-        const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
-        qw[0] = (float)(-0.5 * h10 * rm);
-        qw[1] = (float)(h00 - 0.5 * h10 + 0.5 * h10 * rm - 0.5 * h11);
-        qw[2] = (float)(h01 + 0.5 * h10 - 0.5 * h11 * rp + 0.5 * h11);
-        qw[3] = (float)(0.5 * h11 * rp);
-      } else {
-        qw[0] = (float)(1.0 - t);
-        qw[1] = (float)t;
-        qw[2] = 0.0f;
-        qw[3] = 0.0f;
-      }
-      qw[4] = (float)t;  // linear weight in ln Q^2 for the bilinear fallback
-      // cell guess for knots uniform in ln x (checked here; else binary search)
-      const int n = nxs;
-      const double a0 = lx[0], da = (lx[n - 1] - lx[0]) / (n - 1);
-      bool uni = true;
-      for (int k = 0; k < n; ++k)
-        if (fabs(lx[k] - (a0 + k * da)) > 1e-3 * da) uni = false;
-      qw[5] = (float)a0;
-      qw[6] = (float)(1.0 / da);
-      qw[7] = uni ? 1.0f : 0.0f;
-    }
-    if (threadIdx.x == 0) {
-      // linear Q weights on the cell (j, j+1) for the bilinear fallback: rows
-      // 1, 2 of four staged rows, or 0, 1 of two
-      const float tb = qw[4];
-      const bool four = c.n_rows == 4;
-      qw[8] = four ? 0.0f : 1.0f - tb;
-      qw[9] = four ? 1.0f - tb : tb;
-      qw[10] = four ? tb : 0.0f;
-      qw[11] = 0.0f;
     }
     if (c.contract) {
       // fixed scale: contract the Q^2 direction once.  P with the Hermite Q
@@ -149,8 +109,8 @@ struct PdfRows {
         float hp = 0.f, lp = 0.f;
         if (f < TT_NF && n < nxs) {
           const float4 v = F[node_off(n) + f];
-          hp = fmaf(qw[0], v.x, fmaf(qw[1], v.y, fmaf(qw[2], v.z, qw[3] * v.w)));
-          lp = fmaf(qw[8], v.x, fmaf(qw[9], v.y, qw[10] * v.z));
+          hp = fmaf(c.qh[0], v.x, fmaf(c.qh[1], v.y, fmaf(c.qh[2], v.z, c.qh[3] * v.w)));
+          lp = fmaf(c.ql[0], v.x, fmaf(c.ql[1], v.y, fmaf(c.ql[2], v.z, c.ql[3] * v.w)));
         }
         pv[0][q] = hp;
         pv[1][q] = lp;
@@ -174,10 +134,10 @@ struct PdfRows {
   __device__ __forceinline__ int cell(float a) const {
     const int nx = c.nxs;
     const int klo = c.ix0 > 0 ? 1 : 0;
-    if (qw[7] != 0.0f) {
+    if (c.uniform) {
       // guess from the uniform spacing, then settle on the stored knots
       // (the same cell as a binary search over sa)
-      int i = (int)((a - qw[5]) * qw[6]);
+      int i = (int)((a - c.a0) * c.inv_da);
       i = i < klo ? klo : (i > nx - 2 ? nx - 2 : i);
       while (i > klo && a < sa[i]) --i;
       while (i < nx - 2 && a >= sa[i + 1]) ++i;
@@ -195,29 +155,33 @@ struct PdfRows {
   // weights w.  full: both axes have their four knots, w is the cubic
   // Hermite (secant slopes); else the bilinear fallback, expressed as the
   // same 4-node window with weights (1 - t, t) on the cell's corners and
-  // zeros elsewhere, so that every lane runs one code path.
+  // zeros elsewhere, so that every lane runs one code path.  Bilinear cells
+  // lie at the grid's edges: a wave whose lanes all have the full stencil
+  // (nearly every wave) skips the fallback's weights.
   __device__ __forceinline__ void window(float a, int& base, float (&w)[4], bool& full) const {
     const int nx = c.nxs;
     const int i = cell(a);
     const float t = (a - sa[i]) * sinv[i];
     full = c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3;
     base = i - 1 < 0 ? 0 : (i - 1 > nx - 4 ? nx - 4 : i - 1);
-    const int pos = i - base;  // 1 for the full stencil
     const float hk = sa[i + 1] - sa[i];
     const float rm = hk * sinv[i >= 1 ? i - 1 : 0];
     const float rp = hk * sinv[i + 1];
     const float t2 = t * t, t3 = t2 * t;
     const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
     const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
-    const float c0 = -0.5f * h10 * rm;
-    const float c1 = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
-    const float c2 = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
-    const float c3 = 0.5f * h11 * rp;
-    const float u = 1.f - t;
-    w[0] = full ? c0 : (pos == 0 ? u : 0.f);
-    w[1] = full ? c1 : (pos == 1 ? u : (pos == 0 ? t : 0.f));
-    w[2] = full ? c2 : (pos == 2 ? u : (pos == 1 ? t : 0.f));
-    w[3] = full ? c3 : (pos == 2 ? t : 0.f);
+    w[0] = -0.5f * h10 * rm;
+    w[1] = h00 - 0.5f * h10 + 0.5f * h10 * rm - 0.5f * h11;
+    w[2] = h01 + 0.5f * h10 - 0.5f * h11 * rp + 0.5f * h11;
+    w[3] = 0.5f * h11 * rp;
+    if (!__all(full)) {
+      const int pos = i - base;  // 1 for the full stencil
+      const float u = 1.f - t;
+      w[0] = full ? w[0] : (pos == 0 ? u : 0.f);
+      w[1] = full ? w[1] : (pos == 1 ? u : (pos == 0 ? t : 0.f));
+      w[2] = full ? w[2] : (pos == 2 ? u : (pos == 1 ? t : 0.f));
+      w[3] = full ? w[3] : (pos == 2 ? t : 0.f);
+    }
   }
 
   // step k of a window starting at base visits node 4 mb + k + 4 [k < r]
@@ -265,8 +229,13 @@ struct PdfRows {
       return;
     }
     // Q weights: Hermite for full cells, linear on the cell otherwise
-    const float q0 = full ? qw[0] : qw[8], q1 = full ? qw[1] : qw[9];
-    const float q2 = full ? qw[2] : qw[10], q3 = full ? qw[3] : qw[11];
+    float q0 = c.qh[0], q1 = c.qh[1], q2 = c.qh[2], q3 = c.qh[3];
+    if (!__all(full)) {
+      q0 = full ? q0 : c.ql[0];
+      q1 = full ? q1 : c.ql[1];
+      q2 = full ? q2 : c.ql[2];
+      q3 = full ? q3 : c.ql[3];
+    }
 #pragma unroll
     for (int f = 0; f < TT_NF; ++f) xf[f] = 0.0f;
 #pragma unroll

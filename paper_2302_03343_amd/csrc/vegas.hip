@@ -345,6 +345,40 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
   if (j >= 1 && j <= nq - 3) { t.n_rows = 4; t.row0 = pdf->q_off[sub] + j - 1; }
   else { t.n_rows = 2; t.row0 = pdf->q_off[sub] + j; }
   t.contract = contract ? 1 : 0;
+  // Q-row weights at mu^2 (FP64, stored FP32): the cubic Hermite with secant
+  // slopes on the four rows around mu^2, linear on the cell when two rows are
+  // staged; ql: linear on the cell (j, j + 1), rows 1, 2 of four or 0, 1 of two
+  {
+    const double lj = log(q[j]), lj1 = log(q[j + 1]);
+    const double hb = lj1 - lj;
+    const double tb = (t.lmu2 - lj) / hb;
+    if (t.n_rows == 4) {
+      const double rm = hb / (lj - log(q[j - 1])), rp = hb / (log(q[j + 2]) - lj1);
+      const double t2 = tb * tb, t3 = t2 * tb;
+      const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + tb, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+      t.qh[0] = (float)(-0.5 * h10 * rm);
+      t.qh[1] = (float)(h00 - 0.5 * h10 + 0.5 * h10 * rm - 0.5 * h11);
+      t.qh[2] = (float)(h01 + 0.5 * h10 - 0.5 * h11 * rp + 0.5 * h11);
+      t.qh[3] = (float)(0.5 * h11 * rp);
+      t.ql[0] = 0.0f; t.ql[1] = (float)(1.0 - tb); t.ql[2] = (float)tb; t.ql[3] = 0.0f;
+    } else {
+      t.qh[0] = (float)(1.0 - tb); t.qh[1] = (float)tb; t.qh[2] = 0.0f; t.qh[3] = 0.0f;
+      t.ql[0] = t.qh[0]; t.ql[1] = t.qh[1]; t.ql[2] = 0.0f; t.ql[3] = 0.0f;
+    }
+  }
+  // cell guess for staged ln x knots uniform to 1e-3 of a spacing (else a
+  // binary search)
+  {
+    const int n = t.nxs;
+    const double a0 = log(pdf->h_x[t.ix0]), an = log(pdf->h_x[t.ix0 + n - 1]);
+    const double da = (an - a0) / (n - 1);
+    bool uni = true;
+    for (int k = 0; k < n; ++k)
+      if (fabs(log(pdf->h_x[t.ix0 + k]) - (a0 + k * da)) > 1e-3 * da) uni = false;
+    t.a0 = (float)a0;
+    t.inv_da = (float)(1.0 / da);
+    t.uniform = uni ? 1 : 0;
+  }
   return VGX_OK;
 }
 
