@@ -135,13 +135,15 @@ struct PdfRows {
     const int nx = c.nxs;
     const int klo = c.ix0 > 0 ? 1 : 0;
     if (c.uniform) {
-      // guess from the uniform spacing, then settle on the stored knots
-      // (the same cell as a binary search over sa)
+      // knots uniform to 1e-3 of a spacing (FP32 rounding of ln x adds about
+      // 1e-5 of a spacing): the guess from the spacing is the right cell or
+      // its neighbour, and one comparison with each end of the guessed cell
+      // settles it (the same cell as a binary search over sa)
       int i = (int)((a - c.a0) * c.inv_da);
-      i = i < klo ? klo : (i > nx - 2 ? nx - 2 : i);
-      while (i > klo && a < sa[i]) --i;
-      while (i < nx - 2 && a >= sa[i + 1]) ++i;
-      return i;
+      i = i < 0 ? 0 : (i > nx - 2 ? nx - 2 : i);
+      const float lo = sa[i], hi = sa[i + 1];
+      i += (a >= hi && i < nx - 2 ? 1 : 0) - (a < lo && i > 0 ? 1 : 0);
+      return i < klo ? klo : i;
     }
     int lo = 0, hi = nx - 1;
     while (hi - lo > 1) {
