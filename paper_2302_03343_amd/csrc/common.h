@@ -72,7 +72,9 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 
 // u = (k + 1/2) 2^-32, exact in FP64, strictly inside (0, 1).
 __device__ __forceinline__ double word_to_unit(uint32_t k) {
-  return ((double)k + 0.5) * 0x1p-32;
+  // k 2^-32 has at most 32 significant bits, so k 2^-32 + 2^-33 is exact:
+  // one FMA gives (k + 1/2) 2^-32 bit for bit
+  return fma((double)k, 0x1p-32, 0x1p-33);
 }
 
 // Uniforms of dims [0, D) of sample i; block b covers dims 4b..4b+3.
