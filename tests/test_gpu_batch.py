@@ -125,3 +125,39 @@ def test_batch_rejects_bad_input(vgx, pdf_ctx):
             vgx.vegas_destroy(t)
     finally:
         vgx.vegas_destroy(c)
+
+
+@pytest.mark.parametrize("big_bins", [110, 256])
+def test_batch_with_large_histograms(vgx, big_bins):
+    """Histograms too large for four LDS copies per workgroup: 12 x 110 bins
+    takes two copies, 12 x 256 one; sums, histograms and refined grids still
+    equal those of the single-integral path."""
+    print(f"batch with a 12 x {big_bins} histogram", flush=True)
+    shapes = [(12, big_bins, 40_000), (2, 50, 30_000), (5, 77, 25_001)]
+
+    def make_ctx(k, d, nb):
+        params = np.concatenate([np.full(d, 0.45), np.full(d, 0.25)])
+        return vgx.vegas_create(vgx.GAUSS, d, nb, 1.5, 31, 40 + k, vgx.F32, params)
+
+    A = [make_ctx(k, d, nb) for k, (d, nb, _) in enumerate(shapes)]
+    B = [make_ctx(k, d, nb) for k, (d, nb, _) in enumerate(shapes)]
+    try:
+        b = vgx.batch_create(A, [n for _, _, n in shapes], 0, 0)
+        try:
+            for it in range(3):
+                rb = vgx.batch_iterate(b, it, len(shapes))
+                for k, (d, nb, n) in enumerate(shapes):
+                    rs = vgx.vegas_iterate(B[k], n, it)
+                    hb, hs = vgx.vegas_get_hist(A[k], d, nb), vgx.vegas_get_hist(B[k], d, nb)
+                    assert np.allclose(hb, hs, rtol=1e-12, atol=0.0)
+                    vgx.vegas_refine(B[k])
+                    assert rb[k]["s1"] == pytest.approx(rs["s1"], rel=1e-12)
+                    assert rb[k]["s2"] == pytest.approx(rs["s2"], rel=1e-12)
+            for k, (d, nb, _) in enumerate(shapes):
+                ea, eb = vgx.vegas_get_grid(A[k], d, nb), vgx.vegas_get_grid(B[k], d, nb)
+                assert np.max(np.abs(ea - eb)) < 1e-12
+        finally:
+            vgx.batch_destroy(b)
+    finally:
+        for c in A + B:
+            vgx.vegas_destroy(c)
