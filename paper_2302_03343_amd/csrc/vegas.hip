@@ -47,14 +47,20 @@ struct VegasArgs {
   const double* edges;
   int nb;
   int pstride;   // doubles per workgroup partial row
-  int hcopies;   // histogram copies in LDS: one per wave, or 1 (shared)
+  int hcopies;   // histogram copies in LDS: 4 per wave, one per wave, or 1 (shared)
 };
 
 // Histogram copies a workgroup keeps in LDS: one per wave when they fit in
 // 16 KB (each wave's atomics then meet only its own lanes, and the copies are
-// summed in wave order), else one shared by all waves.
-__host__ __device__ inline int hist_copies(int D, int nb) {
-  return (BLOCK / 64) * D * nb * (int)sizeof(double) <= 16384 ? BLOCK / 64 : 1;
+// summed in wave order), else one shared by all waves.  Integrands that stage
+// no tables in LDS (lane_groups) take four per wave when they fit in 32 KB,
+// lane l of wave w adding into copy 4 w + l mod 4: lanes of one atomic
+// instruction that fall into the same bin then mostly hit different
+// addresses (LDS atomics on one address serialise).
+__host__ __device__ inline int hist_copies(int D, int nb, bool lane_groups) {
+  const int waves = BLOCK / 64, bytes = D * nb * (int)sizeof(double);
+  if (lane_groups && 4 * waves * bytes <= 32768) return 4 * waves;
+  return waves * bytes <= 16384 ? waves : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -84,8 +90,8 @@ struct PointsSrc {
 
 // Offset (in doubles, even: 16-byte aligned) of the integrand tables after
 // the edges [D][nb+1] and, with histograms, [copies][D][nb].
-__host__ __device__ inline int lds_table_offset(int D, int nb, bool hist) {
-  const int n = D * (nb + 1) + (hist ? hist_copies(D, nb) * D * nb : 0);
+__host__ __device__ inline int lds_table_offset(int D, int nb, bool hist, bool lane_groups) {
+  const int n = D * (nb + 1) + (hist ? hist_copies(D, nb, lane_groups) * D * nb : 0);
   return (n + 1) & ~1;
 }
 
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   double* se = lds;
   double* sh = se + D * (nb + 1);
   // integrand tables start on a 16-byte boundary (they are read as float4)
-  float* extra = (float*)(lds + lds_table_offset(D, nb, HIST));
+  float* extra = (float*)(lds + lds_table_offset(D, nb, HIST, !F::kStage));
   for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
   if (HIST)
     for (int k = threadIdx.x; k < a.hcopies * D * nb; k += BLOCK) sh[k] = 0.0;
@@ -120,7 +126,15 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   // a scalar register) and the lane (mbcnt), so that no vector register has
   // to carry it across the sample loop.
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double* hw = sh + (a.hcopies > 1 ? wv * D * nb : 0);  // this wave's histogram
+  // this wave's (integrands with LDS tables: a uniform pointer) or this
+  // lane's histogram copy
+  double* hw;
+  if constexpr (F::kStage) {
+    hw = sh + (a.hcopies > 1 ? wv * D * nb : 0);
+  } else {
+    const int hc = a.hcopies > BLOCK / 64 ? 4 * wv + (int)(threadIdx.x & 3) : (a.hcopies > 1 ? wv : 0);
+    hw = sh + hc * D * nb;
+  }
 
   Comp c1, c2;
   double p1 = 0.0, p2 = 0.0;
@@ -164,7 +178,7 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   if (HIST)
     for (int k = tid; k < D * nb; k += BLOCK) {
       double h = sh[k];
-      for (int c = 1; c < a.hcopies; ++c) h += sh[c * D * nb + k];  // wave order
+      for (int c = 1; c < a.hcopies; ++c) h += sh[c * D * nb + k];  // copy order
       row[4 + k] = h;
     }
 }
@@ -247,7 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_vegas_sample(VegasArgs a, F f, Philox
   extern __shared__ __align__(16) double lds[];
   const int nb = a.nb;
   double* se = lds;
-  float* extra = (float*)(lds + lds_table_offset(D, nb, false));
+  float* extra = (float*)(lds + lds_table_offset(D, nb, false, !F::kStage));
   for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
   F ff = f;
   if constexpr (F::kStage) ff.stage(extra);
@@ -288,7 +302,7 @@ size_t extra_lds_bytes(const vgx_vegas* v) {
 // fills the chip.
 int hadronic_blocks_per_cu(const vgx_vegas* v) {
   int occ = 0;
-  const size_t lds = sizeof(double) * (size_t)lds_table_offset(3, v->nb, true) + extra_lds_bytes(v);
+  const size_t lds = sizeof(double) * (size_t)lds_table_offset(3, v->nb, true, false) + extra_lds_bytes(v);
   const void* k = (v->kind == VGX_TTBAR && v->tt_dyn)
                       ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbarDyn, PhiloxSrc<3>, true>)
                   : v->kind == VGX_TTBAR    ? reinterpret_cast<const void*>(&k_vegas_iter<3, TTbar, PhiloxSrc<3>, true>)
@@ -572,9 +586,9 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
 // Launch helpers dispatching on (kind, prec, D).
 template <int D, class F, class Src, bool HIST>
 vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb)};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage)};
   const int grid = grid_for(v, n);
-  const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST) + extra_lds_bytes(v);
+  const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST, !F::kStage) + extra_lds_bytes(v);
   hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
                      v->partials);
   VGX_HIP(hipGetLastError());
@@ -639,10 +653,10 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
 
 template <int D, class F>
 vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, const F& f, double* u, double* g) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb)};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage)};
   PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
   const int grid = grid_for(v, n);
-  const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false) + extra_lds_bytes(v);
+  const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false, !F::kStage) + extra_lds_bytes(v);
   hipLaunchKernelGGL((k_vegas_sample<D, F>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src, u, g);
   VGX_HIP(hipGetLastError());
   return VGX_OK;
