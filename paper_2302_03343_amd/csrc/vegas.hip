@@ -144,7 +144,9 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
     double u[D], x[D];
     int idx[D];
     const double ws = src.get(i, u);
-    const double jac = grid_map<D>(u, se, nb, x, idx);
+    double jac;
+    if constexpr (F::kStage) jac = grid_map<D>(u, se, nb, x, idx);
+    else jac = grid_map_split<D>(u, se, a.edges, nb, x, idx);  // the LDS is the limit here
     const double w = ff.eval(x) * jac * ws;
     const double w2 = w * w;
     p1 += w;

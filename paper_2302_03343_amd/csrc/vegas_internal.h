@@ -52,6 +52,40 @@ __device__ __forceinline__ double grid_map(const double (&u)[D], const double* s
   return jac;
 }
 
+// The same map with the edge pairs of the odd dimensions read from global
+// memory (one 16-byte load, served by the L1: the grid is a few KB) instead
+// of LDS, for kernels whose LDS is their limit and whose vector-memory path
+// is otherwise idle.  The edges are the same, so is the result.
+typedef double double2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+template <int D>
+__device__ __forceinline__ double grid_map_split(const double (&u)[D], const double* se,
+                                                 const double* __restrict__ ge, int nb, double (&x)[D],
+                                                 int (&idx)[D]) {
+  double jac = 1.0;
+  const double dnb = (double)nb;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double t = u[j] * dnb;
+    int i = (int)t;
+    i = i < nb - 1 ? i : nb - 1;
+    i = i > 0 ? i : 0;
+    const double delta = t - (double)i;
+    double lo, w;
+    if (j & 1) {
+      const double2_a8 e = *(const double2_a8*)(ge + j * (nb + 1) + i);
+      lo = e.x;
+      w = e.y - lo;
+    } else {
+      lo = se[j * (nb + 1) + i];
+      w = se[j * (nb + 1) + i + 1] - lo;
+    }
+    x[j] = fma(delta, w, lo);
+    jac *= dnb * w;
+    idx[j] = i;
+  }
+  return jac;
+}
+
 // Butterfly merge of compensated sums over the 64 lanes of a wave, in a fixed
 // order (partner distance 1, 2, 4, ..., 32).
 __device__ __forceinline__ Comp wave_merge(Comp a) {
