@@ -86,7 +86,7 @@ __device__ __forceinline__ void run_tile(const BatchItem& it, const F& f, const 
     double u[D], x[D];
     int idx[D];
     philox_uniforms<D>((uint64_t)i, iter, it.sid, it.k0, it.k1, u);
-    const double jac = grid_map<D>(u, se, it.nb, x, idx);
+    const double jac = grid_map_split<D>(u, se, it.edges, it.nb, x, idx);  // the LDS is the limit here
     const double w = f.eval(x) * jac;
     const double w2 = w * w;
     p1 += w;
