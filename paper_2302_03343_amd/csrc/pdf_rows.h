@@ -37,7 +37,6 @@ struct PdfRowsConst {
   const float* v32; // device [iq][ix][fstride] FP32 grid
   int fstride;
   const double* lx; // device ln x knots
-  const double* lq2;// device ln Q^2 knots (all subgrids)
   int n_x;          // x knots of the grid
   int ix0;          // first staged x node: events never reach ln x below the
                     // smallest reachable momentum fraction, so nodes below
@@ -45,10 +44,6 @@ struct PdfRowsConst {
   int nxs;          // staged x nodes, n_x - ix0
   int row0;         // global index of the first staged Q^2 row
   int n_rows;       // 4 (bicubic in Q) or 2 (bilinear in Q)
-  int j_local;      // cell index of mu^2 inside its subgrid
-  int nq_sub;       // knots in that subgrid
-  int q_off;        // global knot offset of the subgrid
-  double lmu2;      // ln mu^2
   int contract;     // 1: Q^2 direction contracted once per workgroup
   // set on the host from the knots (kernel arguments, so scalar registers):
   float qh[4];      // Q-row weights at mu^2: cubic Hermite on rows 0..3 (four rows), or linear on rows 0, 1

@@ -344,7 +344,6 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
   t.v32 = pdf->v32;
   t.fstride = pdf->fstride;
   t.lx = pdf->lx;
-  t.lq2 = pdf->lq2;
   t.n_x = pdf->n_x;
   // every event has ln x >= ln x_min; stage from two cells below the cell of
   // x_min (margin for FP32 rounding of ln x)
@@ -354,10 +353,6 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
   if (pdf->n_x - t.ix0 < 4) t.ix0 = pdf->n_x - 4 > 0 ? pdf->n_x - 4 : 0;
   t.nxs = pdf->n_x - t.ix0;
   VGX_CHECK(t.nxs >= 4, "%s needs at least 4 x knots", who);
-  t.j_local = j;
-  t.nq_sub = nq;
-  t.q_off = pdf->q_off[sub];
-  t.lmu2 = log(mu2);
   if (j >= 1 && j <= nq - 3) { t.n_rows = 4; t.row0 = pdf->q_off[sub] + j - 1; }
   else { t.n_rows = 2; t.row0 = pdf->q_off[sub] + j; }
   t.contract = contract ? 1 : 0;
@@ -367,7 +362,7 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
   {
     const double lj = log(q[j]), lj1 = log(q[j + 1]);
     const double hb = lj1 - lj;
-    const double tb = (t.lmu2 - lj) / hb;
+    const double tb = (log(mu2) - lj) / hb;
     if (t.n_rows == 4) {
       const double rm = hb / (lj - log(q[j - 1])), rp = hb / (log(q[j + 2]) - lj1);
       const double t2 = tb * tb, t3 = t2 * tb;
