@@ -25,8 +25,8 @@ parametrisation; the readings used here are:
         * beta / (32 pi s_hat) * 0.3893793721e9 pb GeV^2,
     PDFs at mu^2 = m_t^2, fixed alpha_s, no cuts.
 
-Dynamic scale (the survey's next step on this path; the thesis's PDF tools
-evaluate xf at any (x, Q^2) and alpha_s(Q) by log-cubic interpolation):
+Dynamic scale (the thesis's PDF tools evaluate xf at any (x, Q^2) and
+alpha_s(Q) by log-cubic interpolation):
 integrand_dynamic() sets mu^2 = s_hat/4 per event, with alpha_s(mu) from the
 PDF set's alpha_s table.
 
