@@ -457,6 +457,7 @@ extern "C" vgx_status batch_iterate(vgx_batch* b, int32_t iteration, vgx_iter_re
   vgx_status s = VGX_OK;
   for (int k = 0; k < b->count; ++k) {
     b->ctx[k]->n_rec++;
+    b->ctx[k]->comb_fresh = false;
     b->ctx[k]->have_hist = true;
     const IterRecord& r = b->pinned[k];
     if (out) {

@@ -782,10 +782,15 @@ vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n) {
   return VGX_OK;
 }
 
+// Record k and the combination in one round trip: a later vegas_result
+// reads the combination from the host copy until new records are enqueued.
 vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out) {
   IterRecord* h = (IterRecord*)v->pinned;
+  Combined* hc = (Combined*)((char*)v->pinned + sizeof(IterRecord) * MAX_RECORDS);
   VGX_HIP(hipMemcpyAsync(h, v->rec + k, sizeof(IterRecord), hipMemcpyDeviceToHost, v->stream));
+  VGX_HIP(hipMemcpyAsync(hc, v->comb, sizeof(Combined), hipMemcpyDeviceToHost, v->stream));
   VGX_HIP(hipStreamSynchronize(v->stream));
+  v->comb_fresh = true;
   if (out) {
     out->mean = h->mean;
     out->var = h->var;
@@ -863,12 +868,14 @@ static vgx_status iterate_enqueue(vgx_vegas* v, int64_t n, int32_t iteration) {
 
 extern "C" vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, vgx_iter_result* out) {
   VGX_TRY(iterate_enqueue(v, n, iteration));
+  v->comb_fresh = false;
   const int k = v->n_rec++;
   return read_record(v, k, out);
 }
 
 extern "C" vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration) {
   VGX_TRY(iterate_enqueue(v, n, iteration));
+  v->comb_fresh = false;
   v->n_rec++;
   return VGX_OK;
 }
@@ -891,8 +898,11 @@ extern "C" vgx_status vegas_result(vgx_vegas* v, double* mean, double* sigma, do
     if (n_used) *n_used = 0;
     return VGX_OK;
   }
-  VGX_HIP(hipMemcpyAsync(h, v->comb, sizeof(Combined), hipMemcpyDeviceToHost, v->stream));
-  VGX_HIP(hipStreamSynchronize(v->stream));
+  if (!v->comb_fresh) {
+    VGX_HIP(hipMemcpyAsync(h, v->comb, sizeof(Combined), hipMemcpyDeviceToHost, v->stream));
+    VGX_HIP(hipStreamSynchronize(v->stream));
+    v->comb_fresh = true;
+  }
   if (mean) *mean = h->mean;
   if (sigma) *sigma = h->sigma;
   if (chi2) *chi2 = h->chi2_dof;
@@ -922,6 +932,7 @@ extern "C" vgx_status vegas_results(vgx_vegas* v, vgx_iter_result* out, int32_t 
 extern "C" vgx_status vegas_reset_results(vgx_vegas* v) {
   VGX_CHECK(v, "vegas_reset_results: null context");
   v->n_rec = 0;
+  v->comb_fresh = false;
   VGX_HIP(hipMemsetAsync(v->comb, 0, sizeof(Combined), v->stream));
   return VGX_OK;
 }
@@ -972,6 +983,7 @@ extern "C" vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double
   VGX_TRY(launch_points_iter(v, n, y, logq));
   VGX_TRY(timed_end(v));
   VGX_TRY(launch_reduce(v, grid_for(v, n), 4, n));
+  v->comb_fresh = false;
   const int k = v->n_rec++;
   return read_record(v, k, out);
 }

@@ -262,6 +262,7 @@ struct vgx_vegas {
   vgx::Combined* comb = nullptr;
   void* pinned = nullptr;           // host readback (IterRecord + Combined + grid)
   int n_rec = 0;
+  bool comb_fresh = false;           // the host copy of the combination (in pinned) is current
   bool have_hist = false;
   // kernel timing: event pairs recorded around the fused kernel, read back
   // (and summed) only when asked for, so timing does not synchronise

@@ -337,3 +337,44 @@ def test_run_to_run_agreement(vgx, dim, nb):
     for a, b in zip(ga, gb):
         assert np.max(np.abs(a - b)) < 1e-13
     assert ca["mean"] == pytest.approx(cb["mean"], rel=1e-12)
+
+
+def test_result_after_every_kind_of_update(vgx):
+    """vegas_result after synchronous and asynchronous iterations, a points
+    iteration and a reset always equals the combination of the stored
+    estimates (the synchronous calls read the combination with the record;
+    the others must fetch it again)."""
+    import torch
+    print("result after mixed updates", flush=True)
+    dim, nb = 3, 20
+    v = make(vgx, GAUSS, dim, nb, seed=4, params=gauss_params(dim, 0.5, 0.2))
+
+    def check(n_expected):
+        res = vgx.vegas_result(v)
+        per = vgx.vegas_results(v)
+        assert len(per) == n_expected and res["n_used"] == n_expected
+        m, s, c = ov.combine([p["mean"] for p in per], [p["var"] for p in per])
+        assert res["mean"] == pytest.approx(m, rel=1e-14)
+        assert res["sigma"] == pytest.approx(s, rel=1e-13)
+        if n_expected > 1:
+            assert res["chi2_dof"] == pytest.approx(c, rel=1e-10)
+
+    try:
+        vgx.vegas_iterate(v, 5_000, 0)
+        check(1)
+        vgx.vegas_refine(v)
+        check(1)
+        vgx.vegas_iterate_async(v, 5_000, 1)
+        check(2)
+        vgx.vegas_iterate(v, 5_000, 2)
+        vgx.vegas_iterate_async(v, 5_000, 3)
+        check(4)
+        y = torch.rand((dim, 3000), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+        vgx.vegas_iterate_points(v, y, None)
+        check(5)
+        vgx.vegas_reset_results(v)
+        assert vgx.vegas_result(v)["n_used"] == 0
+        vgx.vegas_iterate(v, 5_000, 4)
+        check(1)
+    finally:
+        vgx.vegas_destroy(v)
