@@ -54,9 +54,9 @@ struct PdfRowsConst {
 
 // LDS footprint in floats for nxs staged x nodes: node values, padded to a
 // multiple of 4 nodes, [4][nxs/4][11][4 rows] (16-byte aligned float4 per
-// node and flavour), ln x knots and inverse spacings.
+// node and flavour), ln x knots (padded to 4) and a float4 per cell.
 __host__ __device__ inline int pdf_rows_lds_floats(int nxs) {
-  return ((nxs + 3) & ~3) * 4 * TT_NF + 2 * nxs;
+  return ((nxs + 3) & ~3) * 4 * TT_NF + ((nxs + 3) & ~3) + 4 * nxs;
 }
 
 struct PdfRows {
@@ -65,7 +65,8 @@ struct PdfRows {
   const float4* F;  // LDS [4][nq4][11] float4: the (up to) four Q^2 rows of one node and flavour
   int nq4;          // staged nodes per residue class mod 4
   float* sa;        // LDS ln x knots [nxs]
-  float* sinv;      // LDS 1/(a_{k+1} - a_k) [nxs]
+  float4* cw;       // LDS per cell k: (a_k, 1/h_k, h_k/h_{k-1}, h_k/h_{k+1}), h_k = a_{k+1} - a_k
+                    // (FP32 knots; h_{-1} read as h_0, 1/h_{nxs-1} as 0)
 
   __device__ void stage(float* lds) {
     float* Fs = lds;
@@ -73,7 +74,7 @@ struct PdfRows {
     const int nxs = c.nxs;
     nq4 = (nxs + 3) >> 2;
     sa = Fs + nq4 * 4 * 4 * TT_NF;
-    sinv = sa + nxs;
+    cw = (float4*)(sa + ((nxs + 3) & ~3));
     const int nr = c.n_rows;
     const int tot = nq4 * 4 * TT_NF * 4;
     const double* lx = c.lx + c.ix0;
@@ -86,7 +87,10 @@ struct PdfRows {
     }
     for (int k = threadIdx.x; k < nxs; k += blockDim.x) {
       sa[k] = (float)lx[k];
-      sinv[k] = k + 1 < nxs ? (float)(1.0 / (lx[k + 1] - lx[k])) : 0.0f;
+      // the inverse spacings of cells k - 1, k, k + 1 (0 past the last knot)
+      auto inv = [&](int m) { return m + 1 < nxs ? (float)(1.0 / (lx[m + 1] - lx[m])) : 0.0f; };
+      const float hk = k + 1 < nxs ? (float)lx[k + 1] - (float)lx[k] : 0.0f;
+      cw[k] = make_float4((float)lx[k], inv(k), hk * inv(k >= 1 ? k - 1 : 0), hk * inv(k + 1));
     }
     if (c.contract) {
       // fixed scale: contract the Q^2 direction once.  P with the Hermite Q
@@ -158,12 +162,11 @@ struct PdfRows {
   __device__ __forceinline__ void window(float a, int& base, float (&w)[4], bool& full) const {
     const int nx = c.nxs;
     const int i = cell(a);
-    const float t = (a - sa[i]) * sinv[i];
+    const float4 q = cw[i];
+    const float t = (a - q.x) * q.y;
     full = c.n_rows == 4 && i + c.ix0 >= 1 && i <= nx - 3;
     base = i - 1 < 0 ? 0 : (i - 1 > nx - 4 ? nx - 4 : i - 1);
-    const float hk = sa[i + 1] - sa[i];
-    const float rm = hk * sinv[i >= 1 ? i - 1 : 0];
-    const float rp = hk * sinv[i + 1];
+    const float rm = q.z, rp = q.w;
     const float t2 = t * t, t3 = t2 * t;
     const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t;
     const float h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
