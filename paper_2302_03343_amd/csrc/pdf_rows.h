@@ -59,14 +59,34 @@ __host__ __device__ inline int pdf_rows_lds_floats(int nxs) {
   return ((nxs + 3) & ~3) * 4 * TT_NF + ((nxs + 3) & ~3) + 4 * nxs;
 }
 
+// Cell k of a knot list s[0..n) (FP32) with s[k] <= a < s[k+1], clamped to
+// [0, n - 2], for knots uniform to 1e-3 of a spacing (FP32 rounding of the
+// logarithms adds about 1e-5 of a spacing): the guess from the spacing is the
+// right cell or its neighbour, and one comparison with each end of the
+// guessed cell settles it (the same cell as a binary search over s).
+__device__ __forceinline__ int uniform_knot_cell(const float* s, int n, float a, float a0, float inv_d) {
+  int i = (int)((a - a0) * inv_d);
+  i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+  const float lo = s[i], hi = s[i + 1];
+  return i + (a >= hi && i < n - 2 ? 1 : 0) - (a < lo && i > 0 ? 1 : 0);
+}
+
+// Per cell k of a knot list (FP32 knots s): (s_k, 1/h_k, h_k/h_{k-1},
+// h_k/h_{k+1}) with h_k = s_{k+1} - s_k, h_{-1} read as h_0 and 1/h past
+// the last knot as 0: the Hermite window's inputs in one 16-byte read.
+__device__ __forceinline__ float4 knot_cell_data(const double* l, int n, int k) {
+  auto inv = [&](int m) { return m + 1 < n ? (float)(1.0 / (l[m + 1] - l[m])) : 0.0f; };
+  const float hk = k + 1 < n ? (float)l[k + 1] - (float)l[k] : 0.0f;
+  return make_float4((float)l[k], inv(k), hk * inv(k >= 1 ? k - 1 : 0), hk * inv(k + 1));
+}
+
 struct PdfRows {
   PdfRowsConst c;
   // LDS tables are indexed by the staged node k = ix - ix0
   const float4* F;  // LDS [4][nq4][11] float4: the (up to) four Q^2 rows of one node and flavour
   int nq4;          // staged nodes per residue class mod 4
   float* sa;        // LDS ln x knots [nxs]
-  float4* cw;       // LDS per cell k: (a_k, 1/h_k, h_k/h_{k-1}, h_k/h_{k+1}), h_k = a_{k+1} - a_k
-                    // (FP32 knots; h_{-1} read as h_0, 1/h_{nxs-1} as 0)
+  float4* cw;       // LDS per cell: knot_cell_data
 
   __device__ void stage(float* lds) {
     float* Fs = lds;
@@ -87,10 +107,7 @@ struct PdfRows {
     }
     for (int k = threadIdx.x; k < nxs; k += blockDim.x) {
       sa[k] = (float)lx[k];
-      // the inverse spacings of cells k - 1, k, k + 1 (0 past the last knot)
-      auto inv = [&](int m) { return m + 1 < nxs ? (float)(1.0 / (lx[m + 1] - lx[m])) : 0.0f; };
-      const float hk = k + 1 < nxs ? (float)lx[k + 1] - (float)lx[k] : 0.0f;
-      cw[k] = make_float4((float)lx[k], inv(k), hk * inv(k >= 1 ? k - 1 : 0), hk * inv(k + 1));
+      cw[k] = knot_cell_data(lx, nxs, k);
     }
     if (c.contract) {
       // fixed scale: contract the Q^2 direction once.  P with the Hermite Q
@@ -134,14 +151,7 @@ struct PdfRows {
     const int nx = c.nxs;
     const int klo = c.ix0 > 0 ? 1 : 0;
     if (c.uniform) {
-      // knots uniform to 1e-3 of a spacing (FP32 rounding of ln x adds about
-      // 1e-5 of a spacing): the guess from the spacing is the right cell or
-      // its neighbour, and one comparison with each end of the guessed cell
-      // settles it (the same cell as a binary search over sa)
-      int i = (int)((a - c.a0) * c.inv_da);
-      i = i < 0 ? 0 : (i > nx - 2 ? nx - 2 : i);
-      const float lo = sa[i], hi = sa[i + 1];
-      i += (a >= hi && i < nx - 2 ? 1 : 0) - (a < lo && i > 0 ? 1 : 0);
+      const int i = uniform_knot_cell(sa, nx, a, c.a0, c.inv_da);
       return i < klo ? klo : i;
     }
     int lo = 0, hi = nx - 1;

@@ -39,14 +39,20 @@ struct TTDynConst {
   const double* a_lq2;// device ln Q^2 knots of the alpha_s subgrid
   const double* a_val;// device alpha_s values there
   int a_nq;           // knots in the alpha_s subgrid
+  // cell guesses for knots uniform in ln x / ln Q^2 (set on the host)
+  float a0, inv_da;   // first staged ln x, 1 / spacing
+  int x_uniform;
+  float b0, inv_db;   // first staged ln Q^2, 1 / spacing
+  int q_uniform;
 };
 
 // LDS footprint in floats: node values [R][4][nxs/4 rounded up][12], ln x
-// knots and inverse spacings, ln Q^2 knots and inverse spacings of the rows,
-// the alpha_s knots and values, and 8 constants.
+// knots (padded to 4) and a float4 per x cell, ln Q^2 knots of the rows
+// (padded to 4) and a float4 per row cell, the alpha_s knots and values.
 __host__ __device__ inline int ttdyn_lds_floats(int nxs, int R, int a_nq) {
-  return R * ((nxs + 3) & ~3) * 12 + 2 * nxs + 2 * R + 2 * a_nq + 8;
+  return R * ((nxs + 3) & ~3) * 12 + ((nxs + 3) & ~3) + 4 * nxs + ((R + 3) & ~3) + 4 * R + 2 * a_nq;
 }
+
 
 // cell k with s[k] <= a < s[k+1] in a staged knot list of length n, clamped
 // to [0, n - 2] (binary search)
@@ -87,9 +93,9 @@ struct TTbarDyn {
   const float4* F;  // LDS [R][4][nq4][3] float4
   int nq4;
   float* sa;        // ln x knots [nxs]
-  float* sinv;      // 1/(a_{k+1} - a_k) [nxs]
+  const float4* cwa;// per x cell (knot_cell_data)
   float* sb;        // ln Q^2 knots of the staged rows [R]
-  float* sbinv;     // 1/(b_{k+1} - b_k) [R]
+  const float4* cwb;// per row cell
   float* sal;       // ln Q^2 knots of the alpha_s subgrid [a_nq]
   float* sav;       // alpha_s values [a_nq]
 
@@ -100,11 +106,13 @@ struct TTbarDyn {
     float* Fs = lds;
     const int plane = nq4 * 4 * 12;  // floats per staged row
     sa = Fs + R * plane;
-    sinv = sa + nxs;
-    sb = sinv + nxs;
-    sbinv = sb + R;
-    sal = sbinv + R;
+    float4* wa = (float4*)(sa + ((nxs + 3) & ~3));
+    sb = (float*)(wa + nxs);
+    float4* wb = (float4*)(sb + ((R + 3) & ~3));
+    sal = (float*)(wb + R);
     sav = sal + c.a_nq;
+    cwa = wa;
+    cwb = wb;
     const int tot = R * plane;
     for (int k = threadIdx.x; k < tot; k += blockDim.x) {
       const int f = k % 12;
@@ -118,12 +126,12 @@ struct TTbarDyn {
     const double* lx = c.lx + c.ix0;
     for (int k = threadIdx.x; k < nxs; k += blockDim.x) {
       sa[k] = (float)lx[k];
-      sinv[k] = k + 1 < nxs ? (float)(1.0 / (lx[k + 1] - lx[k])) : 0.0f;
+      wa[k] = knot_cell_data(lx, nxs, k);
     }
     const double* lb = c.lq2 + c.r0;
     for (int k = threadIdx.x; k < R; k += blockDim.x) {
       sb[k] = (float)lb[k];
-      sbinv[k] = k + 1 < R ? (float)(1.0 / (lb[k + 1] - lb[k])) : 0.0f;
+      wb[k] = knot_cell_data(lb, R, k);
     }
     for (int k = threadIdx.x; k < c.a_nq; k += blockDim.x) {
       sal[k] = (float)c.a_lq2[k];
@@ -135,26 +143,26 @@ struct TTbarDyn {
   __device__ __forceinline__ void xwin(float a, int& base, float (&wh)[4], float (&wl)[4], bool& full) const {
     const int nx = c.nxs;
     const int klo = c.ix0 > 0 ? 1 : 0;
-    int i = knot_cell(sa, nx, a);
+    int i = c.x_uniform ? uniform_knot_cell(sa, nx, a, c.a0, c.inv_da) : knot_cell(sa, nx, a);
     i = i < klo ? klo : i;
-    const float t = (a - sa[i]) * sinv[i];
+    const float4 q = cwa[i];
+    const float t = (a - q.x) * q.y;
     full = i + c.ix0 >= 1 && i <= nx - 3;
     base = i - 1 < 0 ? 0 : (i - 1 > nx - 4 ? nx - 4 : i - 1);
-    const float hk = sa[i + 1] - sa[i];
-    herm4(t, hk * sinv[i >= 1 ? i - 1 : 0], hk * sinv[i + 1], wh);
+    herm4(t, q.z, q.w, wh);
     lin4(t, i - base, wl);
   }
 
   // Q window of ln mu^2 = b in the staged rows: base row, weights, full flag
   __device__ __forceinline__ void qwin(float b, int& base, float (&wh)[4], float (&wl)[4], bool& full) const {
     const int R = c.R;
-    const int jl = knot_cell(sb, R, b);
+    const int jl = c.q_uniform ? uniform_knot_cell(sb, R, b, c.b0, c.inv_db) : knot_cell(sb, R, b);
     const int j = c.r0 + jl;  // subgrid-local cell
-    const float t = (b - sb[jl]) * sbinv[jl];
+    const float4 q = cwb[jl];
+    const float t = (b - q.x) * q.y;
     full = j >= 1 && j <= c.nq - 3;
     base = jl - 1 < 0 ? 0 : (jl - 1 > R - 4 ? R - 4 : jl - 1);
-    const float hk = sb[jl + 1] - sb[jl];
-    herm4(t, hk * sbinv[jl >= 1 ? jl - 1 : 0], hk * sbinv[jl + 1], wh);
+    herm4(t, q.z, q.w, wh);
     lin4(t, jl - base, wl);
   }
 

@@ -323,6 +323,19 @@ int grid_for(const vgx_vegas* v, int64_t n) {
   return (int)(want < v->max_wg ? (want > 0 ? want : 1) : v->max_wg);
 }
 
+// Cell-guess constants for knots v[0..n) uniform in their logarithm to 1e-3
+// of a spacing: first logarithm and inverse spacing; false when not uniform
+// (the kernels then search).
+bool uniform_log_knots(const double* v, int n, float& l0f, float& inv_d) {
+  const double l0 = log(v[0]), d = (log(v[n - 1]) - l0) / (n - 1);
+  bool uni = true;
+  for (int k = 0; k < n; ++k)
+    if (fabs(log(v[k]) - (l0 + k * d)) > 1e-3 * d) uni = false;
+  l0f = (float)l0;
+  inv_d = (float)(1.0 / d);
+  return uni;
+}
+
 // PDF rows at the fixed scale mu2 for an integrand whose momentum fractions
 // never fall below x_min.
 vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, double x_min, bool contract,
@@ -377,19 +390,7 @@ vgx_status setup_pdf_rows(PdfRowsConst& t, const vgx_pdf* pdf, double mu2, doubl
       t.ql[0] = t.qh[0]; t.ql[1] = t.qh[1]; t.ql[2] = 0.0f; t.ql[3] = 0.0f;
     }
   }
-  // cell guess for staged ln x knots uniform to 1e-3 of a spacing (else a
-  // binary search)
-  {
-    const int n = t.nxs;
-    const double a0 = log(pdf->h_x[t.ix0]), an = log(pdf->h_x[t.ix0 + n - 1]);
-    const double da = (an - a0) / (n - 1);
-    bool uni = true;
-    for (int k = 0; k < n; ++k)
-      if (fabs(log(pdf->h_x[t.ix0 + k]) - (a0 + k * da)) > 1e-3 * da) uni = false;
-    t.a0 = (float)a0;
-    t.inv_da = (float)(1.0 / da);
-    t.uniform = uni ? 1 : 0;
-  }
+  t.uniform = uniform_log_knots(pdf->h_x + t.ix0, t.nxs, t.a0, t.inv_da) ? 1 : 0;
   return VGX_OK;
 }
 
@@ -457,6 +458,8 @@ vgx_status setup_ttbar_dynamic(TTDynConst& t, const vgx_pdf* pdf, double rs, dou
   t.a_lq2 = pdf->a_lq2 + pdf->a_off[asub];
   t.a_val = pdf->a_val + pdf->a_off[asub];
   t.a_nq = pdf->a_nq[asub];
+  t.x_uniform = uniform_log_knots(pdf->h_x + t.ix0, t.nxs, t.a0, t.inv_da) ? 1 : 0;
+  t.q_uniform = uniform_log_knots(q + r0, t.R, t.b0, t.inv_db) ? 1 : 0;
   return VGX_OK;
 }
 
