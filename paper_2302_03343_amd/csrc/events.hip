@@ -12,8 +12,12 @@
 // counter of sample e of the VEGAS kernels (low and high words of e, the
 // iteration, stream << 8 | block), block i giving particle i's four numbers.
 // Massive momenta: xi by Newton's method from xi0 = sqrt(1 - (sum m/sqrt s)^2),
-// where the (convex) constraint is >= 0, so the iterates decrease
-// monotonically to the root; the loop ends when they stop decreasing.
+// where the (convex, increasing) constraint is >= 0, so the iterates approach
+// the root from above.  The constraint is evaluated in FP64; its derivative
+// only sets the step length and takes the hardware reciprocal (relative error
+// about 2^-23), which keeps the convergence quadratic down to 2^-23 of the
+// step.  The loop ends after a step below 2^-30 of xi: the error left is then
+// of the order of xi's own rounding.
 //
 // Unweighting: w_max by a max over the positive weights (non-negative
 // doubles order like their bit patterns, so an integer atomicMax is exact);
@@ -31,15 +35,28 @@ constexpr int RB_BLOCK = 256;
 
 struct RamboArgs {
   int64_t n_events, first;
-  double sqrt_s, w0, sum_m;
+  double sqrt_s, w0, w0m, sum_m;  // w0m = w0 s^(2-n), the massive weight's constant
   double m[VGX_MAX_PART];
   uint32_t k0, k1, sid, it;
 };
 
+// x^k for a compile-time k >= 0, by repeated squaring
+template <int K>
+__device__ __forceinline__ double ipow(double x) {
+  if constexpr (K == 0)
+    return 1.0;
+  else if constexpr (K == 1)
+    return x;
+  else {
+    const double h = ipow<K / 2>(x * x);
+    if constexpr (K % 2) return h * x;
+    return h;
+  }
+}
+
 template <int N, bool MASSIVE>
 __global__ __launch_bounds__(RB_BLOCK) void k_rambo(RamboArgs a, double* __restrict__ mom, double* __restrict__ wout) {
   const int64_t stride = (int64_t)gridDim.x * RB_BLOCK;
-  const double s = a.sqrt_s * a.sqrt_s;
   for (int64_t e = (int64_t)blockIdx.x * RB_BLOCK + threadIdx.x; e < a.n_events; e += stride) {
     const uint64_t idx = (uint64_t)(a.first + e);
     double q[N][4];
@@ -63,8 +80,9 @@ __global__ __launch_bounds__(RB_BLOCK) void k_rambo(RamboArgs a, double* __restr
     }
     // boost and scale onto P = (sqrt s, 0): p = x H_b(q)
     const double M = sqrt(Q0 * Q0 - Q1 * Q1 - Q2 * Q2 - Q3 * Q3);
-    const double b1 = -Q1 / M, b2 = -Q2 / M, b3 = -Q3 / M;
-    const double x = a.sqrt_s / M, gam = Q0 / M, aa = 1.0 / (1.0 + gam);
+    const double iM = 1.0 / M;
+    const double b1 = -Q1 * iM, b2 = -Q2 * iM, b3 = -Q3 * iM;
+    const double x = a.sqrt_s * iM, gam = Q0 * iM, aa = 1.0 / (1.0 + gam);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const double bq = b1 * q[i][1] + b2 * q[i][2] + b3 * q[i][3];
@@ -86,26 +104,27 @@ __global__ __launch_bounds__(RB_BLOCK) void k_rambo(RamboArgs a, double* __restr
           const double xe = xi * q[i][0];
           const double k0 = sqrt(a.m[i] * a.m[i] + xe * xe);
           f += k0;
-          fp += xe * q[i][0] / k0;
+          fp += xe * q[i][0] * __builtin_amdgcn_rcp(k0);
         }
-        const double nx = xi - f / fp;
-        if (!(nx < xi)) break;
-        xi = nx;
+        const double step = f * __builtin_amdgcn_rcp(fp);
+        xi -= step;
+        if (!(fabs(step) >= 0x1p-30 * xi)) break;
       }
       double sk = 0.0, pr = 1.0, sk2 = 0.0;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         const double kabs = xi * q[i][0];  // |k_i| = xi |p_i| = xi p_i^0 (p_i massless)
         const double k0 = sqrt(a.m[i] * a.m[i] + kabs * kabs);
+        const double ik = 1.0 / k0;
         sk += kabs;
-        pr *= kabs / k0;
-        sk2 += kabs * kabs / k0;
+        pr *= kabs * ik;
+        sk2 += kabs * kabs * ik;
         q[i][0] = k0;
         q[i][1] *= xi;
         q[i][2] *= xi;
         q[i][3] *= xi;
       }
-      w = a.w0 * (pow(s, (double)(2 - N)) * pow(sk, (double)(2 * N - 3)) * pr / sk2);
+      w = a.w0m * (ipow<2 * N - 3>(sk) * pr / sk2);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -274,7 +293,8 @@ extern "C" vgx_status rambo_generate(int32_t n_part, const double* masses, doubl
   const int n = n_part;
   const double s = sqrt_s * sqrt_s;
   // w0 = (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / (Gamma(n) Gamma(n-1))
-  a.w0 = pow(2.0 * M_PI, 4.0 - 3.0 * n) * pow(M_PI / 2.0, n - 1.0) * pow(s, n - 2.0) / (tgamma((double)n) * tgamma(n - 1.0));
+  a.w0m = pow(2.0 * M_PI, 4.0 - 3.0 * n) * pow(M_PI / 2.0, n - 1.0) / (tgamma((double)n) * tgamma(n - 1.0));
+  a.w0 = a.w0m * pow(s, n - 2.0);
   a.k0 = (uint32_t)seed;
   a.k1 = (uint32_t)(seed >> 32);
   a.sid = stream_id;

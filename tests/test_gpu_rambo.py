@@ -26,6 +26,8 @@ CASES = [
     ([80.4, 91.2, 4.7], 300.0),
     ([173.0, 173.0, 0.0, 0.0, 4.7], 1500.0),
     ([1.0] * 9, 30.0),
+    ([4.9, 5.0], 10.0),  # near threshold: xi small, Newton from far above the root
+    ([30.0, 30.0, 30.0, 9.9], 100.0),
 ]
 
 
