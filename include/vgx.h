@@ -345,7 +345,8 @@ vgx_status rambo_generate(int32_t n_part, const double* masses, double sqrt_s, u
  *   idx_dev    : device [n] int64; the kept indices in ascending order fill
  *                its first *n_kept entries.
  *   w_max_used : host, may be NULL: the bound used.
- * Allocates a small stream-ordered scratch (about n/512 bytes).  n = 0 is a
+ * Allocates a small stream-ordered scratch (about n/512 bytes plus 8 bytes
+ * per workgroup of the max, at most 8 per CU).  n = 0 is a
  * no-op. */
 vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
                     uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used, void* stream);

@@ -19,8 +19,8 @@
 // step.  The loop ends after a step below 2^-30 of xi: the error left is then
 // of the order of xi's own rounding.
 //
-// Unweighting: w_max by a max over the positive weights (non-negative
-// doubles order like their bit patterns, so an integer atomicMax is exact);
+// Unweighting: w_max by a max over the positive weights (block maxima, then
+// one workgroup over those: exact in any order);
 // then kept indices in ascending order by a three-pass compaction: per-block
 // counts, one exclusive scan, and a scatter that regenerates each event's
 // uniform and ranks the kept events with wave ballots.
@@ -141,14 +141,41 @@ constexpr int UW_BLOCK = 256;
 constexpr int UW_ROUNDS = 16;
 constexpr int UW_CHUNK = UW_BLOCK * UW_ROUNDS;  // events per block, ranked in order
 
+// Largest weight: a block maximum per workgroup into part[], then one
+// workgroup reduces part[] (one atomic per workgroup on a single address
+// serialised at the memory: about 30 us for 2048 workgroups).
 __global__ __launch_bounds__(UW_BLOCK) void k_uw_max(int64_t n, const double* __restrict__ w,
-                                                     unsigned long long* __restrict__ out_bits) {
+                                                     double* __restrict__ part) {
   __shared__ double red[UW_BLOCK / 64];
   double m = 0.0;
+  // 16-byte loads, four in flight per lane (one 8-byte load per lane and
+  // round left the kernel waiting on HBM latency); a weight before the first
+  // 16-byte boundary and an odd one at the end are read by thread 0
+  const int64_t head = ((uintptr_t)w & 15) ? 1 : 0;
+  const int64_t n2 = n > head ? (n - head) >> 1 : 0;
+  const double2* w2 = (const double2*)(w + head);
   const int64_t stride = (int64_t)gridDim.x * UW_BLOCK;
-  for (int64_t i = (int64_t)blockIdx.x * UW_BLOCK + threadIdx.x; i < n; i += stride) {
-    const double v = w[i];
-    m = v > m ? v : m;  // NaN and non-positive weights never win
+  int64_t i = (int64_t)blockIdx.x * UW_BLOCK + threadIdx.x;
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    double2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = w2[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      m = v[k].x > m ? v[k].x : m;  // NaN and non-positive weights never win
+      m = v[k].y > m ? v[k].y : m;
+    }
+  }
+  for (; i < n2; i += stride) {
+    const double2 v = w2[i];
+    m = v.x > m ? v.x : m;
+    m = v.y > m ? v.y : m;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double h = head ? w[0] : 0.0;
+    const double t = head + 2 * n2 < n ? w[n - 1] : 0.0;
+    m = h > m ? h : m;
+    m = t > m ? t : m;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -159,7 +186,27 @@ __global__ __launch_bounds__(UW_BLOCK) void k_uw_max(int64_t n, const double* __
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 1; k < UW_BLOCK / 64; ++k) m = red[k] > m ? red[k] : m;
-    atomicMax(out_bits, (unsigned long long)__double_as_longlong(m));
+    part[blockIdx.x] = m;
+  }
+}
+
+constexpr int UW_FINAL = 1024;
+
+__global__ __launch_bounds__(UW_FINAL) void k_uw_max_final(int nparts, const double* __restrict__ part,
+                                                           unsigned long long* __restrict__ out_bits) {
+  __shared__ double red[UW_FINAL / 64];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += UW_FINAL) m = part[i] > m ? part[i] : m;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < UW_FINAL / 64; ++k) m = red[k] > m ? red[k] : m;
+    *out_bits = (unsigned long long)__double_as_longlong(m);  // m >= 0: its bit pattern orders like it
   }
 }
 
@@ -333,17 +380,20 @@ extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uin
   hipStream_t st = (hipStream_t)stream;
   const int64_t nb = (n + UW_CHUNK - 1) / UW_CHUNK;
   VGX_CHECK(nb < (int64_t)1 << 31, "unweight: n too large");
-  // scratch: the max's bit pattern, then nb + 1 counts (stream-ordered)
+  const int64_t want = (n + UW_BLOCK - 1) / UW_BLOCK;
+  const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
+  // scratch: the max's bit pattern, nb + 1 counts, the grid's block maxima
+  // (stream-ordered)
   void* scratch = nullptr;
-  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) + sizeof(int64_t) * (nb + 1), st));
+  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) + sizeof(int64_t) * (nb + 1) + sizeof(double) * grid, st));
   unsigned long long* bits = (unsigned long long*)scratch;
   int64_t* counts = (int64_t*)(bits + 1);
+  double* part = (double*)(counts + nb + 1);
   UwArgs a{n, w_max, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id, iteration};
   hipError_t e = hipMemsetAsync(bits, 0, sizeof(unsigned long long), st);
   if (e == hipSuccess && !(w_max > 0.0)) {
-    const int64_t want = (n + UW_BLOCK - 1) / UW_BLOCK;
-    const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
-    hipLaunchKernelGGL(k_uw_max, dim3(grid), dim3(UW_BLOCK), 0, st, n, w_dev, bits);
+    hipLaunchKernelGGL(k_uw_max, dim3(grid), dim3(UW_BLOCK), 0, st, n, w_dev, part);
+    hipLaunchKernelGGL(k_uw_max_final, dim3(1), dim3(UW_FINAL), 0, st, grid, part, bits);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {

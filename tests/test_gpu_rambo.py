@@ -96,6 +96,31 @@ def test_unweight_bit_exact(vgx, n):
     assert np.array_equal(idx[:k2].cpu().numpy(), ref2)
 
 
+@pytest.mark.parametrize("off,n", [(1, 100_000), (1, 100_001), (1, 1), (1, 2), (0, 2), (2, 3)])
+def test_unweight_on_offset_views(vgx, off, n):
+    """Weights starting off an aligned 16-byte boundary (a view at an odd
+    offset), odd and even lengths: the maximum and the kept indices as the
+    oracle's."""
+    import torch
+    print(f"unweight view off={off} n={n}", flush=True)
+    w = np.random.default_rng(n + off).exponential(1.0, off + n)
+    w[off + n // 2] = 50.0 if n > 2 else w[off + n // 2]  # a maximum inside
+    w[-1] = 60.0  # and one at the end: the last weight
+    wt = torch.from_numpy(w).cuda()[off:]
+    idx = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    k, wm = vgx.unweight(wt, 5, 1, 0, idx)
+    ref, wref = orb.unweight(w[off:], 5, 1, 0)
+    assert wm == wref == 60.0
+    assert k == ref.size and np.array_equal(idx[:k].cpu().numpy(), ref)
+    if n > 1:  # and the first weight as the maximum
+        w2 = w.copy()
+        w2[off] = 70.0
+        k, wm = vgx.unweight(torch.from_numpy(w2).cuda()[off:], 5, 1, 0, idx)
+        ref, wref = orb.unweight(w2[off:], 5, 1, 0)
+        assert wm == wref == 70.0 and k == ref.size
+        assert np.array_equal(idx[:k].cpu().numpy(), ref)
+
+
 def test_unweight_edges(vgx):
     import torch
     idx = torch.empty(10, dtype=torch.int64, device="cuda")
