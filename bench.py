@@ -543,6 +543,7 @@ def extra_events(vgx):
         out[name] = {"events_per_s": n / (ms * 1e-3), "ms": ms, "written_GBps": byt / (ms * 1e-3) / 1e9,
                      "bytes_per_event": (4 * 4 + 1) * 8}
     idx = torch.empty(n, dtype=torch.int64, device="cuda")
+    vgx.unweight(w, 21, 2, 99, idx)  # warm-up: the stream-ordered scratch pool
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = 5

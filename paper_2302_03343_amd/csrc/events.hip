@@ -22,8 +22,8 @@
 // Unweighting: w_max by a max over the positive weights (block maxima, then
 // one workgroup over those: exact in any order);
 // then kept indices in ascending order by a three-pass compaction: per-block
-// counts, one exclusive scan, and a scatter that regenerates each event's
-// uniform and ranks the kept events with wave ballots.
+// counts (keeping each wave's ballot of its decisions), one exclusive scan,
+// and a scatter that ranks the kept events from the ballots.
 #include "common.h"
 
 #include <math.h>
@@ -225,16 +225,27 @@ __device__ __forceinline__ double uw_wmax(const UwArgs& a, const unsigned long l
   return a.w_max > 0.0 ? a.w_max : __longlong_as_double((long long)*bits);
 }
 
+// The keep decisions of a block as UW_MASKS wave ballots, in event order
+// (mask r * 4 + wave covers events base + 256 r + 64 wave + lane), for the
+// scatter; and the block's count.
+constexpr int UW_MASKS = UW_ROUNDS * (UW_BLOCK / 64);
+static_assert(UW_MASKS == 64, "the scatter scans a block's masks within one wave");
+
 __global__ __launch_bounds__(UW_BLOCK) void k_uw_count(UwArgs a, const double* __restrict__ w,
                                                        const unsigned long long* __restrict__ bits,
-                                                       int64_t* __restrict__ counts) {
+                                                       int64_t* __restrict__ counts,
+                                                       unsigned long long* __restrict__ masks) {
   __shared__ int red[UW_BLOCK / 64];
   const double wmax = uw_wmax(a, bits);
   const int64_t base = (int64_t)blockIdx.x * UW_CHUNK;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int c = 0;
   for (int r = 0; r < UW_ROUNDS; ++r) {
     const int64_t i = base + r * UW_BLOCK + threadIdx.x;
-    if (i < a.n) c += uw_keep(a, w, i, wmax) ? 1 : 0;
+    const bool keep = i < a.n && uw_keep(a, w, i, wmax);
+    const unsigned long long m = __ballot(keep);
+    if (lane == 0) masks[(int64_t)blockIdx.x * UW_MASKS + r * (UW_BLOCK / 64) + wv] = m;
+    c += keep ? 1 : 0;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
@@ -276,30 +287,33 @@ __global__ __launch_bounds__(1024) void k_uw_scan(int64_t nb, int64_t* __restric
   if (threadIdx.x == 0) counts[nb] = carry;
 }
 
-__global__ __launch_bounds__(UW_BLOCK) void k_uw_scatter(UwArgs a, const double* __restrict__ w,
-                                                         const unsigned long long* __restrict__ bits,
+// Kept indices from the block's masks: lane j of every wave holds mask j and
+// the exclusive prefix of the popcounts, so the position of each kept event
+// needs no workgroup barrier; the weights are not read again.
+__global__ __launch_bounds__(UW_BLOCK) void k_uw_scatter(int64_t n, const unsigned long long* __restrict__ masks,
                                                          const int64_t* __restrict__ offsets,
                                                          int64_t* __restrict__ idx_out) {
-  __shared__ int wsum[UW_BLOCK / 64];
-  const double wmax = uw_wmax(a, bits);
   const int64_t base = (int64_t)blockIdx.x * UW_CHUNK;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int64_t pos = offsets[blockIdx.x];
+  const unsigned long long mj = masks[(int64_t)blockIdx.x * UW_MASKS + lane];
+  const int cj = __popcll(mj);
+  int incl = cj;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  const int excl = incl - cj;
+  const uint32_t mlo = (uint32_t)mj, mhi = (uint32_t)(mj >> 32);
+  const int64_t pos = offsets[blockIdx.x];
   for (int r = 0; r < UW_ROUNDS; ++r) {
+    const int j = r * (UW_BLOCK / 64) + wv;
+    const uint32_t lo = (uint32_t)__shfl((int)mlo, j, 64), hi = (uint32_t)__shfl((int)mhi, j, 64);
+    const int pre = __shfl(excl, j, 64);
+    const bool keep = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
+    const int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
     const int64_t i = base + r * UW_BLOCK + threadIdx.x;
-    const bool keep = i < a.n && uw_keep(a, w, i, wmax);
-    const unsigned long long mask = __ballot(keep);
-    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-    if (lane == 0) wsum[wv] = __popcll(mask);
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int k = 0; k < UW_BLOCK / 64; ++k) {
-      before += k < wv ? wsum[k] : 0;
-      total += wsum[k];
-    }
-    if (keep) idx_out[pos + before + rank] = i;
-    pos += total;
-    __syncthreads();
+    if (keep && i < n) idx_out[pos + pre + rank] = i;
   }
 }
 
@@ -382,13 +396,15 @@ extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uin
   VGX_CHECK(nb < (int64_t)1 << 31, "unweight: n too large");
   const int64_t want = (n + UW_BLOCK - 1) / UW_BLOCK;
   const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
-  // scratch: the max's bit pattern, nb + 1 counts, the grid's block maxima
-  // (stream-ordered)
+  // scratch: the max's bit pattern, nb + 1 counts, the grid's block maxima,
+  // nb x UW_MASKS keep masks (stream-ordered)
   void* scratch = nullptr;
-  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) + sizeof(int64_t) * (nb + 1) + sizeof(double) * grid, st));
+  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) * (1 + nb * UW_MASKS) + sizeof(int64_t) * (nb + 1) +
+                                       sizeof(double) * grid, st));
   unsigned long long* bits = (unsigned long long*)scratch;
   int64_t* counts = (int64_t*)(bits + 1);
   double* part = (double*)(counts + nb + 1);
+  unsigned long long* masks = (unsigned long long*)(part + grid);
   UwArgs a{n, w_max, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id, iteration};
   hipError_t e = hipMemsetAsync(bits, 0, sizeof(unsigned long long), st);
   if (e == hipSuccess && !(w_max > 0.0)) {
@@ -397,9 +413,9 @@ extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uin
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_uw_count, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts);
+    hipLaunchKernelGGL(k_uw_count, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts, masks);
     hipLaunchKernelGGL(k_uw_scan, dim3(1), dim3(1024), 0, st, nb, counts);
-    hipLaunchKernelGGL(k_uw_scatter, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts, idx_dev);
+    hipLaunchKernelGGL(k_uw_scatter, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, n, masks, counts, idx_dev);
     e = hipGetLastError();
   }
   int64_t total = 0;
