@@ -260,7 +260,8 @@ __global__ __launch_bounds__(UW_BLOCK) void k_uw_count(UwArgs a, const double* _
 
 // Exclusive scan of the block counts in place (one workgroup of 1024), the
 // total in counts[nb].
-__global__ __launch_bounds__(1024) void k_uw_scan(int64_t nb, int64_t* __restrict__ counts) {
+__global__ __launch_bounds__(1024) void k_uw_scan(int64_t nb, int64_t* __restrict__ counts,
+                                                 int64_t* __restrict__ total_out) {
   __shared__ int64_t part[1024 / 64];
   __shared__ int64_t carry;
   if (threadIdx.x == 0) carry = 0;
@@ -284,7 +285,10 @@ __global__ __launch_bounds__(1024) void k_uw_scan(int64_t nb, int64_t* __restric
     if (threadIdx.x == 1023) carry = before + incl;
     __syncthreads();
   }
-  if (threadIdx.x == 0) counts[nb] = carry;
+  if (threadIdx.x == 0) {
+    counts[nb] = carry;
+    *total_out = carry;  // beside the max's bits: one read-back for both
+  }
 }
 
 // Kept indices from the block's masks: lane j of every wave holds mask j and
@@ -396,40 +400,41 @@ extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uin
   VGX_CHECK(nb < (int64_t)1 << 31, "unweight: n too large");
   const int64_t want = (n + UW_BLOCK - 1) / UW_BLOCK;
   const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
-  // scratch: the max's bit pattern, nb + 1 counts, the grid's block maxima,
-  // nb x UW_MASKS keep masks (stream-ordered)
+  // scratch: the max's bit pattern and the kept count, nb + 1 counts, the
+  // grid's block maxima, nb x UW_MASKS keep masks (stream-ordered).  The
+  // bits are written by k_uw_max_final when the maximum is searched and
+  // not read otherwise.
   void* scratch = nullptr;
-  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) * (1 + nb * UW_MASKS) + sizeof(int64_t) * (nb + 1) +
+  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) * (2 + nb * UW_MASKS) + sizeof(int64_t) * (nb + 1) +
                                        sizeof(double) * grid, st));
   unsigned long long* bits = (unsigned long long*)scratch;
-  int64_t* counts = (int64_t*)(bits + 1);
+  int64_t* total_dev = (int64_t*)(bits + 1);
+  int64_t* counts = total_dev + 1;
   double* part = (double*)(counts + nb + 1);
   unsigned long long* masks = (unsigned long long*)(part + grid);
   UwArgs a{n, w_max, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id, iteration};
-  hipError_t e = hipMemsetAsync(bits, 0, sizeof(unsigned long long), st);
-  if (e == hipSuccess && !(w_max > 0.0)) {
+  hipError_t e = hipSuccess;
+  if (!(w_max > 0.0)) {
     hipLaunchKernelGGL(k_uw_max, dim3(grid), dim3(UW_BLOCK), 0, st, n, w_dev, part);
     hipLaunchKernelGGL(k_uw_max_final, dim3(1), dim3(UW_FINAL), 0, st, grid, part, bits);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_uw_count, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts, masks);
-    hipLaunchKernelGGL(k_uw_scan, dim3(1), dim3(1024), 0, st, nb, counts);
+    hipLaunchKernelGGL(k_uw_scan, dim3(1), dim3(1024), 0, st, nb, counts, total_dev);
     hipLaunchKernelGGL(k_uw_scatter, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, n, masks, counts, idx_dev);
     e = hipGetLastError();
   }
-  int64_t total = 0;
-  unsigned long long wb = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&total, counts + nb, sizeof(total), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(&wb, bits, sizeof(wb), hipMemcpyDeviceToHost, st);
+  unsigned long long hb[2] = {0, 0};  // the max's bits, the kept count
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, bits, sizeof(hb), hipMemcpyDeviceToHost, st);
   hipError_t ef = hipFreeAsync(scratch, st);
   if (e == hipSuccess) e = ef;
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "unweight", __FILE__, __LINE__);
-  *n_kept = total;
+  *n_kept = (int64_t)hb[1];
   if (w_max_used) {
     double wm;
-    memcpy(&wm, &wb, sizeof(wm));
+    memcpy(&wm, &hb[0], sizeof(wm));
     *w_max_used = w_max > 0.0 ? w_max : wm;
   }
   return VGX_OK;
