@@ -335,19 +335,25 @@ vgx_status rambo_generate(int32_t n_part, const double* masses, double sqrt_s, u
                           uint32_t iteration, int64_t first, int64_t n_events, double* mom_dev, double* w_dev,
                           void* stream);
 
-/* Acceptance-rejection unweighting (sync: returns the count).  Event e is
- * kept when w_e > r_e w_max, r_e the first uniform of sample e for (seed,
- * stream_id, iteration) -- use a stream or iteration the weights' own
- * sampling did not.
+/* Acceptance-rejection unweighting (sync: returns the count).  Thesis: MC
+ * chapter, acceptance-rejection paragraph; MadFlow chapter, unweighted event
+ * exporter (keep an event when its weight exceeds a uniform number times the
+ * largest weight).  Event e is kept when w_e > r_e w_max, r_e the first
+ * word of Philox block 0xFF of sample e for (seed, stream_id, iteration),
+ * as a uniform.  No sampler of this library uses block 0xFF (VEGAS and the
+ * flow use blocks 0..2, RAMBO blocks 0..n_part-1), so r_e is never one of the
+ * numbers that made event e, even with the weights' own seed, stream and
+ * iteration.
  *   w_dev      : device [n] FP64 weights; NaN and w <= 0 are never kept.
  *   w_max      : > 0: the bound to use (efficiency w/w_max); 0: the largest
  *                weight of the sample, found on the device.
  *   idx_dev    : device [n] int64; the kept indices in ascending order fill
  *                its first *n_kept entries.
  *   w_max_used : host, may be NULL: the bound used.
- * Allocates a small stream-ordered scratch (about n/512 bytes plus 8 bytes
- * per workgroup of the max, at most 8 per CU).  n = 0 is a
- * no-op. */
+ * Allocates a stream-ordered scratch of about n/8 + n/512 bytes (one keep
+ * bit and one 8-byte count per 4096 events) plus 8 bytes per workgroup of
+ * the max search (at most 8 per CU), freed before the call returns.
+ * n = 0 is a no-op. */
 vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
                     uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used, void* stream);
 

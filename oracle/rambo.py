@@ -28,8 +28,10 @@ dimensions; particle i takes dimensions 4i..4i+3).  xi is found here by
 bisection to the last bit (the kernel uses Newton's method).
 
 Unweighting: with w_max the largest weight (or a given bound), event e is
-kept when w_e > r_e w_max, r_e the first uniform of sample e of the given
-(seed, stream, iteration); kept indices in ascending order.
+kept when w_e > r_e w_max, r_e the first uniform of Philox block 0xFF of
+sample e for the given (seed, stream, iteration) -- a block no sampler uses,
+so the accept number is independent of the numbers that made the event;
+kept indices in ascending order.
 
 Pins: tests/test_oracle_rambo.py -- momentum conservation and mass shells;
 the two- and three-body massless volumes 1/(8 pi) and s/(256 pi^3); the
@@ -42,7 +44,11 @@ import math
 
 import numpy as np
 
-from .philox import sample_uniforms
+from .philox import philox4x32, sample_uniforms, to_unit
+
+UNWEIGHT_BLOCK = 0xFF  # Philox block field of the accept numbers (no sampler uses it)
+
+UNWEIGHT_BLOCK = 0xFF  # Philox block field of the accept numbers (no sampler uses it)
 
 
 def massless_weight(n, sqrt_s):
@@ -120,5 +126,13 @@ def unweight(w, seed, stream, iteration, w_max=None):
     w = np.asarray(w, dtype=np.float64)
     if w_max is None or w_max <= 0.0:
         w_max = float(np.max(np.where(w > 0.0, w, 0.0))) if w.size else 0.0
-    r = sample_uniforms(seed, stream, iteration, np.arange(w.size, dtype=np.uint64), 1)[:, 0]
+    # r_e: first word of Philox block 0xFF of sample e.  Sampling uses blocks
+    # 0..(number of 4-word blocks it needs) - 1, so the accept number of an
+    # event is never one of the numbers that made the event, whatever stream
+    # and iteration the caller passes.
+    idx = np.arange(w.size, dtype=np.uint64)
+    lo = (idx & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    hi = (idx >> np.uint64(32)).astype(np.uint32)
+    c3 = np.uint32(((stream << 8) | UNWEIGHT_BLOCK) & 0xFFFFFFFF)
+    r = to_unit(philox4x32(lo, hi, np.uint32(iteration), c3, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)[0])
     return np.nonzero(w > r * w_max)[0], w_max

@@ -216,8 +216,14 @@ struct UwArgs {
   uint32_t k0, k1, sid, it;
 };
 
+// The accept number of event i: word 0 of Philox block 0xFF of sample i.  The
+// samplers use blocks 0 .. (4-word blocks they need) - 1 (at most 10 here), so
+// an accept number never coincides with a number that made the event.
+constexpr uint32_t UW_PHILOX_BLOCK = 0xFFu;
+
 __device__ __forceinline__ bool uw_keep(const UwArgs& a, const double* w, int64_t i, double wmax) {
-  const u32x4 r = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), a.it, a.sid << 8, a.k0, a.k1);
+  const u32x4 r = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), a.it, (a.sid << 8) | UW_PHILOX_BLOCK,
+                                a.k0, a.k1);
   return w[i] > word_to_unit(r.x) * wmax;
 }
 

@@ -134,15 +134,21 @@ def test_c0_estimate_consistent_with_closed_form():
 
 
 def test_pulls_over_seeds():
+    """Unbiasedness and sigma-consistency of the combined estimate (VEGAS
+    section, the chi^2 check of the combination): over 200 independent seeds
+    the pull (E - I)/sigma has mean 0 +- 0.2 and spread 1 +- 0.15 (about 3
+    standard errors each at 200 draws), and the mean chi^2/dof is near 1."""
     f = lambda x: gauss(x, 0.5, 0.15)
     I = gauss_integral(2, 0.5, 0.15)
-    pulls = []
-    for seed in range(40):
+    pulls, chi2 = [], []
+    for seed in range(200):
         res = vegas.run(f, 2, 20, 1.5, 4, 4000, seed)
         pulls.append((res["mean"] - I) / res["sigma"])
+        chi2.append(res["chi2_dof"])
     pulls = np.array(pulls)
-    assert abs(pulls.mean()) < 0.5
-    assert 0.6 < pulls.std() < 1.5
+    assert abs(pulls.mean()) < 0.2
+    assert abs(pulls.std() - 1.0) < 0.15
+    assert abs(np.mean(chi2) - 1.0) < 0.25
 
 
 def test_converged_grid_matches_gaussian_quantiles():
