@@ -51,7 +51,8 @@ typedef enum {
   VGX_EDEVICE = 3,    /* a HIP runtime call failed                          */
   VGX_ERANGE = 4,     /* PDF query outside the grid (outputs set to NaN)    */
   VGX_ENUMERIC = 5,   /* non-finite iteration estimate (excluded)           */
-  VGX_EFALLBACK = 6,  /* flow worse than plain VEGAS or non-finite loss     */
+  VGX_EFALLBACK = 6,  /* proposal worse than plain VEGAS, or non-finite
+                         training loss: fall back to plain VEGAS             */
   VGX_ESTATE = 7      /* call not valid in the context's current state      */
 } vgx_status;
 
@@ -126,7 +127,10 @@ typedef struct {
                                [n_flav][n_q(s)][n_x], blocks concatenated    */
 } vgx_pdf_desc;
 
-/* Copy a grid to the device (sync).  The descriptor's host arrays may be
+/* Copy a grid to the device (sync).  Thesis: LHAPDF section (a set's
+ * members are grids of xf on knots in x and Q^2, split into subgrids at the
+ * flavour thresholds) and PDFFlow's design (the grid is loaded once into
+ * device memory).  The descriptor's host arrays may be
  * freed after the call.  VGX_EINVAL on malformed knots, on a value that is
  * not finite or beyond the FP32 range (the FP32-output path reads an FP32
  * copy), and when 16 (n_x + total Q^2 knots) + 2048 s bytes exceed 64 KiB,
@@ -142,7 +146,13 @@ vgx_status pdf_create(const vgx_pdf_desc* desc, void* stream, vgx_pdf** out);
  * pdf_interp_members evaluates every member.  1 <= n_members <= 65535. */
 vgx_status pdf_create_set(const vgx_pdf_desc* desc, int32_t n_members, void* stream, vgx_pdf** out);
 
-/* xf for every flavour at n points (async).
+/* xf for every flavour at n points (async).  Thesis: LHAPDF section,
+ * interpolation paragraphs (log-bicubic: cubic Hermite splines in ln x and
+ * ln Q^2 on the four knots around the point, bilinear where that stencil
+ * is incomplete; the subgrid figure) and PDFFlow's design (the xfxQ2 call
+ * over a batch of points; accuracy measured by eq. pdfflow-diff).  The
+ * Hermite slopes (not printed in the thesis) are the average of the two
+ * adjacent secants, as in LHAPDF 6.
  *   x_dev, q2_dev : device [n] FP64 query points.
  *   out_dtype     : VGX_F64 or VGX_F32.
  *   out_dev       : device [n_flav][n] of that type.
@@ -156,7 +166,9 @@ vgx_status pdf_create_set(const vgx_pdf_desc* desc, int32_t n_members, void* str
 vgx_status pdf_interp(const vgx_pdf* pdf, int64_t n, const double* x_dev, const double* q2_dev,
                       int32_t out_dtype, void* out_dev, void* stream);
 
-/* Every flavour of every member of a PDF set at n points (async).
+/* Every flavour of every member of a PDF set at n points (async).  Thesis:
+ * PDFFlow section, "Multi-PDF members evaluation" (all members at the x
+ * points of a FastKernel table; the table tab:fktable).
  *   out_dev : device [n_members][n_flav][n] of out_dtype.
  * Same interpolation as pdf_interp; points outside the grid give NaN in all
  * members and are counted once (pdf_out_of_range) whatever the extrapolation
@@ -209,7 +221,9 @@ vgx_status pdf_bounds(const vgx_pdf* pdf, double* xmin, double* xmax, double* q2
  * Host arrays may be freed after the call.  VGX_EINVAL on malformed knots. */
 vgx_status pdf_set_alphas(vgx_pdf* pdf, int32_t n, const double* q2_knots, const double* alphas, void* stream);
 
-/* alpha_s at n scales (async): cubic Hermite in ln Q^2 with secant-average
+/* alpha_s at n scales (async).  Thesis: LHAPDF section, the alpha_s
+ * paragraph (log-cubic interpolation on the set's Q knots); PDFFlow's alpha_s
+ * accuracy figure.  Cubic Hermite in ln Q^2 with secant-average
  * slopes on interior cells of the subgrid holding Q^2 (the upper subgrid at a
  * threshold), linear on a subgrid's first and last cells, the top value
  * above the last knot; below the first knot as the context's extrapolation
@@ -247,10 +261,17 @@ typedef struct {
   int64_t n;
 } vgx_iter_result;
 
-/* Create a context with a uniform grid e[j][k] = k/N (sync). */
+/* Create a context with a uniform grid e[j][k] = k/N (sync).  Thesis: MC
+ * chapter, "Adaptive Monte Carlo: VEGAS algorithm" (a separable grid with a
+ * fixed number of bins per dimension, starting from equal widths). */
 vgx_status vegas_create(const vgx_vegas_cfg* cfg, void* stream, vgx_vegas** out);
 
-/* One iteration (sync): samples i = 0..n-1, uniforms from Philox with
+/* One iteration (sync).  Thesis: MC chapter, the importance-sampling
+ * estimator (eq. mc_est_is, with p the grid's piecewise-constant density,
+ * sampled by the inverse transform method, eq. inverse-method) and its
+ * variance (eq. var-en-est, read as the variance of the mean); the VEGAS
+ * section's per-bin accumulation that drives the refinement.  Samples
+ * i = 0..n-1, uniforms from Philox with
  * counter (i, iteration, stream_id, block) and key seed, mapped through the
  * grid, w = f(x) J(u); accumulates the compensated sums and the per-bin
  * histogram of w^2, appends (E, var) to the context's list of estimates
@@ -262,13 +283,17 @@ vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, vgx_iter_re
  * with vegas_results).  Lets a caller queue many iterations back to back. */
 vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration);
 
-/* Refine the grid from the last iteration's histogram (async): Lepage's
+/* Refine the grid from the last iteration's histogram (async).  Thesis:
+ * VEGAS section (bin widths adjusted so that each bin carries an equal share
+ * of the integrand; the formula is Lepage's, which the thesis cites): Lepage's
  * 3-point smoothing, damping r = ((1-p)/ln(1/p))^alpha, re-binning to equal
- * shares of sum r.  A dimension with an all-zero histogram is unchanged. */
+ * shares of sum r.  A dimension whose histogram is all zero or not finite
+ * (a non-finite iteration) is unchanged. */
 vgx_status vegas_refine(vgx_vegas* v);
 
 /* Inverse-variance combination of the stored estimates and chi^2/dof
- * (sync).  Non-finite estimates are skipped; a zero variance returns that
+ * (sync).  Thesis: VEGAS section, the weighted average of the iterations'
+ * estimates and the consistency check eq. vegas-check.  Non-finite estimates are skipped; a zero variance returns that
  * estimate with sigma 0. */
 vgx_status vegas_result(vgx_vegas* v, double* mean, double* sigma, double* chi2_dof, int32_t* n_used);
 
@@ -283,15 +308,24 @@ vgx_status vegas_get_grid(vgx_vegas* v, double* edges_host);
 vgx_status vegas_set_grid(vgx_vegas* v, const double* edges_host);
 vgx_status vegas_get_hist(vgx_vegas* v, double* hist_host);
 
-/* Materialise samples first .. first+n-1 of an iteration (async):
+/* Materialise samples first .. first+n-1 of an iteration (async), e.g. the
+ * training data of a learned proposal (the VEGAS samples and their weights):
  * u_dev [dim][n] the Philox uniforms (the VEGAS unit-cube coordinates) and
  * g_dev [n] = f(G(u)) J_G(u).  Either output may be NULL. */
 vgx_status vegas_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t iteration,
                         double* u_dev, double* g_dev);
 
-/* Estimate from given unit-cube points y with proposal density q (sync):
+/* Estimate from given unit-cube points y with proposal density q (sync).
+ * Thesis: MC chapter, importance sampling (eq. mc_est_is with p = q times
+ * the grid's density, whatever q is, so the estimate stays unbiased):
  * w = f(G(y)) J_G(y) exp(-logq).  y_dev [dim][n], logq_dev [n] (NULL means
- * q = 1).  Appends the estimate like vegas_iterate; no histogram. */
+ * q = 1).  Appends the estimate like vegas_iterate; no histogram (a later
+ * vegas_refine still uses the last plain iteration's).  Plain VEGAS judges
+ * the proposal: when logq_dev is given and the estimate's variance per sample
+ * n var(E) exceeds that of the context's latest plain iteration read back by
+ * vegas_iterate, the call returns VGX_EFALLBACK (the estimate, which is
+ * unbiased, is still recorded and combined, and *out_host is filled): the
+ * caller should fall back to plain VEGAS.  VGX_ENUMERIC if not finite. */
 vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double* y_dev, const double* logq_dev,
                                 vgx_iter_result* out_host);
 
@@ -317,6 +351,9 @@ void vegas_destroy(vgx_vegas* v);
 /* ------------------------------------------------------------------------ */
 
 /* RAMBO phase-space points for a total momentum P = (sqrt_s, 0, 0, 0) (async).
+ * Thesis: MC chapter, RAMBO subsection (the recipe, eq. rambo-transform,
+ * the weight eq. rambo-w0 and the massive variant); MadFlow chapter, phase
+ * space generation.
  *   n_part     : final-state particles, 2 .. VGX_MAX_PART.
  *   masses     : host [n_part], >= 0, sum < sqrt_s; all zero: massless RAMBO
  *                (flat weight w0), else the massive variant (weight w0 w_m,
@@ -421,7 +458,10 @@ vgx_status lhe_close(vgx_lhe* w);
 /* ------------------------------------------------------------------------ */
 typedef struct vgx_batch vgx_batch;
 
-/* Bundle contexts (all on one device, no hadronic kinds) into a batch.  The batch
+/* Bundle contexts (all on one device, no hadronic kinds) into a batch.  Each
+ * integral is plain VEGAS as above (MC chapter, VEGAS section); the batch is
+ * a scheduling object the thesis does not have (its tools run one integral
+ * per graph).  The batch
  * captures one iteration (persistent kernel + reductions + refinement) in
  * a HIP graph on first use.  tile = samples per work item (0: autotuned),
  * block = threads per workgroup (0: autotuned). */
@@ -460,11 +500,18 @@ vgx_status flow_shape(const vgx_flow* f, int32_t* dim, int64_t* n_params);
 vgx_status flow_param_layout(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden, int32_t* kind_host,
                              int32_t* fan_in_host, int64_t* size_host, int32_t cap, int32_t* n_seg);
 
-/* Create a flow with the given FP32 initial parameters (sync copy). */
+/* Create a flow with the given FP32 initial parameters (sync copy).  The
+ * caller supplies the initial weights (e.g. He-normal hidden layers and a
+ * zero output layer, the identity map); the thesis's dense layer
+ * y = phi(W x + b) and activation table (deep-learning chapter, "Neural
+ * networks") define the networks. */
 vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden,
                        const float* params_host, int64_t n_params, void* stream, vgx_flow** out);
 
-/* Draw n points from the flow (async): u from Philox (counter (i,
+/* Draw n points from the flow (async).  Thesis: MC chapter, importance
+ * sampling (points from the proposal q together with ln q, so that
+ * w = f/q keeps eq. mc_est_is unbiased) and the inverse transform method
+ * (each coupling inverts a piecewise-linear CDF).  u from Philox (counter (i,
  * iteration, stream_id | 2^23, block), key seed), sampling direction
  * (inverse piecewise-linear CDFs, layers L-1..0) -> y_dev [dim][n] and
  * logq_dev [n] = ln q(y). */
@@ -476,20 +523,25 @@ vgx_status flow_sample(vgx_flow* f, int64_t n, uint64_t seed, uint32_t stream_id
 vgx_status flow_density(vgx_flow* f, int64_t n, const double* y_dev, double* u_dev, double* logq_dev,
                         void* stream);
 
-/* Loss L = mean(g^2/q)/mean(g^2) over the batch (y_dev [dim][n] uniform
+/* Loss and gradient.  Thesis: MC chapter, eq. var_is (the variance of the
+ * importance-sampling estimate is the second moment of f/p less I^2, so
+ * minimising mean(g^2/q) minimises it); deep-learning chapter, learning by
+ * gradient descent on a loss (eq. sgd).  Loss L = mean(g^2/q)/mean(g^2) over the batch (y_dev [dim][n] uniform
  * points of the unit cube, g_dev [n]) and its gradient (sync).  grad_host
  * [n_params] may be NULL. */
 vgx_status flow_loss_grad(vgx_flow* f, int64_t n, const double* y_dev, const double* g_dev,
                           double* loss_host, float* grad_host);
 
-/* One training step: loss and gradient as above, then Adam (beta1 0.9,
+/* One training step.  Thesis: "Optimization methods" (the Adam update
+ * equations and their default constants).  Loss and gradient as above, then Adam (beta1 0.9,
  * beta2 0.999, eps 1e-8, learning rate lr) on the FP32 master weights.
  * loss_host may be NULL (then async).  VGX_EFALLBACK if the loss is not
  * finite (the weights are then left unchanged). */
 vgx_status flow_train_step(vgx_flow* f, int64_t n, const double* y_dev, const double* g_dev,
                            float lr, double* loss_host);
 
-/* Adam alone on a given gradient (async; for tests): grad_dev [n_params]. */
+/* Adam alone on a given gradient (async; for tests): grad_dev [n_params].
+ * Thesis: "Optimization methods", the Adam equations. */
 vgx_status flow_adam(vgx_flow* f, const float* grad_dev, float lr);
 
 vgx_status flow_get_params(vgx_flow* f, float* params_host, int64_t cap, int64_t* n_params);

@@ -109,7 +109,9 @@ def refine(edges, hist, alpha):
     out = edges.copy()
     for j in range(d):
         dj = [float(v) for v in hist[j]]
-        if math.fsum(dj) <= 0.0:
+        # an all-zero histogram, or one holding a non-finite weight (an
+        # iteration the combination excludes), leaves the dimension unchanged
+        if not all(math.isfinite(v) for v in dj) or math.fsum(dj) <= 0.0:
             continue
         sm = [0.0] * nb
         if nb == 1:

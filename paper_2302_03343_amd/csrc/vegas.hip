@@ -785,9 +785,16 @@ vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n) {
   return VGX_OK;
 }
 
+// What produced a record: the context's own sampling (plain VEGAS), caller
+// points with q = 1, or caller points from a proposal with density q.
+enum RecordKind { REC_PLAIN = 0, REC_POINTS = 1, REC_PROPOSAL = 2 };
+
 // Record k and the combination in one round trip: a later vegas_result
 // reads the combination from the host copy until new records are enqueued.
-vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out) {
+// Plain VEGAS judges a proposal: a finite proposal estimate whose variance
+// per sample, n var(E), exceeds that of the latest plain iteration read
+// back returns VGX_EFALLBACK (the estimate is unbiased and stays recorded).
+vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out, RecordKind kind) {
   IterRecord* h = (IterRecord*)v->pinned;
   Combined* hc = (Combined*)((char*)v->pinned + sizeof(IterRecord) * MAX_RECORDS);
   VGX_HIP(hipMemcpyAsync(h, v->rec + k, sizeof(IterRecord), hipMemcpyDeviceToHost, v->stream));
@@ -804,6 +811,13 @@ vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out) {
   if (!h->finite) {
     set_error("non-finite iteration estimate (mean=%g var=%g); excluded from the combination", h->mean, h->var);
     return VGX_ENUMERIC;
+  }
+  const double per_sample = h->var * (double)h->n;
+  if (kind == REC_PLAIN) v->judge_var = per_sample;
+  if (kind == REC_PROPOSAL && v->judge_var >= 0.0 && per_sample > v->judge_var) {
+    set_error("proposal variance per sample %.6g exceeds plain VEGAS's %.6g: fall back to VEGAS", per_sample,
+              v->judge_var);
+    return VGX_EFALLBACK;
   }
   return VGX_OK;
 }
@@ -873,7 +887,7 @@ extern "C" vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, 
   VGX_TRY(iterate_enqueue(v, n, iteration));
   v->comb_fresh = false;
   const int k = v->n_rec++;
-  return read_record(v, k, out);
+  return read_record(v, k, out, REC_PLAIN);
 }
 
 extern "C" vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration) {
@@ -988,7 +1002,7 @@ extern "C" vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double
   VGX_TRY(launch_reduce(v, grid_for(v, n), 4, n));
   v->comb_fresh = false;
   const int k = v->n_rec++;
-  return read_record(v, k, out);
+  return read_record(v, k, out, logq ? REC_PROPOSAL : REC_POINTS);
 }
 
 extern "C" void* vegas_stream(vgx_vegas* v) { return v ? (void*)v->stream : nullptr; }

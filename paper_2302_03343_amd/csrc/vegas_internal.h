@@ -175,7 +175,8 @@ __device__ inline void finalize_record(double s1, double s2, int64_t n, IterReco
 // 3-point smoothing of the accumulated (f J)^2 per bin, normalisation to
 // p_i, damping r_i = ((1 - p_i)/ln(1/p_i))^alpha, re-binning to equal shares
 // of sum r with r spread uniformly inside each old bin.  A dimension whose
-// histogram is all zero is left unchanged.
+// histogram is all zero, or not finite (an iteration with a non-finite
+// weight, which the combination excludes too), is left unchanged.
 __device__ inline void refine_dim(double* __restrict__ ej, const double* __restrict__ hj, int nb, double alpha) {
   __shared__ double d[VGX_MAX_BINS], r[VGX_MAX_BINS], cum[VGX_MAX_BINS + 1], e[VGX_MAX_BINS + 1];
   __shared__ double tot_d, tot_sm;
@@ -188,7 +189,7 @@ __device__ inline void refine_dim(double* __restrict__ ej, const double* __restr
     tot_d = s;
   }
   __syncthreads();
-  if (!(tot_d > 0.0)) return;  // uniform decision: every thread returns
+  if (!(tot_d > 0.0) || !isfinite(tot_d)) return;  // uniform decision: every thread returns
   for (int i = threadIdx.x; i < nb; i += 64) {
     double sm;
     if (nb == 1) sm = d[0];
@@ -263,6 +264,7 @@ struct vgx_vegas {
   void* pinned = nullptr;           // host readback (IterRecord + Combined + grid)
   int n_rec = 0;
   bool comb_fresh = false;           // the host copy of the combination (in pinned) is current
+  double judge_var = -1.0;          // n var(E) of the latest plain iteration read back (< 0: none)
   bool have_hist = false;
   // kernel timing: event pairs recorded around the fused kernel, read back
   // (and summed) only when asked for, so timing does not synchronise

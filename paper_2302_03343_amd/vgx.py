@@ -491,7 +491,10 @@ def vegas_sample(v, first, n, iteration, u=None, g=None):
                               _dptr(g, torch.float64, n if g is not None else None, "g")), "vegas_sample")
 
 
-def vegas_iterate_points(v, y, logq=None, allow_numeric=False):
+def vegas_iterate_points(v, y, logq=None, allow_numeric=False, allow_fallback=False):
+    """Estimate from caller points; with allow_fallback a proposal judged
+    worse than plain VEGAS (VGX_EFALLBACK) returns its result with
+    fallback=True instead of raising."""
     import torch
     n = y.shape[-1]
     r = IterResult()
@@ -499,9 +502,11 @@ def vegas_iterate_points(v, y, logq=None, allow_numeric=False):
     st = _c["vegas_iterate_points"](v, n, _dptr(y, torch.float64, dim * n, "y"),
                                     _dptr(logq, torch.float64, n if logq is not None else None, "logq"),
                                     C.byref(r))
-    if not (allow_numeric and st == VGX_ENUMERIC):
+    if not ((allow_numeric and st == VGX_ENUMERIC) or (allow_fallback and st == VGX_EFALLBACK)):
         _check(st, "vegas_iterate_points")
-    return r.as_dict()
+    d = r.as_dict()
+    d["fallback"] = st == VGX_EFALLBACK
+    return d
 
 
 def vegas_stream(v):

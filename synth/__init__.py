@@ -8,7 +8,7 @@ so that the GPU path and the oracle, which both consume these inputs, share
 no computation.
 """
 from .configs import C0, C1, C2, C3, C4, C5, C6, C7, FLAVOURS
-from .pdfgrid import synthetic_pdf_grid, synthetic_pdf_replicas, PdfGridData
+from .pdfgrid import synthetic_pdf_grid, synthetic_pdf_replicas, nonuniform_pdf_grid, PdfGridData
 from .queries import pdf_queries, fk_points
 from .batch import batch_specs, BatchSpec
 from .flowinit import he_init_segments
@@ -16,6 +16,6 @@ from .alphas import synthetic_alphas, AlphasTable
 
 __all__ = [
     "C0", "C1", "C2", "C3", "C4", "C5", "C6", "C7", "FLAVOURS",
-    "synthetic_pdf_grid", "synthetic_pdf_replicas", "PdfGridData", "pdf_queries", "fk_points",
+    "synthetic_pdf_grid", "synthetic_pdf_replicas", "nonuniform_pdf_grid", "PdfGridData", "pdf_queries", "fk_points",
     "batch_specs", "BatchSpec", "he_init_segments", "synthetic_alphas", "AlphasTable",
 ]

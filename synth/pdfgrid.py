@@ -126,6 +126,46 @@ def synthetic_pdf_grid(cfg=C1):
     return grid
 
 
+def _perturb_interior(knots, frac, rng):
+    """Knots moved, in the logarithm, by up to +-frac of the local spacing;
+    the two end knots stay (they are the grid limits or subgrid thresholds)."""
+    lk = np.log(knots)
+    h = np.diff(lk)
+    out = lk.copy()
+    for k in range(1, len(lk) - 1):
+        out[k] = lk[k] + frac * min(h[k - 1], h[k]) * rng.uniform(-1.0, 1.0)
+    res = np.exp(out)
+    res[0], res[-1] = knots[0], knots[-1]
+    assert np.all(np.diff(res) > 0)
+    return res
+
+
+def nonuniform_pdf_grid(cfg=C1, frac=0.2, seed=11):
+    """The grid of `synthetic_pdf_grid` on knots that are not evenly spaced:
+    every interior x knot and every interior Q^2 knot of each subgrid moved
+    by up to +-frac of a spacing in the logarithm (seeded), the same
+    continuous functions sampled at the moved knots.  Real PDF sets are not
+    evenly spaced in ln x or ln Q^2; this exercises the general cell search
+    and the uneven-spacing slope ratios of an interpolator."""
+    base = synthetic_pdf_grid(cfg)
+    rng = np.random.default_rng(seed)
+    x_knots = _perturb_interior(base.x_knots, frac, rng)
+    q2_knots = [_perturb_interior(q, frac, rng) for q in base.q2_knots]
+    grid = PdfGridData(x_knots=x_knots, q2_knots=q2_knots, xf=[], params=base.params,
+                       lambda_qcd=base.lambda_qcd, q0=base.q0)
+    X = x_knots[None, :]
+    for s, q2 in enumerate(q2_knots):
+        vals = np.zeros((len(FLAVOURS), len(q2), len(x_knots)))
+        for fi, pid in enumerate(FLAVOURS):
+            if abs(pid) == 4 and s < 1:
+                continue
+            if abs(pid) == 5 and s < 2:
+                continue
+            vals[fi] = grid.xf_exact(fi, X, q2[:, None])
+        grid.xf.append(vals)
+    return grid
+
+
 def momentum_sum_at_q0(grid):
     """Exact momentum sum of the continuous functions at Q0 (should be 1)."""
     tot = 0.0

@@ -132,3 +132,65 @@ def test_binding_rejects_short_buffers(vgx):
             vgx.flow_adam(f, torch.zeros(n_par - 1, dtype=torch.float32, device="cuda"), 1e-3)
     finally:
         vgx.flow_destroy(f)
+
+
+@pytest.mark.parametrize("bad", ["nan", "-inf"])
+def test_non_finite_points_iteration_is_reported_and_excluded(vgx, bad):
+    """An iteration whose estimate is not finite returns VGX_ENUMERIC and is
+    left out of the inverse-variance combination; later finite iterations
+    combine as if it had not happened.  The non-finite weight comes from
+    caller points with log q = NaN (or -inf: q = 0, an infinite weight)."""
+    import torch
+    print(f"edges: non-finite points iteration ({bad})", flush=True)
+    dim, n, nb = 3, 20_000, 50
+    prm = np.concatenate([np.full(dim, 0.45), np.full(dim, 0.2)])
+    v = vgx.vegas_create(vgx.GAUSS, dim, nb, 1.5, 5, 0, vgx.F64, prm)
+    try:
+        r0 = vgx.vegas_iterate(v, n, 0)
+        vgx.vegas_refine(v)
+        y = torch.rand((dim, n), dtype=torch.float64, device="cuda",
+                       generator=torch.Generator(device="cuda").manual_seed(3))
+        lq = torch.zeros(n, dtype=torch.float64, device="cuda")
+        lq[17] = float(bad)
+        with pytest.raises(vgx.VgxError) as ei:
+            vgx.vegas_iterate_points(v, y, lq)
+        assert ei.value.status == vgx.VGX_ENUMERIC
+        mid = vgx.vegas_result(v)
+        r2 = vgx.vegas_iterate(v, n, 2)
+        res = vgx.vegas_result(v)
+        recs = vgx.vegas_results(v)
+    finally:
+        vgx.vegas_destroy(v)
+    assert len(recs) == 3 and not math.isfinite(recs[1]["mean"] + recs[1]["var"])
+    assert mid["n_used"] == 1 and mid["mean"] == r0["mean"]
+    assert res["n_used"] == 2
+    m, s, c = ov.combine([r0["mean"], r2["mean"]], [r0["var"], r2["var"]])
+    assert res["mean"] == pytest.approx(m, rel=1e-14)
+    assert res["sigma"] == pytest.approx(s, rel=1e-14)
+    assert res["chi2_dof"] == pytest.approx(c, rel=1e-12, abs=1e-15)
+
+
+def test_non_finite_integrand_iteration_leaves_the_grid(vgx):
+    """An FP32 Gaussian whose normalisation overflows FP32 (sigma = 1e-40 in
+    one dimension: the FP32 normalisation and inverse width are infinite,
+    infinity times exp(-infinity)) gives NaN weights in a
+    plain iteration: VGX_ENUMERIC, nothing combined, and the refinement
+    leaves every dimension of the grid unchanged (its histogram is NaN)."""
+    print("edges: non-finite plain iteration (FP32 overflow)", flush=True)
+    dim, n, nb = 3, 20_000, 50
+    prm = np.array([0.5, 0.5, 0.5, 0.2, 1e-40, 0.2])
+    v = vgx.vegas_create(vgx.GAUSS, dim, nb, 1.5, 5, 0, vgx.F32, prm)
+    try:
+        vgx.vegas_set_grid(v, np.tile(np.linspace(0.0, 1.0, nb + 1) ** 1.3, (dim, 1)))
+        e0 = vgx.vegas_get_grid(v, dim, nb)
+        with pytest.raises(vgx.VgxError) as ei:
+            vgx.vegas_iterate(v, n, 0)
+        assert ei.value.status == vgx.VGX_ENUMERIC
+        assert np.isnan(vgx.vegas_get_hist(v, dim, nb)).all()
+        vgx.vegas_refine(v)
+        e1 = vgx.vegas_get_grid(v, dim, nb)
+        res = vgx.vegas_result(v)
+    finally:
+        vgx.vegas_destroy(v)
+    assert np.array_equal(e1, e0)
+    assert res["n_used"] == 0

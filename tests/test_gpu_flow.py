@@ -357,3 +357,67 @@ def test_training_is_bit_reproducible(vgx):
             vgx.vegas_destroy(v)
     assert finals[0][0] == finals[1][0]
     assert np.array_equal(finals[0][1], finals[1][1])
+
+
+def histogram_flow_params(dim, centre, width, sign=-1.0):
+    """Parameters of a flow whose networks ignore their inputs (all weight
+    matrices zero): layers 0 and 1, which between them transform every
+    dimension once, put bin logits sign ((k + 1/2)/K - centre)^2/(2 width^2)
+    on their B dims; the other layers are the identity.  q is then a product
+    of one-dimensional histograms: a Gaussian shape (sign -1) or its
+    opposite, smallest at the centre (sign +1)."""
+    th = np.zeros(of.n_params(dim, L, K, H), dtype=np.float32)
+    t = (np.arange(K) + 0.5) / K
+    logits = (sign * (t - centre) ** 2 / (2 * width ** 2)).astype(np.float32)
+    off = 0
+    for li, sh in enumerate(of.layer_shapes(dim, L, K, H)):
+        sz = sh["sizes"]
+        if li < 2:
+            o3 = off + sum(sz[:5])
+            th[o3:o3 + sz[5]] = np.tile(logits, len(sh["B"]))
+        off += sum(sz)
+    return th
+
+
+def test_proposal_worse_than_vegas_signals_fallback(vgx):
+    """Plain VEGAS judges a proposal: points from a flow whose variance per
+    sample exceeds that of the context's latest plain iteration return
+    VGX_EFALLBACK (the unbiased estimate is still recorded); a better flow
+    does not.  Target: a d = 3 Gaussian (centre 0.5, width 0.1) on the
+    uniform grid, relative variance per sample about 21 for plain VEGAS;
+    a flow peaked on the Gaussian (about 0.025) and one shaped the opposite
+    way, least dense at the peak (about 108; q is bounded below everywhere,
+    so the sample variance is a sound estimate)."""
+    import torch
+    print("flow: fallback judged by plain VEGAS", flush=True)
+    dim, n = 3, 200_000
+    c, s = 0.5, 0.1
+    v = vgx.vegas_create(vgx.GAUSS, dim, 50, 1.5, 8, 0, vgx.F64,
+                         np.concatenate([np.full(dim, c), np.full(dim, s)]))
+    good = make_flow(vgx, dim, histogram_flow_params(dim, 0.5, 0.1))
+    bad = make_flow(vgx, dim, histogram_flow_params(dim, 0.5, 0.3, sign=1.0))
+    try:
+        plain = vgx.vegas_iterate(v, n, 0)
+        y = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(good, n, 9, 0, 0, y, lq)
+        rg = vgx.vegas_iterate_points(v, y, lq)
+        assert not rg["fallback"]
+        vgx.flow_sample(bad, n, 9, 0, 1, y, lq)
+        with pytest.raises(vgx.VgxError) as ei:
+            vgx.vegas_iterate_points(v, y, lq)
+        assert ei.value.status == vgx.VGX_EFALLBACK
+        vgx.flow_sample(bad, n, 9, 0, 2, y, lq)
+        rb = vgx.vegas_iterate_points(v, y, lq, allow_fallback=True)
+        assert rb["fallback"]
+        res = vgx.vegas_result(v)
+    finally:
+        vgx.flow_destroy(good)
+        vgx.flow_destroy(bad)
+        vgx.vegas_destroy(v)
+    rv = lambda r: r["var"] * r["n"] / r["mean"] ** 2
+    print(f"  rel. variance per sample: VEGAS {rv(plain):.3g}, good flow {rv(rg):.3g}, bad flow {rv(rb):.3g}")
+    assert rv(rg) < rv(plain) < rv(rb)
+    I = gauss_integral(dim, c, s)
+    assert abs(rg["mean"] - I) < 5 * math.sqrt(rg["var"])
+    assert res["n_used"] == 4          # fallback estimates stay in the combination

@@ -16,8 +16,11 @@ from oracle import singletop as st, vegas as ov
 from oracle.philox import sample_uniforms
 from synth import C6
 
+from tests import fp32_bars
+
 pytestmark = pytest.mark.gpu
 
+LABEL = "single top"
 PARAMS = np.array([C6["sqrt_s"], C6["m_top"], C6["m_w"], C6["gamma_w"], C6["sw2"], C6["alpha_em"],
                    C6["gev2_to_pb"]])
 
@@ -43,13 +46,9 @@ def oracle_g(grid, u, e):
     return st.integrand_from_config(x, grid, C6) * jac, x
 
 
-def check_events(got, ref, keep):
-    err = np.abs(got - ref)
-    rel = err / np.abs(ref)
-    floor = 1e-7 * np.mean(np.abs(ref))
-    ok = (rel <= 1e-5) | (err <= floor)
-    assert ok[keep].all(), f"p99 rel {np.percentile(rel[keep], 99):.2e}, worst {rel[keep][~ok[keep]].max():.2e}"
-    assert np.mean(rel[keep] > 1e-5) < 5e-3
+def check_events(got, ref, keep, label="single top"):
+    """Per-event bars and their error model: `tests/fp32_bars.py`."""
+    return fp32_bars.check_events(got, ref, keep, label)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -71,7 +70,7 @@ def test_per_event_integrand(vgx, pdf_ctx, c1_grid, grid_kind, mode):
         ref, x = oracle_g(c1_grid, u, e)
         keep = ~near_knot(c1_grid, x)
         assert keep.sum() > 0.999 * n
-        check_events(g.cpu().numpy(), ref, keep)
+        check_events(g.cpu().numpy(), ref, keep, f"{LABEL} mode {mode} {grid_kind}")
     finally:
         vgx.vegas_destroy(v)
 

@@ -163,3 +163,19 @@ def test_converged_grid_matches_gaussian_quantiles():
     q = c + s * ndtri(lo + Z * np.arange(1, nb) / nb)
     widths = np.diff(e)
     assert np.all(np.abs(e[1:-1] - q) < 1.5 * np.maximum(widths[:-1], widths[1:]))
+
+
+def test_refine_skips_non_finite_histograms():
+    """A dimension whose histogram holds a non-finite weight (an iteration the
+    combination excludes) keeps its edges; the other dimensions refine as
+    they would alone."""
+    rng = np.random.default_rng(4)
+    e = vegas.uniform_grid(3, 10)
+    h = rng.uniform(0.1, 2.0, size=(3, 10))
+    ref = vegas.refine(e, h, 1.5)
+    for bad in (np.nan, np.inf):
+        hb = h.copy()
+        hb[1, 4] = bad
+        out = vegas.refine(e, hb, 1.5)
+        assert np.array_equal(out[1], e[1])
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[2], ref[2])
