@@ -162,7 +162,8 @@ def test_non_finite_points_iteration_is_reported_and_excluded(vgx, bad):
     finally:
         vgx.vegas_destroy(v)
     assert len(recs) == 3 and not math.isfinite(recs[1]["mean"] + recs[1]["var"])
-    assert mid["n_used"] == 1 and mid["mean"] == r0["mean"]
+    # one record: the weighted average (E/var)/(1/var) returns E to rounding
+    assert mid["n_used"] == 1 and mid["mean"] == pytest.approx(r0["mean"], rel=1e-15)
     assert res["n_used"] == 2
     m, s, c = ov.combine([r0["mean"], r2["mean"]], [r0["var"], r2["var"]])
     assert res["mean"] == pytest.approx(m, rel=1e-14)
