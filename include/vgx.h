@@ -104,6 +104,7 @@ enum {
 enum { VGX_F64 = 0, VGX_F32 = 1 };   /* integrand / output precision          */
 /* PDF / alpha_s behaviour outside the grid (pdf_set_extrapolation) */
 enum { VGX_EXTRAP_ERROR = 0, VGX_EXTRAP_FREEZE = 1, VGX_EXTRAP_CONTINUE = 2 };
+enum { VGX_OPERANDS_BF16 = 0, VGX_OPERANDS_F32 = 1 };  /* flow matrix-product operands */
 
 #define VGX_MAX_DIM 12
 #define VGX_MAX_BINS 256
@@ -507,6 +508,20 @@ vgx_status flow_param_layout(int32_t dim, int32_t n_layers, int32_t n_bins, int3
  * networks") define the networks. */
 vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins, int32_t hidden,
                        const float* params_host, int64_t n_params, void* stream, vgx_flow** out);
+
+/* Operand precision of the flow's matrix products (sync).  VGX_OPERANDS_BF16
+ * (the default) is the product path: BF16 weights and activations on
+ * v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  VGX_OPERANDS_F32 is a
+ * validation mode running the same kernels and tile structure with FP32
+ * operands (v_mfma_f32_32x32x2_f32), so that densities and every gradient
+ * element can be compared with the FP64 oracle at FP32 rounding.  The
+ * network definition is the thesis's dense layer y = phi(W x + b)
+ * (deep-learning chapter, "Neural networks").  The FP32 mode keeps all
+ * layers' weights in LDS like the BF16 one, at twice the bytes: VGX_EINVAL
+ * if they do not fit (dimensions above 4 with four layers); the mode is
+ * then unchanged.  Training scratch is reallocated on the next training
+ * call; the master weights and Adam moments are kept. */
+vgx_status flow_set_operands(vgx_flow* f, int32_t operands);
 
 /* Draw n points from the flow (async).  Thesis: MC chapter, importance
  * sampling (points from the proposal q together with ln q, so that

@@ -31,11 +31,19 @@ the piecewise-linear one of Mueller et al., "Neural importance sampling",
     whose minimum is at q proportional to |g| (zero-variance importance
     sampling), and dL/dlog q_i = -(g_i^2/q_i) / (n mean(g^2)).
 
+Two optional arguments serve the parity tests and leave the arithmetic
+above unchanged when absent: an `operand` hook that maps each input of a
+matrix product to the value a reduced-precision product takes (the
+spec fixes BF16 operands with FP32 accumulation for the networks),
+and gradient magnitudes (the gradient formula on absolute values), the
+scale of the rounding error of any evaluation order.
+
 Pins: tests/test_oracle_flow.py -- sampling and density directions invert
 each other; q integrates to 1 (lattice sum); zero output weights give the
 identity map with q = 1; analytic gradients match central finite
-differences; Adam on a constant gradient g moves every step by exactly
-lr g/(|g| + eps) (bias corrections cancel), and it converges on a
+differences; the magnitudes bound the per-sample gradient terms (brute
+force over samples); Adam on a constant gradient g moves every step by
+exactly lr g/(|g| + eps) (bias corrections cancel), and it converges on a
 one-dimensional quadratic; unbiasedness of g/q for trained and random
 weights.
 """
@@ -105,21 +113,33 @@ def unpack(theta, dim, n_layers, n_bins, hidden):
     return layers
 
 
-def _mlp(p, zA, n_bins):
-    pre1 = zA @ p["W1"].T + p["b1"]
+def _same(a, mag=None):
+    return a
+
+
+def _mlp(p, zA, n_bins, operand=_same):
+    """The layer's network.  `operand(a, mag)` maps each input of a matrix
+    product (the layer input and the two hidden activations) to the value
+    the product takes, given the sum of the magnitudes of the terms that
+    formed it (mag); the identity (default) is the plain FP64 network, and
+    tests pass a model of reduced-precision operands."""
+    a0 = operand(zA, np.abs(zA))
+    pre1 = a0 @ p["W1"].T + p["b1"]
     h1 = np.maximum(pre1, 0.0)
-    pre2 = h1 @ p["W2"].T + p["b2"]
+    a1 = h1 if operand is _same else operand(h1, np.abs(a0) @ np.abs(p["W1"]).T + np.abs(p["b1"]))
+    pre2 = a1 @ p["W2"].T + p["b2"]
     h2 = np.maximum(pre2, 0.0)
-    logits = h2 @ p["W3"].T + p["b3"]
+    a2 = h2 if operand is _same else operand(h2, np.abs(a1) @ np.abs(p["W2"]).T + np.abs(p["b2"]))
+    logits = a2 @ p["W3"].T + p["b3"]
     n = zA.shape[0]
     lg = logits.reshape(n, len(p["B"]), n_bins)
     lg = lg - lg.max(axis=2, keepdims=True)
     e = np.exp(lg)
     Q = e / e.sum(axis=2, keepdims=True)
-    return dict(pre1=pre1, h1=h1, pre2=pre2, h2=h2, Q=Q)
+    return dict(pre1=pre1, h1=h1, pre2=pre2, h2=h2, Q=Q, a0=a0, a1=a1, a2=a2)
 
 
-def density(theta, y, dim, n_layers, n_bins, hidden, keep=False):
+def density(theta, y, dim, n_layers, n_bins, hidden, keep=False, operand=_same):
     """Density direction: returns (u, log q) [and per-layer caches]."""
     layers = unpack(theta, dim, n_layers, n_bins, hidden)
     z = np.array(y, dtype=np.float64, copy=True)
@@ -128,7 +148,7 @@ def density(theta, y, dim, n_layers, n_bins, hidden, keep=False):
     caches = []
     for p in layers:
         A, B = p["A"], p["B"]
-        m = _mlp(p, z[:, A], n_bins)
+        m = _mlp(p, z[:, A], n_bins, operand)
         Q = m["Q"]
         cum = np.concatenate([np.zeros((n, len(B), 1)), np.cumsum(Q, axis=2)], axis=2)
         zin = z.copy()
@@ -150,7 +170,7 @@ def density(theta, y, dim, n_layers, n_bins, hidden, keep=False):
     return z, logq
 
 
-def sample(theta, u, dim, n_layers, n_bins, hidden):
+def sample(theta, u, dim, n_layers, n_bins, hidden, operand=_same):
     """Sampling direction: returns (y, log q)."""
     layers = unpack(theta, dim, n_layers, n_bins, hidden)
     z = np.array(u, dtype=np.float64, copy=True)
@@ -158,7 +178,7 @@ def sample(theta, u, dim, n_layers, n_bins, hidden):
     logq = np.zeros(n)
     for p in reversed(layers):
         A, B = p["A"], p["B"]
-        Q = _mlp(p, z[:, A], n_bins)["Q"]
+        Q = _mlp(p, z[:, A], n_bins, operand)["Q"]
         cum = np.cumsum(Q, axis=2)
         for jb, j in enumerate(B):
             v = z[:, j]
@@ -178,26 +198,46 @@ def loss(theta, y, g, dim, n_layers, n_bins, hidden):
     return float(np.mean(g2 * np.exp(-logq)) / np.mean(g2))
 
 
-def loss_and_grad(theta, y, g, dim, n_layers, n_bins, hidden):
-    """Return (L, dL/dtheta (flat, FP64), log q)."""
+def loss_and_grad(theta, y, g, dim, n_layers, n_bins, hidden, operand=_same, magnitudes=False):
+    """Return (L, dL/dtheta (flat, FP64), log q) [, magnitudes].
+
+    `operand(a, mag)` maps every input of a matrix product, forward (layer
+    input, hidden activations) and backward (the deltas that meet the
+    weights and the activations), to the value the product takes, given the
+    sum of the magnitudes of the terms that formed it; the identity
+    (default) is plain FP64.
+
+    magnitudes=True also returns, per parameter, the same gradient formula
+    evaluated on magnitudes: every product of a delta and an activation
+    taken as the product of their magnitudes, every sum or difference (the
+    hidden units' pre-activations, the softmax backward's dQ_k - sum Q dQ,
+    the deltas' dot products with the weights, the sums over samples) as
+    the sum of the absolute values of its terms.  It bounds |dL/dtheta_p| from above and sets the scale of
+    the rounding error of any evaluation order of the gradient (the
+    running-error bound of a sum); where no cancellation occurs it equals
+    |dL/dtheta_p|.
+    """
     y = np.asarray(y, dtype=np.float64)
     g2 = np.asarray(g, dtype=np.float64) ** 2
     n = y.shape[0]
     layers = unpack(theta, dim, n_layers, n_bins, hidden)
-    _, logq, caches = density(theta, y, dim, n_layers, n_bins, hidden, keep=True)
+    _, logq, caches = density(theta, y, dim, n_layers, n_bins, hidden, keep=True, operand=operand)
     ratio = g2 * np.exp(-logq)
     m2 = np.mean(g2)
     L = float(np.mean(ratio) / m2)
     dlogq = -ratio / (n * m2)           # dL/dlog q_i (shared by all layers)
     dz = np.zeros_like(y)               # dL/dz at the output (u): zero
-    grads = []
+    mz = np.zeros_like(y)               # its magnitude
+    grads, mags = [], []
     for p, c in zip(reversed(layers), reversed(caches)):
         A, B = p["A"], p["B"]
         m = c["m"]
         Q = m["Q"]
         bins, alphas = c["bins"], c["alphas"]
         dQ = np.zeros_like(Q)
+        mQ = np.zeros_like(Q)
         dz_in = dz.copy()
+        mz_in = mz.copy()
         rows = np.arange(n)
         for jb, j in enumerate(B):
             b = bins[:, jb]
@@ -206,28 +246,53 @@ def loss_and_grad(theta, y, g, dim, n_layers, n_bins, hidden):
             # z'_j = sum_{k<b} Q_k + alpha Q_b ;  ld = ln K + ln Q_b
             mask_lt = np.arange(n_bins)[None, :] < b[:, None]
             dQ[:, jb, :] += gz[:, None] * mask_lt
+            mQ[:, jb, :] += mz[:, j][:, None] * mask_lt
             qb = Q[rows, jb, b]
             dQ[rows, jb, b] += gz * al + dlogq / qb
+            mQ[rows, jb, b] += mz[:, j] * al + np.abs(dlogq) / qb
             dz_in[:, j] = gz * n_bins * qb  # dz'_j/dz_j = K Q_b
+            mz_in[:, j] = mz[:, j] * n_bins * qb
         # softmax backward
         dlog = Q * (dQ - np.sum(Q * dQ, axis=2, keepdims=True))
         dlog = dlog.reshape(n, -1)
-        gW3 = dlog.T @ m["h2"]
-        gb3 = dlog.sum(axis=0)
-        dh2 = dlog @ p["W3"]
+        mlog = (Q * (mQ + np.sum(Q * mQ, axis=2, keepdims=True))).reshape(n, -1)
+        if operand is _same:
+            o3 = dlog
+        else:
+            aQ = np.abs(dQ)
+            o3 = operand(dlog, (Q * (aQ + np.sum(Q * aQ, axis=2, keepdims=True))).reshape(n, -1))
+        gW3 = o3.T @ m["a2"]
+        gb3 = o3.sum(axis=0)
+        dh2 = o3 @ p["W3"]
         dpre2 = dh2 * (m["pre2"] > 0)
-        gW2 = dpre2.T @ m["h1"]
-        gb2 = dpre2.sum(axis=0)
-        dh1 = dpre2 @ p["W2"]
+        o2 = dpre2 if operand is _same else operand(dpre2, (np.abs(o3) @ np.abs(p["W3"])) * (m["pre2"] > 0))
+        gW2 = o2.T @ m["a1"]
+        gb2 = o2.sum(axis=0)
+        dh1 = o2 @ p["W2"]
         dpre1 = dh1 * (m["pre1"] > 0)
-        zA = c["zin"][:, A]
-        gW1 = dpre1.T @ zA
-        gb1 = dpre1.sum(axis=0)
-        dzA = dpre1 @ p["W1"]
+        o1 = dpre1 if operand is _same else operand(dpre1, (np.abs(o2) @ np.abs(p["W2"])) * (m["pre1"] > 0))
+        gW1 = o1.T @ m["a0"]
+        gb1 = o1.sum(axis=0)
+        dzA = o1 @ p["W1"]
         dz_in[:, A] += dzA
         dz = dz_in
         grads.append([gW1, gb1, gW2, gb2, gW3, gb3])
+        if magnitudes:
+            # activations as sums of magnitudes too (a hidden unit just above
+            # zero is a cancellation of its pre-activation's terms)
+            ma0 = np.abs(m["a0"])
+            ma1 = (ma0 @ np.abs(p["W1"]).T + np.abs(p["b1"])) * (m["pre1"] > 0)
+            ma2 = (ma1 @ np.abs(p["W2"]).T + np.abs(p["b2"])) * (m["pre2"] > 0)
+            m2p = (mlog @ np.abs(p["W3"])) * (m["pre2"] > 0)
+            m1p = (m2p @ np.abs(p["W2"])) * (m["pre1"] > 0)
+            mz_in[:, A] += m1p @ np.abs(p["W1"])
+            mags.append([m1p.T @ ma0, m1p.sum(axis=0), m2p.T @ ma1, m2p.sum(axis=0), mlog.T @ ma2,
+                         mlog.sum(axis=0)])
+        mz = mz_in
     flat = np.concatenate([np.concatenate([t.ravel() for t in gl]) for gl in reversed(grads)])
+    if magnitudes:
+        mflat = np.concatenate([np.concatenate([t.ravel() for t in gl]) for gl in reversed(mags)])
+        return L, flat, logq, mflat
     return L, flat, logq
 
 

@@ -42,7 +42,44 @@
 namespace vgx {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Operand precision of the networks' matrix products.  OpBF16 is the
+// product path (v_mfma_f32_32x32x16_bf16).  OpF32 is a validation build of
+// the same tile structure: a K = 16 step becomes eight K = 2 steps of
+// v_mfma_f32_32x32x2_f32 over the same eight operand registers (lane (i, h)
+// supplies k = h of step e, the element that the BF16 form reads as
+// k = 8 h + e, so the sum over a step is the same), FP32 packs and tiles;
+// with it the kernels can be compared with the FP64 oracle at FP32 rounding.
+struct OpBF16 {
+  using S = unsigned short;  // storage element of the weight packs and tiles
+  using frag = bf16x8;
+  static constexpr int kEs = 2;
+  static __device__ __forceinline__ f32x16 mma(const frag& a, const frag& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void set(frag& f, int e, float x) { f[e] = (__bf16)x; }
+  static __device__ __forceinline__ float get(const frag& f, int e) { return (float)f[e]; }
+  static __device__ __forceinline__ S store(float x) {
+    const __bf16 b = (__bf16)x;
+    return *(const S*)&b;
+  }
+};
+
+struct OpF32 {
+  using S = float;
+  using frag = f32x8;
+  static constexpr int kEs = 4;
+  static __device__ __forceinline__ f32x16 mma(const frag& a, const frag& b, f32x16 c) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], c, 0, 0, 0);
+    return c;
+  }
+  static __device__ __forceinline__ void set(frag& f, int e, float x) { f[e] = x; }
+  static __device__ __forceinline__ float get(const frag& f, int e) { return f[e]; }
+  static __device__ __forceinline__ S store(float x) { return x; }
+};
 
 constexpr int FH = 64;       // hidden width
 constexpr int FK = 32;       // bins
@@ -74,10 +111,6 @@ struct FlowDesc {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-
 __device__ __forceinline__ f32x16 zero16() {
   f32x16 z;
 #pragma unroll
@@ -86,10 +119,11 @@ __device__ __forceinline__ f32x16 zero16() {
 }
 
 // 8 consecutive accumulator registers as a B operand (K step half 0 or 1).
-__device__ __forceinline__ bf16x8 to_b(const f32x16& c, int half) {
-  bf16x8 r;
+template <class OP>
+__device__ __forceinline__ typename OP::frag to_b(const f32x16& c, int half) {
+  typename OP::frag r;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) r[e] = (__bf16)(half ? c[8 + e] : c[e]);
+  for (int e = 0; e < 8; ++e) OP::set(r, e, half ? c[8 + e] : c[e]);
   return r;
 }
 
@@ -119,22 +153,26 @@ __device__ __forceinline__ void zset(float (&z)[FDM], int j, float v) {
   for (int k = 0; k < FDM; ++k) z[k] = (k == j) ? v : z[k];
 }
 
+template <class OP>
 struct LayerLds {
-  const bf16x8* w1p;   // [2][32][2]
-  const bf16x8* w2p;   // [2][4][32][2]
-  const bf16x8* w3p;   // [nb][4][32][2]
+  using frag = typename OP::frag;
+  const frag* w1p;   // [2][32][2]
+  const frag* w2p;   // [2][4][32][2]
+  const frag* w3p;   // [nb][4][32][2]
   const float* b1;
   const float* b2;
   const float* b3;
 };
 
-__device__ __forceinline__ LayerLds layer_lds(const unsigned short* fw, const float* bias, const FlowLayerDesc& L,
-                                              int fw_base, int bias_base) {
-  LayerLds r;
-  const unsigned short* p = fw + (L.fw_off - fw_base);
-  r.w1p = (const bf16x8*)p;
-  r.w2p = (const bf16x8*)(p + 1024);
-  r.w3p = (const bf16x8*)(p + 1024 + 4096);
+template <class OP>
+__device__ __forceinline__ LayerLds<OP> layer_lds(const typename OP::S* fw, const float* bias, const FlowLayerDesc& L,
+                                                  int fw_base, int bias_base) {
+  using frag = typename OP::frag;
+  LayerLds<OP> r;
+  const typename OP::S* p = fw + (L.fw_off - fw_base);
+  r.w1p = (const frag*)p;
+  r.w2p = (const frag*)(p + 1024);
+  r.w3p = (const frag*)(p + 1024 + 4096);
   const float* b = bias + (L.bias_off - bias_base);
   r.b1 = b;
   r.b2 = b + FH;
@@ -159,16 +197,16 @@ __device__ __forceinline__ f32x16 bias_tile(const float* b, int h) {
 
 // Network forward of one layer for the wave's 32 samples (transposed form);
 // the biases enter as the accumulators' initial values.
-template <int NBM>
-__device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, const LayerLds& W, f32x16 (&h1)[2],
+template <int NBM, class OP>
+__device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, const LayerLds<OP>& W, f32x16 (&h1)[2],
                                         f32x16 (&h2)[2], f32x16 (&lg)[NBM]) {
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
-  bf16x8 bz;
+  typename OP::frag bz;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) bz[e] = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
+  for (int e = 0; e < 8; ++e) OP::set(bz, e, (h == 0 && e < na) ? za[e] : 0.0f);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    h1[t] = mfma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
+    h1[t] = OP::mma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
 #pragma unroll
     for (int v = 0; v < 16; ++v) h1[t][v] = fmaxf(h1[t][v], 0.0f);
   }
@@ -176,7 +214,8 @@ __device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, 
   for (int t = 0; t < 2; ++t) {
     f32x16 acc = bias_tile(W.b2 + 32 * t, h);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], to_b(h1[kk >> 1], kk & 1), acc);
+    for (int kk = 0; kk < 4; ++kk)
+      acc = OP::mma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], to_b<OP>(h1[kk >> 1], kk & 1), acc);
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v], 0.0f);
     h2[t] = acc;
@@ -186,7 +225,8 @@ __device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, 
     if (t < nb) {
       f32x16 acc = bias_tile(W.b3 + 32 * t, h);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], to_b(h2[kk >> 1], kk & 1), acc);
+      for (int kk = 0; kk < 4; ++kk)
+        acc = OP::mma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], to_b<OP>(h2[kk >> 1], kk & 1), acc);
       lg[t] = acc;
     }
   }
@@ -195,38 +235,41 @@ __device__ __forceinline__ void mlp_fwd(const float (&za)[FAB], int na, int nb, 
 // The network's hidden layers for the wave's 32 samples (transposed form):
 // h2 = relu(W2 relu(W1 zA + b1) + b2), returned as the four BF16 K-step
 // operands of the output layer (each activation converted once).
-__device__ __forceinline__ void mlp_hidden(const float (&za)[FAB], int na, const LayerLds& W, bf16x8 (&h2b)[4]) {
+template <class OP>
+__device__ __forceinline__ void mlp_hidden(const float (&za)[FAB], int na, const LayerLds<OP>& W,
+                                           typename OP::frag (&h2b)[4]) {
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
-  bf16x8 bz;
+  typename OP::frag bz;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) bz[e] = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
-  bf16x8 h1b[4];
+  for (int e = 0; e < 8; ++e) OP::set(bz, e, (h == 0 && e < na) ? za[e] : 0.0f);
+  typename OP::frag h1b[4];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    f32x16 h1 = mfma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
+    f32x16 h1 = OP::mma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
 #pragma unroll
     for (int v = 0; v < 16; ++v) h1[v] = fmaxf(h1[v], 0.0f);
-    h1b[2 * t] = to_b(h1, 0);
-    h1b[2 * t + 1] = to_b(h1, 1);
+    h1b[2 * t] = to_b<OP>(h1, 0);
+    h1b[2 * t + 1] = to_b<OP>(h1, 1);
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     f32x16 acc = bias_tile(W.b2 + 32 * t, h);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], h1b[kk], acc);
+    for (int kk = 0; kk < 4; ++kk) acc = OP::mma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], h1b[kk], acc);
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v], 0.0f);
-    h2b[2 * t] = to_b(acc, 0);
-    h2b[2 * t + 1] = to_b(acc, 1);
+    h2b[2 * t] = to_b<OP>(acc, 0);
+    h2b[2 * t + 1] = to_b<OP>(acc, 1);
   }
 }
 
 // The 32 logits of transformed dimension t for the wave's 32 samples.
-__device__ __forceinline__ f32x16 mlp_logits(const bf16x8 (&h2b)[4], int t, const LayerLds& W) {
+template <class OP>
+__device__ __forceinline__ f32x16 mlp_logits(const typename OP::frag (&h2b)[4], int t, const LayerLds<OP>& W) {
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
   f32x16 acc = bias_tile(W.b3 + 32 * t, h);
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) acc = mfma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], h2b[kk], acc);
+  for (int kk = 0; kk < 4; ++kk) acc = OP::mma(W.w3p[((t * 4 + kk) * 32 + i) * 2 + h], h2b[kk], acc);
   return acc;
 }
 
@@ -367,8 +410,9 @@ struct FwdArgs {
 };
 
 // LDS of a forward kernel: packed weights | biases | per-lane z [d][FWD_BLOCK]
-__host__ __device__ inline size_t fwd_z_offset(int fw_total, int bias_total) {
-  return (((size_t)fw_total * 2 + (size_t)bias_total * 4) + 15) & ~(size_t)15;
+// (es: bytes per packed weight)
+__host__ __device__ inline size_t fwd_z_offset(int fw_total, int bias_total, int es) {
+  return (((size_t)fw_total * es + (size_t)bias_total * 4) + 15) & ~(size_t)15;
 }
 
 // ---- one sample per lane after a tile pair's exchange ---------------------
@@ -490,17 +534,19 @@ __device__ __forceinline__ float cdf_inv_own(const f32x16& lo, const f32x16& hi,
   return ((float)bb + frac) * (1.0f / (float)FK);
 }
 
-template <int NBM, int MODE>
-__global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restrict__ Dp, FwdArgs a, const unsigned short* __restrict__ fw,
+template <int NBM, int MODE, class OP>
+__global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restrict__ Dp, FwdArgs a,
+                                                     const typename OP::S* __restrict__ fw,
                                                      const float* __restrict__ bias) {
+  using S = typename OP::S;
   extern __shared__ __align__(16) unsigned char flds[];
   const FlowDesc& D = *Dp;
-  unsigned short* sfw = (unsigned short*)flds;
-  float* sb = (float*)(flds + D.fw_total * 2);
+  S* sfw = (S*)flds;
+  float* sb = (float*)(flds + (size_t)D.fw_total * sizeof(S));
   // each lane keeps its own sample's coordinates in its own LDS column (the
   // layer masks index them with runtime, wave-uniform indices)
-  float* z = (float*)(flds + fwd_z_offset(D.fw_total, D.bias_total)) + threadIdx.x;
-  copy16(sfw, fw, D.fw_total * 2);
+  float* z = (float*)(flds + fwd_z_offset(D.fw_total, D.bias_total, (int)sizeof(S))) + threadIdx.x;
+  copy16(sfw, fw, D.fw_total * (int)sizeof(S));
   copy16(sb, bias, D.bias_total * 4);
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -539,14 +585,14 @@ __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restri
         za[e] = (e < L.na) ? z[L.a_idx[e] * FWD_BLOCK] : 0.0f;
         zb[e] = xor32(za[e]);
       }
-      const LayerLds W = layer_lds(sfw, sb, L, 0, 0);
-      bf16x8 h2A[4], h2B[4];
-      mlp_hidden(za, L.na, W, h2A);
-      mlp_hidden(zb, L.na, W, h2B);
+      const LayerLds<OP> W = layer_lds<OP>(sfw, sb, L, 0, 0);
+      typename OP::frag h2A[4], h2B[4];
+      mlp_hidden<OP>(za, L.na, W, h2A);
+      mlp_hidden<OP>(zb, L.na, W, h2B);
       // one transformed dimension at a time: its logits for both tiles,
       // exchanged so that every lane holds its own sample's 32 logits
       for (int jb = 0; jb < L.nb; ++jb) {
-        f32x16 lo = mlp_logits(h2A, jb, W), hi = mlp_logits(h2B, jb, W);
+        f32x16 lo = mlp_logits<OP>(h2A, jb, W), hi = mlp_logits<OP>(h2B, jb, W);
         pair_swap(lo, hi);
         const float sum = softexp_own(lo, hi);
         const int j = L.b_idx[jb];
@@ -623,48 +669,49 @@ struct BwdArgs {
   float* dzin;          // [d][n] gradient w.r.t. the layer input
   const double* rsave;  // [n]
   const double* loss;   // [3]: L, scale, ok
-  unsigned short* scr;  // bf16 scratch
+  void* scr;            // operand tiles (OP::S elements)
   int srows;            // scratch rows per tile
 };
 
-__device__ __forceinline__ void put_tile(unsigned short* base, int row0, const f32x16& c, int s, int h) {
+template <class OP>
+__device__ __forceinline__ void put_tile(typename OP::S* base, int row0, const f32x16& c, int s, int h) {
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const __bf16 x = (__bf16)c[v];
-    base[(row0 + drow(v, h)) * 32 + s] = *(const unsigned short*)&x;
-  }
+  for (int v = 0; v < 16; ++v) base[(row0 + drow(v, h)) * 32 + s] = OP::store(c[v]);
 }
 
 // LDS of the backward kernel: the layer's forward and backward packs and
 // biases, then per-lane columns z, dz_out, dz [3][d][FBLOCK]
-__host__ __device__ inline size_t bwd_z_offset(int fw_len, int bw_len, int bias_len) {
-  return (((size_t)fw_len * 2 + (size_t)bw_len * 2 + (size_t)bias_len * 4) + 15) & ~(size_t)15;
+__host__ __device__ inline size_t bwd_z_offset(int fw_len, int bw_len, int bias_len, int es) {
+  return (((size_t)fw_len * es + (size_t)bw_len * es + (size_t)bias_len * 4) + 15) & ~(size_t)15;
 }
 
-template <int NBM>
-__global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const FlowDesc* __restrict__ Dp, BwdArgs a, const unsigned short* __restrict__ fw,
-                                                     const unsigned short* __restrict__ bw,
-                                                     const float* __restrict__ bias) {
+template <int NBM, class OP>
+__global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const FlowDesc* __restrict__ Dp, BwdArgs a,
+                                                                       const typename OP::S* __restrict__ fw,
+                                                                       const typename OP::S* __restrict__ bw,
+                                                                       const float* __restrict__ bias) {
+  using S = typename OP::S;
+  using frag = typename OP::frag;
   extern __shared__ __align__(16) unsigned char flds[];
   const FlowDesc& D = *Dp;
   const FlowLayerDesc& L = D.l[a.layer];
-  unsigned short* sfw = (unsigned short*)flds;
-  unsigned short* sbw = sfw + L.fw_len;
+  S* sfw = (S*)flds;
+  S* sbw = sfw + L.fw_len;
   float* sb = (float*)(sbw + L.bw_len);
   const int d = D.d;
   // the sample's coordinates (z), the incoming gradient (gz) and the
   // outgoing gradient (dz) in the lane's own LDS columns
-  float* z = (float*)(flds + bwd_z_offset(L.fw_len, L.bw_len, L.bias_len)) + threadIdx.x;
+  float* z = (float*)(flds + bwd_z_offset(L.fw_len, L.bw_len, L.bias_len, (int)sizeof(S))) + threadIdx.x;
   float* gz = z + d * FBLOCK;
   float* dz = gz + d * FBLOCK;
-  copy16(sfw, fw + L.fw_off, L.fw_len * 2);
-  copy16(sbw, bw + L.bw_off, L.bw_len * 2);
+  copy16(sfw, fw + L.fw_off, L.fw_len * (int)sizeof(S));
+  copy16(sbw, bw + L.bw_off, L.bw_len * (int)sizeof(S));
   copy16(sb, bias + L.bias_off, L.bias_len * 4);
   __syncthreads();
-  const LayerLds W = layer_lds(sfw, sb, L, L.fw_off, L.bias_off);
-  const bf16x8* w3t = (const bf16x8*)sbw;                         // [2][2nb][32][2]
-  const bf16x8* w2t = (const bf16x8*)(sbw + L.nb * 2048);         // [2][4][32][2]
-  const bf16x8* w1t = (const bf16x8*)(sbw + L.nb * 2048 + 4096);  // [1][4][32][2]
+  const LayerLds<OP> W = layer_lds<OP>(sfw, sb, L, L.fw_off, L.bias_off);
+  const frag* w3t = (const frag*)sbw;                         // [2][2nb][32][2]
+  const frag* w2t = (const frag*)(sbw + L.nb * 2048);         // [2][4][32][2]
+  const frag* w1t = (const frag*)(sbw + L.nb * 2048 + 4096);  // [1][4][32][2]
   const double scale = a.loss[1];
   const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
   const int wave = blockIdx.x * (FBLOCK / 64) + (threadIdx.x >> 6);
@@ -685,20 +732,17 @@ __global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const F
 #pragma unroll
     for (int e = 0; e < FAB; ++e) za[e] = (e < na) ? z[L.a_idx[e] * FBLOCK] : 0.0f;
     f32x16 h1[2], h2[2], lg[NBM];
-    mlp_fwd<NBM>(za, na, nb, W, h1, h2, lg);
-    // BF16 operand tiles for the weight gradients, written as soon as they
+    mlp_fwd<NBM, OP>(za, na, nb, W, h1, h2, lg);
+    // operand tiles for the weight gradients, written as soon as they
     // exist; only the ReLU masks of h1, h2 stay live (invalid samples carry
     // zero deltas, so they add nothing)
-    unsigned short* base = a.scr + (size_t)t * a.srows * 32;
+    S* base = (S*)a.scr + (size_t)t * a.srows * 32;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const __bf16 x = (__bf16)((h == 0 && e < na) ? za[e] : 0.0f);
-      base[(8 * h + e) * 32 + s] = *(const unsigned short*)&x;
-    }
-    put_tile(base, 32, h1[0], s, h);
-    put_tile(base, 64, h1[1], s, h);
-    put_tile(base, 96, h2[0], s, h);
-    put_tile(base, 128, h2[1], s, h);
+    for (int e = 0; e < 8; ++e) base[(8 * h + e) * 32 + s] = OP::store((h == 0 && e < na) ? za[e] : 0.0f);
+    put_tile<OP>(base, 32, h1[0], s, h);
+    put_tile<OP>(base, 64, h1[1], s, h);
+    put_tile<OP>(base, 96, h2[0], s, h);
+    put_tile<OP>(base, 128, h2[1], s, h);
     unsigned m1[2] = {0u, 0u}, m2[2] = {0u, 0u};
 #pragma unroll
     for (int to = 0; to < 2; ++to)
@@ -729,7 +773,7 @@ __global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const F
 #pragma unroll
         for (int v = 0; v < 16; ++v) lg[jb][v] = lg[jb][v] * (dq[v] - sdot);  // dlogit
         dz[j * FBLOCK] = g_out * (float)FK * qb;
-        put_tile(base, 288 + 32 * jb, lg[jb], s, h);
+        put_tile<OP>(base, 288 + 32 * jb, lg[jb], s, h);
       }
     }
     // dh2 = W3^T dlogit, masked by relu'
@@ -739,30 +783,30 @@ __global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const F
       f32x16 acc = zero16();
 #pragma unroll
       for (int kk = 0; kk < 2 * NBM; ++kk)
-        if (kk < 2 * nb) acc = mfma(w3t[((to * 2 * nb + kk) * 32 + s) * 2 + h], to_b(lg[kk >> 1], kk & 1), acc);
+        if (kk < 2 * nb) acc = OP::mma(w3t[((to * 2 * nb + kk) * 32 + s) * 2 + h], to_b<OP>(lg[kk >> 1], kk & 1), acc);
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = ((m2[to] >> v) & 1u) ? acc[v] : 0.0f;
       d2[to] = acc;
     }
-    put_tile(base, 224, d2[0], s, h);
-    put_tile(base, 256, d2[1], s, h);
+    put_tile<OP>(base, 224, d2[0], s, h);
+    put_tile<OP>(base, 256, d2[1], s, h);
     // dh1 = W2^T dpre2, masked
     f32x16 d1[2];
 #pragma unroll
     for (int to = 0; to < 2; ++to) {
       f32x16 acc = zero16();
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], to_b(d2[kk >> 1], kk & 1), acc);
+      for (int kk = 0; kk < 4; ++kk) acc = OP::mma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], to_b<OP>(d2[kk >> 1], kk & 1), acc);
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = ((m1[to] >> v) & 1u) ? acc[v] : 0.0f;
       d1[to] = acc;
     }
-    put_tile(base, 160, d1[0], s, h);
-    put_tile(base, 192, d1[1], s, h);
+    put_tile<OP>(base, 160, d1[0], s, h);
+    put_tile<OP>(base, 192, d1[1], s, h);
     // dzA = W1^T dpre1: rows a = 4h + r in registers 0..3
     f32x16 d0 = zero16();
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) d0 = mfma(w1t[(kk * 32 + s) * 2 + h], to_b(d1[kk >> 1], kk & 1), d0);
+    for (int kk = 0; kk < 4; ++kk) d0 = OP::mma(w1t[(kk * 32 + s) * 2 + h], to_b<OP>(d1[kk >> 1], kk & 1), d0);
     float dza[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -787,24 +831,26 @@ __global__ __launch_bounds__(FBLOCK, (NBM <= 2 ? 2 : 1)) void k_flow_bwd(const F
 struct WgradArgs {
   int64_t n;
   int layer;
-  const unsigned short* scr;
+  const void* scr;  // operand tiles (OP::S elements)
   int srows;
   float* gpart;   // [grid][n_par] partials of this layer
 };
 
-__device__ __forceinline__ bf16x8 ld_frag(const unsigned short* base, int row, int kk, int h) {
-  return *(const bf16x8*)(base + row * 32 + 16 * kk + 8 * h);
+template <class OP>
+__device__ __forceinline__ typename OP::frag ld_frag(const typename OP::S* base, int row, int kk, int h) {
+  return *(const typename OP::frag*)(base + row * 32 + 16 * kk + 8 * h);
 }
 
-__device__ __forceinline__ float frag_sum(const bf16x8& x) {
+template <class OP>
+__device__ __forceinline__ float frag_sum(const typename OP::frag& x) {
   float s = 0.0f;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) s += (float)x[e];
+  for (int e = 0; e < 8; ++e) s += OP::get(x, e);
   return s;
 }
 
-template <int MT, int NT>
-__device__ __forceinline__ void wgrad_gemm(const unsigned short* scr, int srows, int64_t ntiles, int wave, int nwaves,
+template <int MT, int NT, class OP>
+__device__ __forceinline__ void wgrad_gemm(const typename OP::S* scr, int srows, int64_t ntiles, int wave, int nwaves,
                                            int arow0, int brow0, int mt, int nt, f32x16 (&acc)[MT][NT],
                                            float (&bsum)[MT]) {
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
@@ -815,21 +861,21 @@ __device__ __forceinline__ void wgrad_gemm(const unsigned short* scr, int srows,
     for (int nn = 0; nn < NT; ++nn) acc[m][nn] = zero16();
   }
   for (int64_t t = wave; t < ntiles; t += nwaves) {
-    const unsigned short* base = scr + (size_t)t * srows * 32;
+    const typename OP::S* base = scr + (size_t)t * srows * 32;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      bf16x8 bf[NT];
+      typename OP::frag bf[NT];
 #pragma unroll
       for (int nn = 0; nn < NT; ++nn)
-        if (nn < nt) bf[nn] = ld_frag(base, brow0 + 32 * nn + i, kk, h);
+        if (nn < nt) bf[nn] = ld_frag<OP>(base, brow0 + 32 * nn + i, kk, h);
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         if (m < mt) {
-          const bf16x8 af = ld_frag(base, arow0 + 32 * m + i, kk, h);
-          bsum[m] += frag_sum(af);
+          const typename OP::frag af = ld_frag<OP>(base, arow0 + 32 * m + i, kk, h);
+          bsum[m] += frag_sum<OP>(af);
 #pragma unroll
           for (int nn = 0; nn < NT; ++nn)
-            if (nn < nt) acc[m][nn] = mfma(af, bf[nn], acc[m][nn]);
+            if (nn < nt) acc[m][nn] = OP::mma(af, bf[nn], acc[m][nn]);
         }
       }
     }
@@ -859,8 +905,9 @@ __device__ __forceinline__ void in_wave_order(Fn&& f) {
   }
 }
 
-template <int NBM>
+template <int NBM, class OP>
 __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restrict__ Dp, WgradArgs a) {
+  const typename OP::S* scr = (const typename OP::S*)a.scr;
   extern __shared__ __align__(16) unsigned char flds[];
   const FlowLayerDesc& L = Dp->l[a.layer];
   float* blk = (float*)flds;  // the layer's parameter block
@@ -875,7 +922,7 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restric
   {  // dW3 [o][f], db3
     f32x16 acc[NBM][2];
     float bs[NBM];
-    wgrad_gemm<NBM, 2>(a.scr, a.srows, ntiles, wave, nwaves, 288, 96, nb, 2, acc, bs);
+    wgrad_gemm<NBM, 2, OP>(scr, a.srows, ntiles, wave, nwaves, 288, 96, nb, 2, acc, bs);
     in_wave_order([&] {
 #pragma unroll
       for (int m = 0; m < NBM; ++m)
@@ -890,7 +937,7 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restric
   {  // dW2 [f][f'], db2
     f32x16 acc[2][2];
     float bs[2];
-    wgrad_gemm<2, 2>(a.scr, a.srows, ntiles, wave, nwaves, 224, 32, 2, 2, acc, bs);
+    wgrad_gemm<2, 2, OP>(scr, a.srows, ntiles, wave, nwaves, 224, 32, 2, 2, acc, bs);
     in_wave_order([&] {
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
@@ -904,7 +951,7 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restric
   {  // dW1 [f][a], db1
     f32x16 acc[2][1];
     float bs[2];
-    wgrad_gemm<2, 1>(a.scr, a.srows, ntiles, wave, nwaves, 160, 0, 2, 1, acc, bs);
+    wgrad_gemm<2, 1, OP>(scr, a.srows, ntiles, wave, nwaves, 160, 0, 2, 1, acc, bs);
     in_wave_order([&] {
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
@@ -983,22 +1030,21 @@ __global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ 
   a.master[p] -= a.lr * mh / (sqrtf(vh) + a.eps);
 }
 
-// master FP32 weights -> permuted BF16 packs and FP32 bias pack
+// master FP32 weights -> permuted operand packs (OP::S) and FP32 bias pack
+template <class OP>
 __global__ __launch_bounds__(256) void k_flow_pack(const float* __restrict__ master, const int* __restrict__ fw_src,
                                                    int fw_total, const int* __restrict__ bw_src, int bw_total,
                                                    const int* __restrict__ b_src, int b_total,
-                                                   unsigned short* __restrict__ fw, unsigned short* __restrict__ bw,
+                                                   typename OP::S* __restrict__ fw, typename OP::S* __restrict__ bw,
                                                    float* __restrict__ bias) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k < fw_total) {
     const int s = fw_src[k];
-    const __bf16 x = (__bf16)(s >= 0 ? master[s] : 0.0f);
-    fw[k] = *(const unsigned short*)&x;
+    fw[k] = OP::store(s >= 0 ? master[s] : 0.0f);
   }
   if (k < bw_total) {
     const int s = bw_src[k];
-    const __bf16 x = (__bf16)(s >= 0 ? master[s] : 0.0f);
-    bw[k] = *(const unsigned short*)&x;
+    bw[k] = OP::store(s >= 0 ? master[s] : 0.0f);
   }
   if (k < b_total) bias[k] = master[b_src[k]];
 }
@@ -1019,8 +1065,9 @@ struct vgx_flow {
   float* m = nullptr;
   float* v = nullptr;
   float* grad = nullptr;
-  unsigned short* fw = nullptr;
-  unsigned short* bw = nullptr;
+  int f32ops = 0;               // 1: FP32-operand validation kernels (OpF32)
+  void* fw = nullptr;           // operand packs, sized for 4-byte elements
+  void* bw = nullptr;
   float* bias = nullptr;
   int* fw_src = nullptr;
   int* bw_src = nullptr;
@@ -1034,7 +1081,7 @@ struct vgx_flow {
   double* rsave = nullptr;      // [n]
   double* lqsave = nullptr;     // [n]
   float* dz[2] = {nullptr, nullptr};  // [d][n]
-  unsigned short* scr = nullptr;
+  void* scr = nullptr;          // operand tiles [tiles][srows][32] of OP::S
   float* gpart = nullptr;       // [n_par * grid_w]
   float* gtmp = nullptr;        // [GSPLIT][n_par]
   int grid_w = 0;
@@ -1149,25 +1196,35 @@ vgx_status build_desc(int dim, int L, FlowDesc& D, std::vector<int>& fws, std::v
   return VGX_OK;
 }
 
+int op_es(const vgx_flow* f) { return f->f32ops ? 4 : 2; }
+
 size_t bwd_lds(const vgx_flow* f, int l) {
   const FlowLayerDesc& Ld = f->D.l[l];
-  return bwd_z_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len) + sizeof(float) * 3 * (size_t)f->dim * FBLOCK;
+  return bwd_z_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len, op_es(f)) + sizeof(float) * 3 * (size_t)f->dim * FBLOCK;
 }
 
-size_t fwd_lds(const vgx_flow* f) {
-  return fwd_z_offset(f->D.fw_total, f->D.bias_total) + sizeof(float) * (size_t)f->dim * FWD_BLOCK;
+size_t fwd_lds_es(const vgx_flow* f, int es) {
+  return fwd_z_offset(f->D.fw_total, f->D.bias_total, es) + sizeof(float) * (size_t)f->dim * FWD_BLOCK;
 }
+
+size_t fwd_lds(const vgx_flow* f) { return fwd_lds_es(f, op_es(f)); }
 
 vgx_status pack(vgx_flow* f) {
   const int tot = f->D.fw_total > f->D.bw_total ? f->D.fw_total : f->D.bw_total;
-  hipLaunchKernelGGL(k_flow_pack, dim3((tot + 255) / 256), dim3(256), 0, f->stream, f->master, f->fw_src,
-                     f->D.fw_total, f->bw_src, f->D.bw_total, f->b_src, f->D.bias_total, f->fw, f->bw, f->bias);
+  if (f->f32ops)
+    hipLaunchKernelGGL(k_flow_pack<OpF32>, dim3((tot + 255) / 256), dim3(256), 0, f->stream, f->master, f->fw_src,
+                       f->D.fw_total, f->bw_src, f->D.bw_total, f->b_src, f->D.bias_total, (float*)f->fw,
+                       (float*)f->bw, f->bias);
+  else
+    hipLaunchKernelGGL(k_flow_pack<OpBF16>, dim3((tot + 255) / 256), dim3(256), 0, f->stream, f->master, f->fw_src,
+                       f->D.fw_total, f->bw_src, f->D.bw_total, f->b_src, f->D.bias_total, (unsigned short*)f->fw,
+                       (unsigned short*)f->bw, f->bias);
   VGX_HIP(hipGetLastError());
   return VGX_OK;
 }
 
 // Allow the dynamic LDS the kernels of this flow need (beyond 64 KB), once.
-template <int NB>
+template <int NB, class OP>
 vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr) {
   // never lower a limit another live flow may rely on
   static size_t cur_f = 0, cur_b = 0, cur_w = 0;
@@ -1177,12 +1234,22 @@ vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr) {
   cur_f = fwd;
   cur_b = bwd;
   cur_w = wgr;
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwd<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd));
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_wgrad<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wgr));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 0, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 1, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 2, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwd<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd));
+  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_wgrad<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wgr));
   return VGX_OK;
+}
+
+template <class OP>
+vgx_status set_lds_limits_nb(int nbm, size_t fwd, size_t bwd, size_t wgr) {
+  switch (nbm) {
+    case 1: return set_lds_limits<1, OP>(fwd, bwd, wgr);
+    case 2: return set_lds_limits<2, OP>(fwd, bwd, wgr);
+    case 4: return set_lds_limits<4, OP>(fwd, bwd, wgr);
+    default: return set_lds_limits<8, OP>(fwd, bwd, wgr);
+  }
 }
 
 vgx_status init_lds_limits(const vgx_flow* f) {
@@ -1193,12 +1260,8 @@ vgx_status init_lds_limits(const vgx_flow* f) {
     bwd = b > bwd ? b : bwd;
     wgr = (size_t)Ld.n_par * 4 > wgr ? (size_t)Ld.n_par * 4 : wgr;
   }
-  switch (f->nbm) {
-    case 1: return set_lds_limits<1>(fwd, bwd, wgr);
-    case 2: return set_lds_limits<2>(fwd, bwd, wgr);
-    case 4: return set_lds_limits<4>(fwd, bwd, wgr);
-    default: return set_lds_limits<8>(fwd, bwd, wgr);
-  }
+  return f->f32ops ? set_lds_limits_nb<OpF32>(f->nbm, fwd, bwd, wgr)
+                   : set_lds_limits_nb<OpBF16>(f->nbm, fwd, bwd, wgr);
 }
 
 int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
@@ -1210,17 +1273,23 @@ int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
   return (int)(g < 1 ? 1 : g);
 }
 
-template <int MODE>
-vgx_status launch_fwd(vgx_flow* f, int grid, const FwdArgs& a, hipStream_t st) {
+template <int MODE, class OP>
+vgx_status launch_fwd_op(vgx_flow* f, int grid, const FwdArgs& a, hipStream_t st) {
   const size_t lds = fwd_lds(f);
-#define L_(NB)                                                                                        \
-  case NB:                                                                                            \
-    hipLaunchKernelGGL((k_flow_fwd<NB, MODE>), dim3(grid), dim3(FWD_BLOCK), lds, st, f->d_desc, a, f->fw, f->bias); \
+  const typename OP::S* fw = (const typename OP::S*)f->fw;
+#define L_(NB)                                                                                                  \
+  case NB:                                                                                                      \
+    hipLaunchKernelGGL((k_flow_fwd<NB, MODE, OP>), dim3(grid), dim3(FWD_BLOCK), lds, st, f->d_desc, a, fw, f->bias); \
     break;
   switch (f->nbm) { L_(1) L_(2) L_(4) L_(8) default: set_error("flow: bad |B| bound"); return VGX_EINVAL; }
 #undef L_
   VGX_HIP(hipGetLastError());
   return VGX_OK;
+}
+
+template <int MODE>
+vgx_status launch_fwd(vgx_flow* f, int grid, const FwdArgs& a, hipStream_t st) {
+  return f->f32ops ? launch_fwd_op<MODE, OpF32>(f, grid, a, st) : launch_fwd_op<MODE, OpBF16>(f, grid, a, st);
 }
 
 vgx_status ensure_train(vgx_flow* f, int64_t n) {
@@ -1231,6 +1300,7 @@ vgx_status ensure_train(vgx_flow* f, int64_t n) {
   f->gpart = nullptr;
   f->cap_n = 0;
   const int64_t tiles = (n + 31) / 32;
+  const size_t es = (size_t)op_es(f);
   f->srows = 32 + 4 * FH + FK * f->nbm;
   f->grid_w = device_cus();
   VGX_TRY(dev_alloc((void**)&f->zsave, sizeof(float) * (size_t)f->L * f->dim * n));
@@ -1238,11 +1308,11 @@ vgx_status ensure_train(vgx_flow* f, int64_t n) {
   VGX_TRY(dev_alloc((void**)&f->lqsave, sizeof(double) * (size_t)n));
   VGX_TRY(dev_alloc((void**)&f->dz[0], sizeof(float) * (size_t)f->dim * n));
   VGX_TRY(dev_alloc((void**)&f->dz[1], sizeof(float) * (size_t)f->dim * n));
-  VGX_TRY(dev_alloc((void**)&f->scr, sizeof(unsigned short) * (size_t)tiles * f->srows * 32));
+  VGX_TRY(dev_alloc((void**)&f->scr, es * (size_t)tiles * f->srows * 32));
   VGX_TRY(dev_alloc((void**)&f->gpart, sizeof(float) * (size_t)f->n_par * f->grid_w));
   if (!f->gtmp) VGX_TRY(dev_alloc((void**)&f->gtmp, sizeof(float) * (size_t)f->n_par * GSPLIT));
   // rows 16..31 of the zA block are never written and must read as zero
-  VGX_HIP(hipMemsetAsync(f->scr, 0, sizeof(unsigned short) * (size_t)tiles * f->srows * 32, f->stream));
+  VGX_HIP(hipMemsetAsync(f->scr, 0, es * (size_t)tiles * f->srows * 32, f->stream));
   f->cap_n = n;
   return VGX_OK;
 }
@@ -1283,11 +1353,16 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     b.scr = f->scr;
     b.srows = f->srows;
     const size_t lds = bwd_lds(f, l);
-#define B_(NB)                                                                                        \
-  case NB:                                                                                            \
-    hipLaunchKernelGGL((k_flow_bwd<NB>), dim3(bgrid), dim3(FBLOCK), lds, f->stream, f->d_desc, b, f->fw, f->bw, f->bias); \
+#define B_(NB, OP)                                                                                        \
+  case NB:                                                                                                \
+    hipLaunchKernelGGL((k_flow_bwd<NB, OP>), dim3(bgrid), dim3(FBLOCK), lds, f->stream, f->d_desc, b,     \
+                       (const OP::S*)f->fw, (const OP::S*)f->bw, f->bias);                                \
     break;
-    switch (f->nbm) { B_(1) B_(2) B_(4) B_(8) default: return VGX_EINVAL; }
+    if (f->f32ops) {
+      switch (f->nbm) { B_(1, OpF32) B_(2, OpF32) B_(4, OpF32) B_(8, OpF32) default: return VGX_EINVAL; }
+    } else {
+      switch (f->nbm) { B_(1, OpBF16) B_(2, OpBF16) B_(4, OpBF16) B_(8, OpBF16) default: return VGX_EINVAL; }
+    }
 #undef B_
     VGX_HIP(hipGetLastError());
     WgradArgs w{};
@@ -1297,11 +1372,15 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     w.srows = f->srows;
     w.gpart = f->gpart + (size_t)Ld.p_off * wgrid;
     const size_t wl = (size_t)Ld.n_par * 4;
-#define W_(NB)                                                                                        \
+#define W_(NB, OP)                                                                                    \
   case NB:                                                                                            \
-    hipLaunchKernelGGL((k_flow_wgrad<NB>), dim3(wgrid), dim3(FBLOCK), wl, f->stream, f->d_desc, w); \
+    hipLaunchKernelGGL((k_flow_wgrad<NB, OP>), dim3(wgrid), dim3(FBLOCK), wl, f->stream, f->d_desc, w); \
     break;
-    switch (f->nbm) { W_(1) W_(2) W_(4) W_(8) default: return VGX_EINVAL; }
+    if (f->f32ops) {
+      switch (f->nbm) { W_(1, OpF32) W_(2, OpF32) W_(4, OpF32) W_(8, OpF32) default: return VGX_EINVAL; }
+    } else {
+      switch (f->nbm) { W_(1, OpBF16) W_(2, OpBF16) W_(4, OpBF16) W_(8, OpBF16) default: return VGX_EINVAL; }
+    }
 #undef W_
     VGX_HIP(hipGetLastError());
     cur ^= 1;
@@ -1416,8 +1495,8 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
     if ((s = dev_alloc((void**)&f->m, sizeof(float) * f->n_par)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->v, sizeof(float) * f->n_par)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->grad, sizeof(float) * f->n_par)) != VGX_OK) break;
-    if ((s = dev_alloc((void**)&f->fw, 2 * (size_t)f->D.fw_total)) != VGX_OK) break;
-    if ((s = dev_alloc((void**)&f->bw, 2 * (size_t)f->D.bw_total)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->fw, 4 * (size_t)f->D.fw_total)) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&f->bw, 4 * (size_t)f->D.bw_total)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->bias, 4 * (size_t)f->D.bias_total)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->fw_src, 4 * fws.size())) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->bw_src, 4 * bws.size())) != VGX_OK) break;
@@ -1445,6 +1524,30 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
   }
   if (s != VGX_OK) { flow_destroy(f); return s; }
   *out = f;
+  return VGX_OK;
+}
+
+extern "C" vgx_status flow_set_operands(vgx_flow* f, int32_t operands) {
+  VGX_CHECK(f, "flow_set_operands: null flow");
+  VGX_CHECK(operands == VGX_OPERANDS_BF16 || operands == VGX_OPERANDS_F32, "flow_set_operands: unknown mode %d",
+            operands);
+  const int want = operands == VGX_OPERANDS_F32 ? 1 : 0;
+  if (want == f->f32ops) return VGX_OK;
+  if (fwd_lds_es(f, want ? 4 : 2) > 160 * 1024) {
+    set_error("flow_set_operands: the FP32 weight packs of a %d-dimensional flow exceed the LDS", f->dim);
+    return VGX_EINVAL;
+  }
+  VGX_HIP(hipStreamSynchronize(f->stream));
+  // the training tiles change element size: reallocated on the next use
+  hipFree(f->zsave); hipFree(f->rsave); hipFree(f->lqsave); hipFree(f->dz[0]); hipFree(f->dz[1]); hipFree(f->scr);
+  hipFree(f->gpart);
+  f->zsave = nullptr; f->rsave = nullptr; f->lqsave = nullptr; f->dz[0] = f->dz[1] = nullptr; f->scr = nullptr;
+  f->gpart = nullptr;
+  f->cap_n = 0;
+  f->f32ops = want;
+  VGX_TRY(init_lds_limits(f));
+  VGX_TRY(pack(f));
+  VGX_HIP(hipStreamSynchronize(f->stream));
   return VGX_OK;
 }
 

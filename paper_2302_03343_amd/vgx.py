@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ERANGE", 5:
 GAUSS, GENZ_OSC, GENZ_PEAK, TTBAR, DRELLYAN, SINGLETOP = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 EXTRAP_ERROR, EXTRAP_FREEZE, EXTRAP_CONTINUE = 0, 1, 2
+OPERANDS_BF16, OPERANDS_F32 = 0, 1
 MAX_DIM, MAX_BINS = 12, 256
 
 
@@ -152,6 +153,7 @@ _optional("flow_train_step", _S, _vp, _i64, _vp, _vp, _f32, C.POINTER(_f64))
 _optional("flow_adam", _S, _vp, _vp, _f32)
 _optional("flow_get_params", _S, _vp, C.POINTER(_f32), _i64, C.POINTER(_i64))
 _optional("flow_set_params", _S, _vp, C.POINTER(_f32), _i64)
+_optional("flow_set_operands", _S, _vp, _i32)
 _optional("flow_destroy", None, _vp)
 
 EXPORTED = sorted(_c)
@@ -645,6 +647,11 @@ def flow_get_params(f, n_params):
 def flow_set_params(f, params):
     p = np.ascontiguousarray(params, dtype=np.float32)
     _check(_c["flow_set_params"](f, _hptr(p, _f32), p.size), "flow_set_params")
+
+
+def flow_set_operands(f, operands):
+    """OPERANDS_BF16 (the product path) or OPERANDS_F32 (validation mode)."""
+    _check(_c["flow_set_operands"](f, int(operands)), "flow_set_operands")
 
 
 def flow_destroy(f):

@@ -1,22 +1,29 @@
 """GPU coupling flow (MFMA, BF16 operands, FP32 accumulation) vs the oracle.
 
-The oracle evaluates the same network in FP64 with the kernel's BF16 weights
-(biases stay FP32 on both sides); the remaining difference is the BF16
-rounding of the activations that feed each matrix product (relative 2^-9).
-Error model (BF16 mode): each rounded activation carries a relative error
-<= 2^-9; through K = 64 terms a logit moves by ~sqrt(64) 2^-9 |W||h| ~ 1e-3,
-and log q sums ln(32 Q_b) over 2 L |B| / 2 transforms, a random walk of such
-errors.  Bars: median |d log q| <= 5e-3 and 99th percentile <= 3e-2, |d y|
-99th percentile <= 2e-3; the loss to 1e-2 relative; gradients to 5e-2 in
-relative L2 norm per weight tensor (BF16 deltas too) with overall cosine
-similarity > 0.995.  A bin decision flips where a sample lies within the
-activation error of a bin edge (density direction) or of a cumulative knot
-(sampling direction); there log q jumps, so the percentile bars are taken
-over samples whose oracle-side margin exceeds 2e-3, and >= 90% of all
-samples must meet |d log q| <= 2e-2 and |d y| <= 2e-3.  Output-layer
-weights are drawn with a scale that gives logits of O(1) spread, as in a
-flow part-way through training; much larger logits make log q so steep
-that the comparison (and g/q itself) is dominated by bin-edge effects.
+Error model (BF16 mode).  The kernels round every matrix-product operand
+(layer input, hidden activations, and in training the deltas that meet the
+weights) to BF16, 8 significant bits, and accumulate in FP32; the weights
+are BF16 on both sides.  The oracle evaluated with that operand rounding
+(oracle.flow's `operand` hook with flow_model.bf16_operand: FP64 values
+rounded to FP32, then to BF16) is the model of what the kernels compute;
+against the plain FP64 oracle it differs by ~1e-3 in ln q per transform
+and, where a sample lies within that error of a bin decision, by a whole
+bin (sample 11651 of the d = 3 sampling case below: 1.31 in ln q).
+
+The kernels and the model can still round an operand differently where
+its FP32 value lies within the accumulation error (at most 65 eps32 of the
+sum of its terms' magnitudes) of a BF16 rounding midpoint.  Simulated
+under the model (each operand moved by up to that bound before rounding,
+8 draws of 20000 samples at d = 3 and 8, before any GPU run), such ties
+change ln q by at most 1.3e-2 and y by at most 2.9e-3 on samples farther
+than 1e-3 from every decision (the model's own), the gradient by at most
+3.7e-3 of a parameter tensor's L2 norm, and leave most samples untouched.
+Bars, against the model: for every sample farther than 1e-3 from every
+decision, |d ln q| <= 5e-2 and |d y| <= 1e-2, and the median sample within
+1e-4 (no tie: FP32 agreement); every parameter tensor's gradient (none
+skipped) within 1e-2 in relative L2 norm, the loss within 1e-3.  The FP32
+operand mode (test_gpu_flow_f32.py) checks the same kernels against the
+FP64 oracle at 1e-5 per sample and per gradient element.
 """
 import math
 
@@ -28,80 +35,24 @@ from oracle.integrands import gauss, gauss_integral
 from oracle.philox import sample_uniforms
 from synth import he_init_segments
 
+from flow_model import H, K, L, bf16_operand, margins, random_theta, weights_bf16
+
 pytestmark = pytest.mark.gpu
 
-L, K, H = 4, 32, 64
+MODEL_SAFE = 1e-3   # distance from every decision (model's own) for per-sample bars
+BAR_LQ, BAR_Y, BAR_MEDIAN = 5e-2, 1e-2, 1e-4
+BAR_SEG, BAR_LOSS = 1e-2, 1e-3
 
 
-def bf16(a):
-    a = np.ascontiguousarray(a, dtype=np.float32)
-    u = a.view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
-
-
-def weights_bf16(theta, dim):
-    """Round the W segments (not the biases) to BF16, as the kernels do."""
-    th = np.array(theta, dtype=np.float32, copy=True)
-    off = 0
-    for sh in of.layer_shapes(dim, L, K, H):
-        sz = sh["sizes"]
-        for k, size in enumerate(sz):
-            if k in (0, 2, 4):
-                th[off:off + size] = bf16(th[off:off + size])
-            off += size
-    return th.astype(np.float64)
-
-
-def random_theta(dim, seed, out_scale=0.1):
-    rng = np.random.default_rng(seed)
-    th = he_init_segments(of.init_segments(dim, L, K, H), seed)
-    off = 0
-    for sh in of.layer_shapes(dim, L, K, H):
-        sz = sh["sizes"]
-        o3 = off + sum(sz[:4])
-        th[o3:o3 + sz[4] + sz[5]] = rng.normal(0, out_scale, sz[4] + sz[5]).astype(np.float32)
-        # non-zero hidden biases exercise the bias path
-        th[off + sz[0]:off + sz[0] + sz[1]] = rng.normal(0, 0.1, sz[1]).astype(np.float32)
-        off += sum(sz)
-    return th
-
-
-def margins(theta, pts, dim, direction):
-    """Oracle-side distance of every sample to the nearest decision boundary
-    over all layers (bin edges in z for the density direction, cumulative
-    knots for the sampling direction)."""
-    layers = of.unpack(theta, dim, L, K, H)
-    z = np.array(pts, dtype=np.float64, copy=True)
-    n = z.shape[0]
-    marg = np.full(n, np.inf)
-    seq = layers if direction == "density" else list(reversed(layers))
-    for p in seq:
-        A, B = p["A"], p["B"]
-        Q = of._mlp(p, z[:, A], K)["Q"]
-        cum = np.concatenate([np.zeros((n, len(B), 1)), np.cumsum(Q, axis=2)], axis=2)
-        for jb, j in enumerate(B):
-            if direction == "density":
-                t = K * z[:, j]
-                marg = np.minimum(marg, np.abs(t - np.round(t)) / K)
-                b = np.minimum(np.floor(t).astype(int), K - 1)
-                z[:, j] = cum[np.arange(n), jb, b] + (t - b) * Q[np.arange(n), jb, b]
-            else:
-                v = z[:, j]
-                marg = np.minimum(marg, np.min(np.abs(cum[:, jb, 1:K] - v[:, None]), axis=1))
-                b = np.minimum(np.sum(cum[:, jb, 1:K] <= v[:, None], axis=1), K - 1)
-                z[:, j] = (b + (v - cum[np.arange(n), jb, b]) / Q[np.arange(n), jb, b]) / K
-    return marg
-
-
-def check_bars(dl, dy, safe):
-    print(f"  |dlogq| median {np.median(dl[safe]):.2e} p99 {np.percentile(dl[safe], 99):.2e} "
-          f"max {dl[safe].max():.2e}; |dy| p99 {np.percentile(dy[safe], 99):.2e}; safe frac {safe.mean():.2f}")
-    assert safe.mean() > 0.05  # d = 8: 16 bin decisions per sample
-    assert np.median(dl[safe]) <= 5e-3
-    assert np.percentile(dl[safe], 99) <= 3e-2
-    assert np.percentile(dy[safe], 99) <= 2e-3
-    assert np.mean((dl <= 2e-2) & (dy <= 2e-3)) >= 0.9
+def check_against_model(dl, dy, safe, dl64):
+    print(f"  vs BF16 model, samples >= {MODEL_SAFE:.0e} from decisions ({safe.mean():.3f}): |dlogq| max "
+          f"{dl[safe].max():.2e} p99 {np.percentile(dl[safe], 99):.2e} median {np.median(dl[safe]):.2e}; |dy| max "
+          f"{dy[safe].max():.2e}; vs FP64 (all samples): |dlogq| median {np.median(dl64):.2e} p99 "
+          f"{np.percentile(dl64, 99):.2e} max {dl64.max():.2e}", flush=True)
+    assert safe.mean() > 0.2
+    assert dl[safe].max() <= BAR_LQ
+    assert dy[safe].max() <= BAR_Y
+    assert np.median(dl[safe]) <= BAR_MEDIAN
 
 
 def make_flow(vgx, dim, theta):
@@ -147,14 +98,22 @@ def test_sampling_direction_matches_oracle(vgx, dim):
         y = torch.empty((dim, n), dtype=torch.float64, device="cuda")
         lq = torch.empty(n, dtype=torch.float64, device="cuda")
         vgx.flow_sample(f, n, 7, 3, 2, y, lq)
-        u = sample_uniforms(7, 3 | (1 << 23), 2, np.arange(n, dtype=np.uint64), dim)
-        yr, lqr = of.sample(thb, u, dim, L, K, H)
-        dy = np.max(np.abs(y.cpu().numpy().T - yr), axis=1)
-        dl = np.abs(lq.cpu().numpy() - lqr)
-        m = margins(thb, u, dim, "sampling")
-        check_bars(dl, dy, m > 2e-3)
+        y, lq = y.cpu().numpy().T, lq.cpu().numpy()
     finally:
         vgx.flow_destroy(f)
+    u = sample_uniforms(7, 3 | (1 << 23), 2, np.arange(n, dtype=np.uint64), dim)
+    ym, lqm = of.sample(thb, u, dim, L, K, H, operand=bf16_operand())
+    _, lq64 = of.sample(thb, u, dim, L, K, H)
+    safe = margins(thb, u, dim, "sampling", operand=bf16_operand()) > MODEL_SAFE
+    check_against_model(np.abs(lq - lqm), np.max(np.abs(y - ym), axis=1), safe, np.abs(lq - lq64))
+    if dim == 3:
+        # the sample that differs from FP64 by a whole bin: layer 3 puts z_0 in
+        # bin 6 (Q = 0.010), whose cumulative knot moves by 1.1e-3 under BF16
+        # operands; dividing by K Q moves z_0 by 3.2e-3, across layer 1's knot
+        # (2.6e-3 away in FP64): bin 5 (Q = 0.084) for bin 6 (Q = 0.022)
+        i = 11651
+        assert abs(lqm[i] - lq64[i] - math.log(0.0836 / 0.0224)) < 2e-2
+        assert abs(lq[i] - lqm[i]) <= BAR_LQ and abs(lq[i] - lq64[i]) > 1.0
 
 
 @pytest.mark.parametrize("dim", [3, 8])
@@ -172,10 +131,11 @@ def test_density_direction_matches_oracle_and_inverts_sampling(vgx, dim):
         u = torch.empty((dim, n), dtype=torch.float64, device="cuda")
         lq = torch.empty(n, dtype=torch.float64, device="cuda")
         vgx.flow_density(f, yt, lq, u=u)
-        ur, lqr = of.density(thb, yy, dim, L, K, H)
-        du = np.max(np.abs(u.cpu().numpy().T - ur), axis=1)
-        dl = np.abs(lq.cpu().numpy() - lqr)
-        check_bars(dl, du, margins(thb, yy, dim, "density") > 2e-3)
+        um, lqm = of.density(thb, yy, dim, L, K, H, operand=bf16_operand())
+        _, lq64 = of.density(thb, yy, dim, L, K, H)
+        safe = margins(thb, yy, dim, "density", operand=bf16_operand()) > MODEL_SAFE
+        check_against_model(np.abs(lq.cpu().numpy() - lqm), np.max(np.abs(u.cpu().numpy().T - um), axis=1), safe,
+                            np.abs(lq.cpu().numpy() - lq64))
         # GPU self-consistency: density(sample(u)) returns u and the same log q
         y2 = torch.empty((dim, n), dtype=torch.float64, device="cuda")
         lq2 = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -189,6 +149,26 @@ def test_density_direction_matches_oracle_and_inverts_sampling(vgx, dim):
         assert np.mean((back < 1e-4) & (same < 1e-4)) > 0.99
     finally:
         vgx.flow_destroy(f)
+
+
+def check_gradient_against_model(grad, loss, thb, yy, g, dim):
+    lm, gm, _ = of.loss_and_grad(thb, yy, g, dim, L, K, H, operand=bf16_operand())
+    l64, g64, _ = of.loss_and_grad(thb, yy, g, dim, L, K, H)
+    grad = grad.astype(np.float64)
+    worst, worst64 = 0.0, 0.0
+    off = 0
+    for li, sh in enumerate(of.layer_shapes(dim, L, K, H)):
+        for k, size in enumerate(sh["sizes"]):
+            a, b, c = grad[off:off + size], gm[off:off + size], g64[off:off + size]
+            e = np.linalg.norm(a - b) / np.linalg.norm(b)
+            worst = max(worst, e)
+            worst64 = max(worst64, np.linalg.norm(a - c) / np.linalg.norm(c))
+            assert e <= BAR_SEG, f"layer {li} tensor {k}: relative L2 {e:.2e}"
+            off += size
+    cos64 = float(np.dot(grad, g64) / (np.linalg.norm(grad) * np.linalg.norm(g64)))
+    print(f"  vs BF16 model: worst tensor relative L2 {worst:.2e}, loss rel {abs(loss - lm) / lm:.2e}; vs FP64: worst "
+          f"tensor {worst64:.2e}, cosine {cos64:.7f}, loss rel {abs(loss - l64) / l64:.2e}", flush=True)
+    assert loss == pytest.approx(lm, rel=BAR_LOSS)
 
 
 @pytest.mark.parametrize("dim", [3, 8])
@@ -205,20 +185,9 @@ def test_loss_and_gradient_match_oracle(vgx, dim):
         g = gauss(yy, 0.5, 0.25) + 0.05
         P = vgx.flow_num_params(dim, L, K, H)
         loss, grad = vgx.flow_loss_grad(f, torch.tensor(yy.T.copy(), device="cuda"), torch.tensor(g, device="cuda"), P)
-        lr, gr, _ = of.loss_and_grad(thb, yy, g, dim, L, K, H)
-        assert loss == pytest.approx(lr, rel=1e-2)
-        cos = float(np.dot(grad, gr) / (np.linalg.norm(grad) * np.linalg.norm(gr)))
-        assert cos > 0.995
-        off = 0
-        for sh in of.layer_shapes(dim, L, K, H):
-            for k, size in enumerate(sh["sizes"]):
-                a, b = grad[off:off + size].astype(np.float64), gr[off:off + size]
-                nb = np.linalg.norm(b)
-                if nb > 1e-3 * np.linalg.norm(gr):
-                    assert np.linalg.norm(a - b) <= 5e-2 * nb, f"segment {k} at {off}"
-                off += size
     finally:
         vgx.flow_destroy(f)
+    check_gradient_against_model(grad, loss, thb, yy, g, dim)
 
 
 def test_adam_matches_oracle(vgx):
@@ -320,12 +289,9 @@ def test_full_batch_gradient_matches_oracle(vgx):
         g = gauss(yy, 0.5, 0.3) + 0.05
         P = vgx.flow_num_params(dim, L, K, H)
         loss, grad = vgx.flow_loss_grad(f, torch.tensor(yy.T.copy(), device="cuda"), torch.tensor(g, device="cuda"), P)
-        lr, gr, _ = of.loss_and_grad(thb, yy, g, dim, L, K, H)
-        assert loss == pytest.approx(lr, rel=1e-2)
-        cos = float(np.dot(grad, gr) / (np.linalg.norm(grad) * np.linalg.norm(gr)))
-        assert cos > 0.995
     finally:
         vgx.flow_destroy(f)
+    check_gradient_against_model(grad, loss, thb, yy, g, dim)
 
 
 def test_training_is_bit_reproducible(vgx):

@@ -131,3 +131,32 @@ def test_training_reduces_variance():
     w0 = f(u)
     assert w.var() < 0.5 * w0.var()
     assert Lv < 0.7 * first
+
+
+def test_gradient_magnitudes_bound_the_per_sample_terms():
+    """The magnitude of each gradient element (the gradient formula on
+    absolute values) bounds the sum over samples of |per-sample gradient|,
+    which bounds |gradient|.  The loss is sum_s g_s^2 q_s^-1 / (n mean g^2)
+    with mean g^2 fixed by the batch, so sample s's share of the gradient
+    is g_s^2 / (n mean g^2) times the gradient of the one-sample loss q_s^-1."""
+    dim, L, K, H = 3, 4, 8, 8
+    th = random_theta(dim, L, K, H, seed=12, out_scale=0.8)
+    rng = np.random.default_rng(6)
+    y = rng.uniform(size=(24, dim))
+    g = gauss(y, 0.5, 0.2) + 0.1
+    _, grad, _, mag = flow.loss_and_grad(th, y, g, dim, L, K, H, magnitudes=True)
+    _, grad0, _ = flow.loss_and_grad(th, y, g, dim, L, K, H)
+    assert np.array_equal(grad, grad0)
+    m2 = np.mean(g ** 2)
+    per = np.zeros_like(grad)
+    for s in range(len(y)):
+        _, gs, _ = flow.loss_and_grad(th, y[s:s + 1], g[s:s + 1], dim, L, K, H)
+        per += np.abs(gs) * g[s] ** 2 / (len(y) * m2)
+    assert np.all(per <= mag * (1 + 1e-12) + 1e-300)
+    assert np.all(np.abs(grad) <= per * (1 + 1e-12) + 1e-300)
+    # the magnitude is not a loose multiple of the gradient: some elements
+    # (no cancellation) meet it, and it is finite and non-zero where the
+    # gradient is
+    nz = np.abs(grad) > 0
+    assert np.all(mag[nz] > 0) and np.all(np.isfinite(mag))
+    assert np.max(np.abs(grad[nz]) / mag[nz]) > 0.99
