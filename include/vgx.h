@@ -395,6 +395,23 @@ vgx_status rambo_generate(int32_t n_part, const double* masses, double sqrt_s, u
 vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
                     uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used, void* stream);
 
+/* Allocation-free unweighting, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the operation, arguments, results and errors of
+ * unweight(), with its scratch (block maxima, block counts, keep masks) in
+ * a fixed device array of VGX_UNWEIGHT_STATIC_BYTES that the library holds
+ * on every GPU it runs on until the process ends; no allocation, no free.
+ * n is limited to VGX_UNWEIGHT_NOALLOC_MAX events (one keep bit per event
+ * and 8 bytes per 4096 events must fit): VGX_EINVAL beyond, nothing
+ * launched.  All calls on one GPU share its array and leave their contents
+ * in it: calls that overlap in time on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  Sync (a 16-byte read-back). */
+#define VGX_UNWEIGHT_STATIC_BYTES (8 << 20)
+#define VGX_UNWEIGHT_NOALLOC_MAX 65945600LL
+vgx_status unweight_noalloc(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
+                            uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used,
+                            void* stream);
+
 /* Asynchronous LHE 3.0 export (thesis MadFlow chapter, unweighted event
  * exporter: events written as Les Houches Event records by a CPU thread
  * separate from the device work).  A writer owns a file and one thread;

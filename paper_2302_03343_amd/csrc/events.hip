@@ -29,6 +29,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 namespace vgx {
 
 constexpr int RB_BLOCK = 256;
@@ -388,60 +390,155 @@ extern "C" vgx_status rambo_generate(int32_t n_part, const double* masses, doubl
   return VGX_OK;
 }
 
-extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
-                               uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used,
-                               void* stream) {
-  VGX_CHECK(n >= 0, "unweight: n < 0");
-  VGX_CHECK(n_kept, "unweight: null n_kept");
-  VGX_CHECK(stream_id < (1u << 24), "unweight: stream_id must be < 2^24");
-  VGX_CHECK(!(w_max < 0.0) && !isnan(w_max), "unweight: w_max must be >= 0 (0: the sample's maximum)");
+namespace {
+
+// Scratch of one unweighting call: the max's bit pattern and the kept count,
+// nb + 1 block counts (scanned in place), the max search's block maxima,
+// nb x UW_MASKS keep masks (one bit per event).  Every word is written
+// before it is read, so nothing needs clearing; the bits are written by
+// k_uw_max_final when the maximum is searched and not read otherwise.
+size_t uw_scratch_bytes(int64_t nb, int grid) {
+  return sizeof(unsigned long long) * (2 + (size_t)nb * UW_MASKS) + sizeof(int64_t) * (size_t)(nb + 1) +
+         sizeof(double) * (size_t)grid;
+}
+
+struct UwPlan {
+  int64_t nb;
+  int grid;
+};
+
+vgx_status uw_check(int64_t n, const double* w_dev, double w_max, uint32_t stream_id, int64_t* idx_dev,
+                    int64_t* n_kept, double* w_max_used, const char* who, UwPlan* plan, bool* done) {
+  VGX_CHECK(n >= 0, "%s: n < 0", who);
+  VGX_CHECK(n_kept, "%s: null n_kept", who);
+  VGX_CHECK(stream_id < (1u << 24), "%s: stream_id must be < 2^24", who);
+  VGX_CHECK(!(w_max < 0.0) && !isnan(w_max), "%s: w_max must be >= 0 (0: the sample's maximum)", who);
   *n_kept = 0;
+  *done = false;
   if (n == 0) {
     if (w_max_used) *w_max_used = w_max;
+    *done = true;
     return VGX_OK;
   }
-  VGX_CHECK(w_dev && idx_dev, "unweight: null device pointer");
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t nb = (n + UW_CHUNK - 1) / UW_CHUNK;
-  VGX_CHECK(nb < (int64_t)1 << 31, "unweight: n too large");
+  VGX_CHECK(w_dev && idx_dev, "%s: null device pointer", who);
+  plan->nb = (n + UW_CHUNK - 1) / UW_CHUNK;
+  VGX_CHECK(plan->nb < (int64_t)1 << 31, "%s: n too large", who);
   const int64_t want = (n + UW_BLOCK - 1) / UW_BLOCK;
-  const int grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
-  // scratch: the max's bit pattern and the kept count, nb + 1 counts, the
-  // grid's block maxima, nb x UW_MASKS keep masks (stream-ordered).  The
-  // bits are written by k_uw_max_final when the maximum is searched and
-  // not read otherwise.
-  void* scratch = nullptr;
-  VGX_HIP(hipMallocAsync(&scratch, sizeof(unsigned long long) * (2 + nb * UW_MASKS) + sizeof(int64_t) * (nb + 1) +
-                                       sizeof(double) * grid, st));
-  unsigned long long* bits = (unsigned long long*)scratch;
+  plan->grid = (int)(want < (int64_t)device_cus() * 8 ? want : (int64_t)device_cus() * 8);
+  return VGX_OK;
+}
+
+// Enqueue the unweighting kernels on buf (uw_scratch_bytes) and the
+// read-back of the max's bits and the kept count into hb.
+hipError_t uw_enqueue(const UwPlan& p, int64_t n, const double* w_dev, double w_max, uint64_t seed,
+                      uint32_t stream_id, uint32_t iteration, int64_t* idx_dev, void* buf, hipStream_t st,
+                      unsigned long long (&hb)[2]) {
+  unsigned long long* bits = (unsigned long long*)buf;
   int64_t* total_dev = (int64_t*)(bits + 1);
   int64_t* counts = total_dev + 1;
-  double* part = (double*)(counts + nb + 1);
-  unsigned long long* masks = (unsigned long long*)(part + grid);
+  double* part = (double*)(counts + p.nb + 1);
+  unsigned long long* masks = (unsigned long long*)(part + p.grid);
   UwArgs a{n, w_max, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id, iteration};
-  hipError_t e = hipSuccess;
   if (!(w_max > 0.0)) {
-    hipLaunchKernelGGL(k_uw_max, dim3(grid), dim3(UW_BLOCK), 0, st, n, w_dev, part);
-    hipLaunchKernelGGL(k_uw_max_final, dim3(1), dim3(UW_FINAL), 0, st, grid, part, bits);
-    e = hipGetLastError();
+    hipLaunchKernelGGL(k_uw_max, dim3(p.grid), dim3(UW_BLOCK), 0, st, n, w_dev, part);
+    hipLaunchKernelGGL(k_uw_max_final, dim3(1), dim3(UW_FINAL), 0, st, p.grid, part, bits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_uw_count, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts, masks);
-    hipLaunchKernelGGL(k_uw_scan, dim3(1), dim3(1024), 0, st, nb, counts, total_dev);
-    hipLaunchKernelGGL(k_uw_scatter, dim3((unsigned)nb), dim3(UW_BLOCK), 0, st, n, masks, counts, idx_dev);
-    e = hipGetLastError();
-  }
-  unsigned long long hb[2] = {0, 0};  // the max's bits, the kept count
-  if (e == hipSuccess) e = hipMemcpyAsync(hb, bits, sizeof(hb), hipMemcpyDeviceToHost, st);
-  hipError_t ef = hipFreeAsync(scratch, st);
-  if (e == hipSuccess) e = ef;
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "unweight", __FILE__, __LINE__);
+  hipLaunchKernelGGL(k_uw_count, dim3((unsigned)p.nb), dim3(UW_BLOCK), 0, st, a, w_dev, bits, counts, masks);
+  hipLaunchKernelGGL(k_uw_scan, dim3(1), dim3(1024), 0, st, p.nb, counts, total_dev);
+  hipLaunchKernelGGL(k_uw_scatter, dim3((unsigned)p.nb), dim3(UW_BLOCK), 0, st, n, masks, counts, idx_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(hb, bits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+}
+
+void uw_results(const unsigned long long (&hb)[2], double w_max, int64_t* n_kept, double* w_max_used) {
   *n_kept = (int64_t)hb[1];
   if (w_max_used) {
     double wm;
     memcpy(&wm, &hb[0], sizeof(wm));
     *w_max_used = w_max > 0.0 ? w_max : wm;
   }
+}
+
+}  // namespace
+
+extern "C" vgx_status unweight(int64_t n, const double* w_dev, double w_max, uint64_t seed, uint32_t stream_id,
+                               uint32_t iteration, int64_t* idx_dev, int64_t* n_kept, double* w_max_used,
+                               void* stream) {
+  UwPlan p{};
+  bool done = false;
+  VGX_TRY(uw_check(n, w_dev, w_max, stream_id, idx_dev, n_kept, w_max_used, "unweight", &p, &done));
+  if (done) return VGX_OK;
+  hipStream_t st = (hipStream_t)stream;
+  void* buf = nullptr;  // stream-ordered
+  VGX_HIP(hipMallocAsync(&buf, uw_scratch_bytes(p.nb, p.grid), st));
+  unsigned long long hb[2] = {0, 0};  // the max's bits, the kept count
+  hipError_t e = uw_enqueue(p, n, w_dev, w_max, seed, stream_id, iteration, idx_dev, buf, st, hb);
+  hipError_t ef = hipFreeAsync(buf, st);
+  if (e == hipSuccess) e = ef;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "unweight", __FILE__, __LINE__);
+  uw_results(hb, w_max, n_kept, w_max_used);
+  return VGX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free unweighting: the same kernels on a fixed device array.
+// ---------------------------------------------------------------------------
+// One copy per GPU, held until the process ends.  In host code the name is
+// a host-side stand-in, not a device address: host code uses only the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[VGX_UNWEIGHT_STATIC_BYTES];
+
+namespace {
+
+constexpr int UW_MAX_DEVICES = 64;
+std::mutex g_uw_mu;
+void* g_uw_scratch[UW_MAX_DEVICES] = {};
+
+// The current device's address of the array, looked up once per device.
+vgx_status uw_static_scratch(void** out) {
+  int dev = 0;
+  VGX_HIP(hipGetDevice(&dev));
+  VGX_CHECK(dev >= 0 && dev < UW_MAX_DEVICES, "unweight_noalloc: device %d beyond %d", dev, UW_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_uw_mu);
+  if (!g_uw_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      set_error("unweight_noalloc: hipGetSymbolAddress of the scratch array failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return VGX_EDEVICE;
+    }
+    g_uw_scratch[dev] = p;
+  }
+  *out = g_uw_scratch[dev];
+  return VGX_OK;
+}
+
+}  // namespace
+
+extern "C" vgx_status unweight_noalloc(int64_t n, const double* w_dev, double w_max, uint64_t seed,
+                                       uint32_t stream_id, uint32_t iteration, int64_t* idx_dev, int64_t* n_kept,
+                                       double* w_max_used, void* stream) {
+  UwPlan p{};
+  bool done = false;
+  VGX_TRY(uw_check(n, w_dev, w_max, stream_id, idx_dev, n_kept, w_max_used, "unweight_noalloc", &p, &done));
+  if (done) return VGX_OK;
+  VGX_CHECK(n <= VGX_UNWEIGHT_NOALLOC_MAX && uw_scratch_bytes(p.nb, p.grid) <= VGX_UNWEIGHT_STATIC_BYTES,
+            "unweight_noalloc: n = %lld needs %zu bytes of scratch, beyond the fixed %d (at most %lld events)",
+            (long long)n, uw_scratch_bytes(p.nb, p.grid), VGX_UNWEIGHT_STATIC_BYTES,
+            (long long)VGX_UNWEIGHT_NOALLOC_MAX);
+  void* buf = nullptr;
+  VGX_TRY(uw_static_scratch(&buf));
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long hb[2] = {0, 0};
+  hipError_t e = uw_enqueue(p, n, w_dev, w_max, seed, stream_id, iteration, idx_dev, buf, st, hb);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "unweight_noalloc", __FILE__, __LINE__);
+  uw_results(hb, w_max, n_kept, w_max_used);
   return VGX_OK;
 }

@@ -104,6 +104,7 @@ for _name, _res, _args in [
     ("pdf_destroy", None, [_vp]),
     ("rambo_generate", _S, [_i32, C.POINTER(_f64), _f64, _u64, _u32, _u32, _i64, _i64, _vp, _vp, _vp]),
     ("unweight", _S, [_i64, _vp, _f64, _u64, _u32, _u32, _vp, C.POINTER(_i64), C.POINTER(_f64), _vp]),
+    ("unweight_noalloc", _S, [_i64, _vp, _f64, _u64, _u32, _u32, _vp, C.POINTER(_i64), C.POINTER(_f64), _vp]),
     ("lhe_open", _S, [C.c_char_p, C.POINTER(LheInit), C.POINTER(_vp)]),
     ("lhe_write_events", _S, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_f64), C.POINTER(LheEventInfo),
                               _i64, _vp, _vp, _i64, _vp]),
@@ -415,6 +416,21 @@ def unweight(w, seed, stream_id, iteration, idx, w_max=0.0, stream=None):
     _check(_c["unweight"](n, _dptr(w, torch.float64, n, "w"), float(w_max), int(seed), int(stream_id),
                           int(iteration), _dptr(idx, torch.int64, n, "idx"), C.byref(k), C.byref(wm),
                           _stream(stream)), "unweight")
+    return int(k.value), float(wm.value)
+
+
+UNWEIGHT_NOALLOC_MAX = 65945600
+
+
+def unweight_noalloc(w, seed, stream_id, iteration, idx, w_max=0.0, stream=None):
+    """unweight() without any device allocation (fixed scratch array); n up to
+    UNWEIGHT_NOALLOC_MAX."""
+    import torch
+    n = w.numel()
+    k, wm = _i64(), _f64()
+    _check(_c["unweight_noalloc"](n, _dptr(w, torch.float64, n, "w"), float(w_max), int(seed), int(stream_id),
+                                  int(iteration), _dptr(idx, torch.int64, n, "idx"), C.byref(k), C.byref(wm),
+                                  _stream(stream)), "unweight_noalloc")
     return int(k.value), float(wm.value)
 
 
