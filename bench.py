@@ -31,11 +31,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "events/s + time to 1e-4 rel. error: plain VEGAS vs flow sampler, 1 MI355X"
 
-# Algorithmic FP32 flops per t tbar event of the fused kernel: per x value
-# the 4x4 Hermite stencil for 11 flavours (16 weights + 176 FMA = 368 flops)
-# plus ~32 flops of cell/basis setup, twice (x1, x2), plus ~60 flops of
-# kinematics, matrix elements and luminosities.
+# Algorithmic FP32 flops per t tbar event of the fused kernel as built: per x
+# value the tensor-product weights of the 4x4 Hermite stencil (16 products)
+# shared by the 11 flavours, whose values are 11 x 16 FMA (352 flops), plus
+# ~32 flops of cell and basis setup, twice (x1, x2), plus ~60 flops of
+# kinematics, matrix elements and luminosities: 860.  Counting each
+# flavour's 2-d stencil separately (four 1-d Hermites in x and one in Q^2,
+# with slopes, ~50 flops a flavour) gives the ~1.3k of a per-flavour
+# evaluation; the line reports both, the figure as built first.
 FLOPS_PER_EVENT_F32 = 2 * (368 + 32) + 60
+FLOPS_PER_EVENT_PER_FLAVOUR_COUNT = 1300
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector (packed) peak
 PEAK_FP32_UNPACKED = 78.6e12
 
@@ -118,6 +123,8 @@ def parse():
     ap.add_argument("--events", type=int, default=None, help="events per iteration (default 1e7)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-flow", action="store_true", help="skip the flow comparison")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="skip the compact figures of the other configurations (C0, C1, C3, C4 d = 8)")
     ap.add_argument("--extras", action="store_true",
                     help="also measure the other workloads (PDF interpolation alone, plain Gaussian VEGAS, "
                          "batched integrals) as extra fields")
@@ -130,33 +137,63 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(grid, n_sample, chunk=250_000):
-    """The FP64 oracle on the first n_sample events of iteration 0 (uniform
-    grid), in chunks of consecutive sample indices, timed on the host.
-    Returns (events/s, seconds).  Library thread pools are held to one
-    thread, so the figure is for one core."""
-    from oracle import vegas as ov
-    from synth import C2
-    from threadpoolctl import threadpool_limits
-    e = ov.uniform_grid(3, C2["n_bins"])
-    with threadpool_limits(limits=1):
-        return _cpu_baseline_run(grid, n_sample, chunk, e)
-
-
-def _cpu_baseline_run(grid, n_sample, chunk, e):
+def _oracle_weights(grid, first, count, chunk):
+    """FP64 oracle weights f J of events first .. first+count-1 of iteration
+    0 on the uniform grid (the headline's counters), in chunks."""
     import numpy as np
     from oracle import ttbar as ot, vegas as ov
     from oracle.philox import sample_uniforms
     from synth import C2
-    t0 = time.perf_counter()
-    for s0 in range(0, n_sample, chunk):
-        idx_s = np.arange(s0, min(s0 + chunk, n_sample), dtype=np.uint64)
+    e = ov.uniform_grid(3, C2["n_bins"])
+    out = []
+    for s0 in range(first, first + count, chunk):
+        idx_s = np.arange(s0, min(s0 + chunk, first + count), dtype=np.uint64)
         u = sample_uniforms(C2["seed"], 0, 0, idx_s, 3)
         x, jac, idx = ov.vegas_map(u, e)
         w = ot.integrand(x, grid, C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]) * jac
-        ov.estimate_from_weights(w, idx, 3, C2["n_bins"])
-    dt = time.perf_counter() - t0
-    return n_sample / dt, dt
+        ov.estimate_from_weights(w, idx, 3, C2["n_bins"])   # sums and histograms, as an iteration does
+        out.append(w)
+    return np.concatenate(out)
+
+
+def _oracle_range(args):
+    """Worker of the P-core leg: one contiguous range of sample indices."""
+    from threadpoolctl import threadpool_limits
+    from synth import synthetic_pdf_grid
+    first, count, chunk = args
+    grid = synthetic_pdf_grid()
+    with threadpool_limits(limits=1):
+        _oracle_weights(grid, first, count, chunk)
+    return count
+
+
+def cpu_baseline(n_sample, chunk=250_000):
+    """The FP64 oracle on the first n_sample events of iteration 0 (uniform
+    grid): on one host core (library thread pools held to one thread), and
+    over P worker processes splitting the sample-index range (P = the
+    process's CPU affinity, at most 16, the host share of one GPU).  Runs
+    before anything touches the GPU, so the workers are plain forks.
+    Returns the figures and the oracle's S1, S2 (exact sums, math.fsum)."""
+    import math
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from synth import synthetic_pdf_grid
+    grid = synthetic_pdf_grid()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        w = _oracle_weights(grid, 0, n_sample, chunk)
+        dt1 = time.perf_counter() - t0
+    s1, s2 = math.fsum(w), math.fsum(w * w)
+    P = max(1, min(16, len(os.sched_getaffinity(0))))
+    share = (n_sample + P - 1) // P
+    jobs = [(k * share, min(share, n_sample - k * share), min(chunk, share)) for k in range(P) if k * share < n_sample]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(jobs)) as pool:
+        done = sum(pool.map(_oracle_range, jobs))
+    dtp = time.perf_counter() - t0
+    assert done == n_sample
+    return dict(eps_1=n_sample / dt1, secs_1=dt1, eps_p=n_sample / dtp, secs_p=dtp, procs=len(jobs), s1=s1, s2=s2)
 
 
 def next_batch(res, rel_var, target, n_max, n_min=100_000):
@@ -566,6 +603,67 @@ def extra_events(vgx):
     return out
 
 
+def gpu_sums_on_oracle_sample(vgx, pdf, params, n_sample):
+    """The GPU's S1, S2 over the same first n_sample events of iteration 0
+    on the uniform grid (a fresh context: same seed, stream and counters)."""
+    from synth import C2
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], C2["seed"], 0, vgx.F32, params, pdf=pdf)
+    try:
+        r = vgx.vegas_iterate(v, n_sample, 0)
+    finally:
+        vgx.vegas_destroy(v)
+    return r["s1"], r["s2"]
+
+
+def compact_extras(vgx):
+    """The other configurations, compactly: C0 (FP64 VEGAS on the d = 4
+    Gaussian: its own size, time to 1e-4, and the chip-filling 1e9-sample
+    roofline run), C1 (PDF interpolation, 1e8 queries), C3 (64 batched
+    integrals) and C4 on the d = 8 narrow Gaussian (VEGAS vs flow)."""
+    import numpy as np
+    from synth import C0, C4
+    out = {}
+    g = extra_gauss(vgx)
+    prm = np.concatenate([np.full(4, C0["centre"]), np.full(4, C0["sigma"])])
+    # C0's own iteration size (1e5); the target needs ~4e7 samples
+    tv = time_to_precision_vegas(vgx, None, prm, C0["n_per_iter"], kind=vgx.GAUSS, dim=4, seed=C0["seed"],
+                                 max_iter=1500)
+    out["c0_gauss4_f64"] = {"events_per_s_10x1e5": g["small"]["events_per_s"], "ms_10x1e5": g["small"]["ms_total"],
+                            "time_to_1e-4": tv, "events_per_s_1e9": g["large"]["events_per_s"],
+                            "kernel_ms_1e9": g["large"]["kernel_ms"],
+                            "fp64_flops_per_sample": g["large"]["fp64_flops_per_sample"],
+                            "frac_of_fp64_peak": g["large"]["frac_of_fp64_peak"]}
+    pdfx = vgx.pdf_create(*_c1_grid_arrays())
+    try:
+        c1 = extra_pdf(vgx, pdfx)
+    finally:
+        vgx.pdf_destroy(pdfx)
+    out["c1_pdf_interp_1e8"] = {k: {"queries_per_s": v["queries_per_s"], "frac_of_8TBps": v["frac_of_8TBps"],
+                                    "ms": v["ms"]} for k, v in c1.items()}
+    b = extra_batch(vgx)
+    out["c3_batched_64"] = {"events_per_s": b["events_per_s"], "ms_per_iteration": b["ms_per_iteration"],
+                            "autotuned_tile": b["autotuned_tile"], "autotuned_block": b["autotuned_block"]}
+    d8 = C4["gauss_dim"]
+    gp = np.concatenate([np.full(d8, C4["gauss_centre"]), np.full(d8, C4["gauss_sigma"])])
+    # VEGAS: iterations of 1e7 (at most 30); flow: two warm-up iterations of
+    # 1e6 (the narrow peak needs the second refinement before the flow's
+    # training points see it), batches up to 1e7
+    gv = time_to_precision_vegas(vgx, None, gp, 10_000_000, kind=vgx.GAUSS, dim=d8, seed=C4["seed"])
+    gf = flow_pipeline(vgx, vgx.GAUSS, d8, gp, None, 1_000_000, warm_iters=2, steps=C4["steps"], batch=C4["batch"],
+                       lr=C4["lr"], n_flow=10_000_000, seed=C4["seed"])
+    keys = ("seconds", "seconds_excluding_training", "training_seconds", "reached", "rel_var_per_sample_flow",
+            "rel_var_per_sample_vegas_refined_grid", "gain_trained_vs_identity_flow")
+    out["c4_flow_gauss8"] = {"vegas_seconds": gv["seconds"], "vegas_reached": gv["reached"],
+                             "flow": {k: gf.get(k) for k in keys}}
+    return out
+
+
+def _c1_grid_arrays():
+    from synth import synthetic_pdf_grid
+    g = synthetic_pdf_grid()
+    return g.x_knots, g.q2_knots, g.xf
+
+
 def main():
     args = parse()
     if args.copy_reference:
@@ -581,6 +679,11 @@ def main():
         print(f"bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    # the oracle's host legs first, before anything touches the GPU (its
+    # worker processes are forks of this one)
+    n_cpu = 4_000_000
+    cpu = None if args.no_cpu else cpu_baseline(n_cpu)
+
     import numpy as np
     import torch
     import paper_2302_03343_amd.vgx as vgx
@@ -592,8 +695,36 @@ def main():
     pdf = vgx.pdf_create(grid.x_knots, grid.q2_knots, grid.xf)
     params = np.array([C2["sqrt_s"], C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"]])
     n = args.events or C2["n_per_iter"]
-    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], C2["seed"], 0, vgx.F32, params, pdf=pdf)
 
+    out_tail = {}
+    # comparisons and the other configurations run before the headline's
+    # warm-up and timed steps, which therefore run on a GPU whose clocks have
+    # left idle
+    if not args.no_flow:
+        from synth import C4
+        tv = time_to_precision_vegas(vgx, pdf, params, n)
+        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, n, warm_iters=1, steps=C4["steps"], batch=C4["batch"],
+                           lr=C4["lr"], n_flow=n, seed=1000 + C2["seed"])
+        out_tail["time_to_1e-4"] = {"vegas": tv, "flow": tf,
+                                    "flow_faster_including_training": tf["seconds"] < tv["seconds"],
+                                    "flow_faster_excluding_training": tf["seconds_excluding_training"] < tv["seconds"]}
+    if not args.no_compact:
+        out_tail["other_configs"] = compact_extras(vgx)
+    if args.extras:
+        out_tail["extras"] = {k: f() for k, f in extras_table(vgx, pdf, grid, params, n).items()}
+    if cpu is not None:
+        g1, g2 = gpu_sums_on_oracle_sample(vgx, pdf, params, n_cpu)
+        out_tail["cpu_baseline"] = {
+            "value": cpu["eps_1"], "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_cpu} events of iteration 0 (uniform grid), FP64 numpy, chunks of 250k: "
+                      f"{cpu['secs_1']:.1f} s on one core; {cpu['secs_p']:.1f} s over {cpu['procs']} processes",
+            "value_multi": cpu["eps_p"], "cores_multi": cpu["procs"],
+            "oracle_s1": cpu["s1"], "oracle_s2": cpu["s2"], "gpu_s1": g1, "gpu_s2": g2,
+            "gpu_vs_oracle_rel_s1": abs(g1 - cpu["s1"]) / abs(cpu["s1"]),
+            "gpu_vs_oracle_rel_s2": abs(g2 - cpu["s2"]) / abs(cpu["s2"]),
+        }
+
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], C2["seed"], 0, vgx.F32, params, pdf=pdf)
     it = 0
     for _ in range(args.warmup):
         vgx.vegas_iterate(v, n, it)
@@ -614,6 +745,7 @@ def main():
     vgx.vegas_set_timing(v, False)
     res = vgx.vegas_result(v)
     vgx.vegas_destroy(v)
+    vgx.pdf_destroy(pdf)
 
     ms_per_step = dt / args.steps * 1e3
     value = n * args.steps / dt
@@ -652,38 +784,11 @@ def main():
             "kernel_avg_ms": kern_avg_s * 1e3,
             "flops_per_event": FLOPS_PER_EVENT_F32,
             "events_per_launch": n,
+            "frac_per_flavour_count": FLOPS_PER_EVENT_PER_FLAVOUR_COUNT * n / kern_avg_s / PEAK_FP32,
+            "flops_per_event_per_flavour_count": FLOPS_PER_EVENT_PER_FLAVOUR_COUNT,
         },
     }
-    if not args.no_flow:
-        from synth import C4
-        tv = time_to_precision_vegas(vgx, pdf, params, n)
-        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, n, warm_iters=1, steps=C4["steps"], batch=C4["batch"],
-                           lr=C4["lr"], n_flow=n, seed=1000 + C2["seed"])
-        tv["ns_per_event"] = ms_per_step * 1e6 / n
-        out["time_to_1e-4"] = {"vegas": tv, "flow": tf,
-                               "flow_faster_including_training": tf["seconds"] < tv["seconds"],
-                               "flow_faster_excluding_training": tf["seconds_excluding_training"] < tv["seconds"]}
-        if args.extras:
-            # the d = 8 narrow Gaussian (sigma 0.05), FP64 integrand
-            import numpy as np
-            d8 = C4["gauss_dim"]
-            gp = np.concatenate([np.full(d8, C4["gauss_centre"]), np.full(d8, C4["gauss_sigma"])])
-            # VEGAS: iterations of 1e7 (at most 30); flow: two warm-up
-            # iterations of 1e6 (the narrow peak needs the second refinement
-            # before the flow's training points see it), batches up to 1e7
-            gv = time_to_precision_vegas(vgx, None, gp, 10_000_000, kind=vgx.GAUSS, dim=d8, seed=C4["seed"])
-            gf = flow_pipeline(vgx, vgx.GAUSS, d8, gp, None, 1_000_000, warm_iters=2, steps=C4["steps"],
-                               batch=C4["batch"], lr=C4["lr"], n_flow=10_000_000, seed=C4["seed"])
-            out["time_to_1e-4"]["gauss8"] = {"vegas": gv, "flow": gf}
-    if args.extras:
-        out["extras"] = {k: f() for k, f in extras_table(vgx, pdf, grid, params, n).items()}
-    if not args.no_cpu:
-        n_cpu = 4_000_000
-        eps, secs = cpu_baseline(grid, n_cpu)
-        out["cpu_baseline"] = {"value": eps, "unit": "events/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {n_cpu} events of iteration 0 (uniform grid), FP64 numpy on one "
-                                         f"core, chunks of 250k, {secs:.1f} s"}
-    vgx.pdf_destroy(pdf)
+    out.update(out_tail)
     print(json.dumps(out), flush=True)
 
 

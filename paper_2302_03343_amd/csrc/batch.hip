@@ -67,16 +67,17 @@ struct BatchItem {
   double* hist;          // context histogram [dim][nb]
   IterRecord* rec;       // context records
   Combined* comb;
-  int k_rec;             // record slot of this iteration (host-updated)
-  int pad;
   IntegrandParams prm;
 };
 
+// Per-iteration inputs, one host-to-device copy: the tile counter, the
+// iteration number, then the record slot of every integral (int32[count]).
 struct BatchState {
   unsigned long long tile_counter;
   int iteration;
   int pad;
 };
+__host__ __device__ inline int* batch_krec(BatchState* st) { return (int*)(st + 1); }
 
 template <int D, class F>
 __device__ __forceinline__ void run_tile(const BatchItem& it, const F& f, const double* se, double* sh, int64_t s0,
@@ -199,8 +200,12 @@ __global__ __launch_bounds__(BB_MAX) void k_batch(const BatchItem* __restrict__ 
 }
 
 // Per integral (blockIdx.y) and column block (blockIdx.x): sum the tile rows
-// in tile order; block x = 0 finalises the record and the combination.
-__global__ __launch_bounds__(256) void k_batch_reduce(const BatchItem* __restrict__ items, const double* __restrict__ partials) {
+// in tile order; block x = 0 finalises the record and the combination, and
+// copies the record to out[blockIdx.y] (all integrals' records in one array:
+// one read-back).
+__global__ __launch_bounds__(256) void k_batch_reduce(const BatchItem* __restrict__ items,
+                                                      const double* __restrict__ partials, BatchState* st,
+                                                      IterRecord* __restrict__ out) {
   const BatchItem& it = items[blockIdx.y];
   __shared__ double ss[4][64], sc[4][64];
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
@@ -220,8 +225,11 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchItem* __restric
     if (col >= 4 && col < ncols) it.hist[col - 4] = t.value();
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < 64)
-    finalize_record(ss[0][0] + ss[0][1], ss[0][2] + ss[0][3], it.n, it.rec, it.k_rec, it.comb);
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    const int k_rec = batch_krec(st)[blockIdx.y];
+    finalize_record(ss[0][0] + ss[0][1], ss[0][2] + ss[0][3], it.n, it.rec, k_rec, it.comb);
+    if (threadIdx.x == 0) out[blockIdx.y] = it.rec[k_rec];  // the lane that stored it
+  }
 }
 
 // Per integral (blockIdx.y) and dimension (blockIdx.x): Lepage refinement.
@@ -244,7 +252,8 @@ struct vgx_batch {
   std::vector<int64_t> n;
   std::vector<BatchItem> items;      // host mirror
   BatchItem* d_items = nullptr;
-  BatchState* d_state = nullptr;
+  BatchState* d_state = nullptr;     // BatchState + int32 record slots [count]
+  IterRecord* d_out = nullptr;       // this iteration's records [count]
   double* partials = nullptr;
   size_t part_cap = 0;               // doubles
   int tile = 0, block = 0, grid = 0;
@@ -280,6 +289,8 @@ size_t partial_doubles(const vgx_batch* b, int tile) {
   return off;
 }
 
+size_t state_bytes(int count) { return sizeof(BatchState) + sizeof(int) * (size_t)count; }
+
 vgx_status upload_items(vgx_batch* b, hipStream_t st) {
   VGX_HIP(hipMemcpyAsync(b->d_items, b->items.data(), sizeof(BatchItem) * b->count, hipMemcpyHostToDevice, st));
   return VGX_OK;
@@ -291,7 +302,7 @@ vgx_status enqueue_iteration(vgx_batch* b, hipStream_t st, bool refine) {
                      b->tile, b->copies, b->d_state, b->partials);
   if (refine) {
     hipLaunchKernelGGL(k_batch_reduce, dim3((b->max_cols + 63) / 64, b->count), dim3(256), 0, st, b->d_items,
-                       b->partials);
+                       b->partials, b->d_state, b->d_out);
     hipLaunchKernelGGL(k_batch_refine, dim3(VGX_MAX_DIM, b->count), dim3(64), 0, st, b->d_items, b->d_state);
   }
   VGX_HIP(hipGetLastError());
@@ -406,12 +417,13 @@ extern "C" vgx_status batch_create(vgx_vegas* const* ctxs, int32_t count, const 
     b->part_cap = partial_doubles(b, tile > 0 ? tile : 2048);
     if ((s = dev_alloc((void**)&b->partials, sizeof(double) * b->part_cap)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&b->d_items, sizeof(BatchItem) * count)) != VGX_OK) break;
-    if ((s = dev_alloc((void**)&b->d_state, sizeof(BatchState))) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&b->d_state, state_bytes(count))) != VGX_OK) break;
+    if ((s = dev_alloc((void**)&b->d_out, sizeof(IterRecord) * count)) != VGX_OK) break;
     if ((s = host_alloc((void**)&b->pinned, sizeof(IterRecord) * count)) != VGX_OK) break;
-    if ((s = host_alloc((void**)&b->pinned_state, sizeof(BatchState))) != VGX_OK) break;
+    if ((s = host_alloc((void**)&b->pinned_state, state_bytes(count))) != VGX_OK) break;
   } while (0);
   if (s != VGX_OK) { batch_destroy(b); return s; }
-  hipError_t e = hipMemsetAsync(b->d_state, 0, sizeof(BatchState), b->stream);
+  hipError_t e = hipMemsetAsync(b->d_state, 0, state_bytes(count), b->stream);
   if (e != hipSuccess) { s = hip_fail(e, "batch_create", __FILE__, __LINE__); batch_destroy(b); return s; }
   s = autotune(b, tile, block);
   if (s == VGX_OK) s = upload_items(b, b->stream);
@@ -439,20 +451,19 @@ extern "C" vgx_status batch_create(vgx_vegas* const* ctxs, int32_t count, const 
 
 extern "C" vgx_status batch_iterate(vgx_batch* b, int32_t iteration, vgx_iter_result* out) {
   VGX_CHECK(b, "batch_iterate: null batch");
+  // per-iteration inputs in one copy: the iteration number and each
+  // integral's record slot (its context's count of stored records)
+  int* krec = batch_krec(b->pinned_state);
   for (int k = 0; k < b->count; ++k) {
     if (b->ctx[k]->n_rec >= MAX_RECORDS) { set_error("batch_iterate: context %d has too many records", k); return VGX_ESTATE; }
-    b->items[k].k_rec = b->ctx[k]->n_rec;
+    krec[k] = b->ctx[k]->n_rec;
   }
-  // per-iteration inputs: record slots and the iteration number
-  VGX_TRY(upload_items(b, b->stream));
   b->pinned_state->tile_counter = 0;
   b->pinned_state->iteration = iteration;
   b->pinned_state->pad = 0;
-  VGX_HIP(hipMemcpyAsync(b->d_state, b->pinned_state, sizeof(BatchState), hipMemcpyHostToDevice, b->stream));
+  VGX_HIP(hipMemcpyAsync(b->d_state, b->pinned_state, state_bytes(b->count), hipMemcpyHostToDevice, b->stream));
   VGX_HIP(hipGraphLaunch(b->exec, b->stream));
-  for (int k = 0; k < b->count; ++k)
-    VGX_HIP(hipMemcpyAsync(b->pinned + k, b->ctx[k]->rec + b->items[k].k_rec, sizeof(IterRecord),
-                           hipMemcpyDeviceToHost, b->stream));
+  VGX_HIP(hipMemcpyAsync(b->pinned, b->d_out, sizeof(IterRecord) * b->count, hipMemcpyDeviceToHost, b->stream));
   VGX_HIP(hipStreamSynchronize(b->stream));
   vgx_status s = VGX_OK;
   for (int k = 0; k < b->count; ++k) {
@@ -491,6 +502,7 @@ extern "C" void batch_destroy(vgx_batch* b) {
   hipFree(b->partials);
   hipFree(b->d_items);
   hipFree(b->d_state);
+  hipFree(b->d_out);
   if (b->pinned) hipHostFree(b->pinned);
   if (b->pinned_state) hipHostFree(b->pinned_state);
   delete b;
