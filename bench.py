@@ -82,7 +82,8 @@ def measured_traffic(events_per_launch):
 
 
 EXTRA_NAMES = ("ttbar_fixed_scale_contraction", "ttbar_dynamic_scale", "drell_yan_1e7", "single_top_s_1e7",
-               "pdf_interp_1e8", "vegas_gauss4_f64", "batched_64", "events", "pdf_members_fk_2415")
+               "pdf_interp_1e8", "vegas_gauss4_f64", "batched_64", "events", "pdf_members_fk_2415",
+               "flow_train_ttbar", "flow_sample_ttbar")
 
 
 def extras_table(vgx, pdf, grid, params, n):
@@ -95,7 +96,65 @@ def extras_table(vgx, pdf, grid, params, n):
             "vegas_gauss4_f64": lambda: extra_gauss(vgx),
             "batched_64": lambda: extra_batch(vgx),
             "events": lambda: extra_events(vgx),
-            "pdf_members_fk_2415": lambda: extra_members(vgx, grid)}
+            "pdf_members_fk_2415": lambda: extra_members(vgx, grid),
+            "flow_train_ttbar": lambda: extra_flow_train(vgx, pdf, params),
+            "flow_sample_ttbar": lambda: extra_flow_sample(vgx, pdf, params, n)}
+
+
+def _ttbar_flow_setup(vgx, pdf, params):
+    """A t tbar context after one refinement and a coupling flow (d = 3) with
+    He-normal hidden layers and a zero output layer."""
+    from synth import C2, C4, he_init_segments
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], 1000 + C2["seed"], 0, vgx.F32, params, pdf=pdf)
+    vgx.vegas_iterate(v, 1_000_000, 0)
+    vgx.vegas_refine(v)
+    f = vgx.flow_create(3, he_init_segments(vgx.flow_param_layout(3), C4["seed"]))
+    return v, f
+
+
+def extra_flow_train(vgx, pdf, params, steps=50):
+    """Training steps of the d = 3 flow on t tbar samples of the refined grid
+    (batch 1e5, lr 1e-3): milliseconds per step (training kernels alone, HIP
+    events around the loop, data drawn beforehand)."""
+    import torch
+    from synth import C4
+    v, f = _ttbar_flow_setup(vgx, pdf, params)
+    try:
+        n = C4["batch"]
+        u = torch.empty((steps, 3, n), dtype=torch.float64, device="cuda")
+        g = torch.empty((steps, n), dtype=torch.float64, device="cuda")
+        for s in range(steps):
+            vgx.vegas_sample(v, 0, n, 10_000 + s, u=u[s], g=g[s])
+        vgx.flow_train_step(f, u[0], g[0], C4["lr"])  # first use allocates the training buffers
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in range(1, steps):
+            vgx.flow_train_step(f, u[s], g[s], C4["lr"], sync=False)
+        e1.record()
+        e1.synchronize()
+        loss = vgx.flow_train_step(f, u[0], g[0], 0.0)
+        return {"ms_per_step": e0.elapsed_time(e1) / (steps - 1), "batch": n, "loss_after": loss}
+    finally:
+        vgx.flow_destroy(f)
+        vgx.vegas_destroy(v)
+
+
+def extra_flow_sample(vgx, pdf, params, n):
+    """Flow points and their evaluation (weights f/q) for n t tbar events:
+    milliseconds for the pair of calls (HIP events)."""
+    import torch
+    v, f = _ttbar_flow_setup(vgx, pdf, params)
+    try:
+        y = torch.empty((3, n), dtype=torch.float64, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.flow_sample(f, n, 1, 5, 0, y, lq)
+        vgx.vegas_iterate_points(v, y, lq)
+        ms = cuda_timed(lambda: (vgx.flow_sample(f, n, 1, 5, 0, y, lq), vgx.vegas_iterate_points(v, y, lq)))
+        return {"ms": ms, "ns_per_event": ms * 1e6 / n}
+    finally:
+        vgx.flow_destroy(f)
+        vgx.vegas_destroy(v)
 
 
 def one_extra(name, n_events):
@@ -703,7 +762,10 @@ def main():
     if not args.no_flow:
         from synth import C4
         tv = time_to_precision_vegas(vgx, pdf, params, n)
-        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, n, warm_iters=1, steps=C4["steps"], batch=C4["batch"],
+        # one VEGAS warm-up iteration of 1e6 events: it refines the grid the
+        # flow trains on (the training draws its own 1e5-point batches)
+        tf = flow_pipeline(vgx, vgx.TTBAR, 3, params, pdf, 1_000_000, warm_iters=1, steps=C4["steps"],
+                           batch=C4["batch"],
                            lr=C4["lr"], n_flow=n, seed=1000 + C2["seed"])
         out_tail["time_to_1e-4"] = {"vegas": tv, "flow": tf,
                                     "flow_faster_including_training": tf["seconds"] < tv["seconds"],

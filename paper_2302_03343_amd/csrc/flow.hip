@@ -966,6 +966,269 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Fused backward and weight gradients of one layer (|B| <= 4).
+//
+// The workgroup's four waves take four 32-sample tiles at a time.  Each wave
+// runs the backward of its tile as k_flow_bwd does; the operands of the
+// weight-gradient products (deltas and activations, feature-major) go to an
+// LDS stage instead of global memory, one product at a time: [dlogit | h2],
+// then [dpre2 | h1], then [dpre1 | zA].  After each stage the four waves
+// contract the four tiles (K = 128 samples) into the weight-gradient tiles
+// they own: output tile tau of [dW3 (2 |B|) | dW2 (4) | dW1 (2)] belongs to
+// wave tau mod 4, whose accumulators persist over all the tiles of the
+// workgroup.  Each workgroup finally stores its partial of the layer's
+// parameter block (every element from its one owner: no LDS reduction), in
+// the layout k_flow_wgrad writes.
+// ---------------------------------------------------------------------------
+constexpr int FUSE_WAVES = 4;
+
+// rows of a stage: the largest of (32 |B|max + 64), 128 and 96
+__host__ __device__ constexpr int fuse_stage_rows(int nbm) { return 32 * nbm + 64 > 128 ? 32 * nbm + 64 : 128; }
+// row stride of a stage in elements: 32 samples, + 16 bytes of padding for
+// BF16 stages (the FP32 validation stages go without, to fit the LDS)
+template <class OP>
+__host__ __device__ constexpr int fuse_rs() { return sizeof(typename OP::S) == 2 ? 40 : 32; }
+
+// LDS of the fused kernel: packs and biases | z, dz columns [2][d][FBLOCK] |
+// stage [FUSE_WAVES][rows][rs]
+__host__ __device__ inline size_t fuse_z_offset(int fw_len, int bw_len, int bias_len, int es) {
+  return bwd_z_offset(fw_len, bw_len, bias_len, es);
+}
+__host__ __device__ inline size_t fuse_stage_offset(int fw_len, int bw_len, int bias_len, int es, int d) {
+  return fuse_z_offset(fw_len, bw_len, bias_len, es) + sizeof(float) * 2 * (size_t)d * FBLOCK;
+}
+
+// one 32x32 D tile into a stage, feature-major (row = feature, column = sample)
+template <class OP>
+__device__ __forceinline__ void stage_tile(typename OP::S* st, int row0, const f32x16& c, int s, int h) {
+  constexpr int RS = fuse_rs<OP>();
+#pragma unroll
+  for (int v = 0; v < 16; ++v) st[(row0 + drow(v, h)) * RS + s] = OP::store(c[v]);
+}
+
+template <class OP>
+__device__ __forceinline__ typename OP::frag stage_frag(const typename OP::S* st, int row, int kk, int h) {
+  constexpr int RS = fuse_rs<OP>();
+  return *(const typename OP::frag*)(st + row * RS + 16 * kk + 8 * h);
+}
+
+// contract the four waves' stages: A rows arow0 + 32 m, B rows brow0 + 32 n
+template <class OP>
+__device__ __forceinline__ void fuse_contract(const typename OP::S* stage, int srows, int arow0, int brow0, int m,
+                                              int n, f32x16& acc, float& bsum) {
+  constexpr int RS = fuse_rs<OP>();
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int q = 0; q < FUSE_WAVES; ++q) {
+    const typename OP::S* st = stage + (size_t)q * srows * RS;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const typename OP::frag af = stage_frag<OP>(st, arow0 + 32 * m + i, kk, h);
+      const typename OP::frag bf = stage_frag<OP>(st, brow0 + 32 * n + i, kk, h);
+      if (n == 0) bsum += frag_sum<OP>(af);
+      acc = OP::mma(af, bf, acc);
+    }
+  }
+}
+
+template <int NBM, class OP>
+__global__ __launch_bounds__(FBLOCK) void k_flow_bwdw(const FlowDesc* __restrict__ Dp, BwdArgs a,
+                                                     const typename OP::S* __restrict__ fw,
+                                                     const typename OP::S* __restrict__ bw,
+                                                     const float* __restrict__ bias, float* __restrict__ gpart) {
+  static_assert(NBM <= 4, "the fused kernel holds at most four weight-gradient tiles per wave");
+  using S = typename OP::S;
+  using frag = typename OP::frag;
+  constexpr int SR = fuse_stage_rows(NBM);
+  constexpr int RS = fuse_rs<OP>();
+  constexpr int OWN = (2 * NBM + 6 + FUSE_WAVES - 1) / FUSE_WAVES;  // output tiles per wave
+  extern __shared__ __align__(16) unsigned char flds[];
+  const FlowDesc& D = *Dp;
+  const FlowLayerDesc& L = D.l[a.layer];
+  S* sfw = (S*)flds;
+  S* sbw = sfw + L.fw_len;
+  float* sb = (float*)(sbw + L.bw_len);
+  const int d = D.d;
+  const int es = (int)sizeof(S);
+  float* z = (float*)(flds + fuse_z_offset(L.fw_len, L.bw_len, L.bias_len, es)) + threadIdx.x;
+  float* dz = z + d * FBLOCK;
+  S* stage = (S*)(flds + fuse_stage_offset(L.fw_len, L.bw_len, L.bias_len, es, d));
+  copy16(sfw, fw + L.fw_off, L.fw_len * es);
+  copy16(sbw, bw + L.bw_off, L.bw_len * es);
+  copy16(sb, bias + L.bias_off, L.bias_len * 4);
+  __syncthreads();
+  const LayerLds<OP> W = layer_lds<OP>(sfw, sb, L, L.fw_off, L.bias_off);
+  const frag* w3t = (const frag*)sbw;                         // [2][2nb][32][2]
+  const frag* w2t = (const frag*)(sbw + L.nb * 2048);         // [2][4][32][2]
+  const frag* w1t = (const frag*)(sbw + L.nb * 2048 + 4096);  // [1][4][32][2]
+  const double scale = a.loss[1];
+  const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+  const int wave = threadIdx.x >> 6;
+  S* mystage = stage + (size_t)wave * SR * RS;
+  const int64_t ntiles = (a.n + 31) / 32;
+  const int na = L.na, nb = L.nb;
+  const int T3 = 2 * nb, T = 2 * nb + 6;
+  f32x16 acc[OWN];
+  float bsum[OWN];
+#pragma unroll
+  for (int k = 0; k < OWN; ++k) {
+    acc[k] = zero16();
+    bsum[k] = 0.0f;
+  }
+  for (int64_t g = blockIdx.x; g * FUSE_WAVES < ntiles; g += gridDim.x) {
+    // tiles past the end run with no valid sample: zero deltas, nothing added
+    const int64_t t = g * FUSE_WAVES + wave;
+    const int64_t i = t * 32 + s;
+    const bool valid = i < a.n;
+    for (int j = 0; j < d; ++j) {
+      z[j * FBLOCK] = valid ? a.zin[(int64_t)j * a.n + i] : 0.5f;
+      dz[j * FBLOCK] = (valid && a.dzout) ? a.dzout[(int64_t)j * a.n + i] : 0.0f;
+    }
+    const float dlq = valid ? (float)(a.rsave[i] * scale) : 0.0f;
+    float za[FAB];
+#pragma unroll
+    for (int e = 0; e < FAB; ++e) za[e] = (e < na) ? z[L.a_idx[e] * FBLOCK] : 0.0f;
+    f32x16 h1[2], h2[2], lg[NBM];
+    mlp_fwd<NBM, OP>(za, na, nb, W, h1, h2, lg);
+    unsigned m1[2] = {0u, 0u}, m2[2] = {0u, 0u};
+#pragma unroll
+    for (int to = 0; to < 2; ++to)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        m1[to] |= (h1[to][v] > 0.0f ? 1u : 0u) << v;
+        m2[to] |= (h2[to][v] > 0.0f ? 1u : 0u) << v;
+      }
+    // bins, dQ and dlogit per transformed dim (the incoming gradient of z_j
+    // is dz[j] before this layer's update)
+#pragma unroll
+    for (int jb = 0; jb < NBM; ++jb) {
+      if (jb < nb) {
+        softmax32(lg[jb]);
+        const int j = L.b_idx[jb];
+        int b;
+        float al, qb;
+        cdf_fwd(lg[jb], z[j * FBLOCK], b, al, qb);
+        const float g_out = dz[j * FBLOCK];
+        float dq[16];
+        float sdot = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int k = drow(v, h);
+          dq[v] = g_out * ((k < b) ? 1.0f : ((k == b) ? al : 0.0f)) + ((k == b) ? dlq / qb : 0.0f);
+          sdot += lg[jb][v] * dq[v];
+        }
+        sdot += xor32(sdot);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) lg[jb][v] = lg[jb][v] * (dq[v] - sdot);  // dlogit
+        dz[j * FBLOCK] = g_out * (float)FK * qb;
+      }
+    }
+    // stage 1: [dlogit rows 0 .. 32 nb | h2 rows 32 NBM ..]; dW3, db3
+#pragma unroll
+    for (int jb = 0; jb < NBM; ++jb)
+      if (jb < nb) stage_tile<OP>(mystage, 32 * jb, lg[jb], s, h);
+    stage_tile<OP>(mystage, 32 * NBM, h2[0], s, h);
+    stage_tile<OP>(mystage, 32 * NBM + 32, h2[1], s, h);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+      const int tau = wave + FUSE_WAVES * k;
+      if (tau < T3) fuse_contract<OP>(stage, SR, 0, 32 * NBM, tau >> 1, tau & 1, acc[k], bsum[k]);
+    }
+    __syncthreads();
+    // dh2 = W3^T dlogit, masked by relu'
+    f32x16 d2[2];
+#pragma unroll
+    for (int to = 0; to < 2; ++to) {
+      f32x16 ac = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 2 * NBM; ++kk)
+        if (kk < 2 * nb) ac = OP::mma(w3t[((to * 2 * nb + kk) * 32 + s) * 2 + h], to_b<OP>(lg[kk >> 1], kk & 1), ac);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) ac[v] = ((m2[to] >> v) & 1u) ? ac[v] : 0.0f;
+      d2[to] = ac;
+    }
+    // stage 2: [dpre2 rows 0 .. 64 | h1 rows 64 .. 128]; dW2, db2
+    stage_tile<OP>(mystage, 0, d2[0], s, h);
+    stage_tile<OP>(mystage, 32, d2[1], s, h);
+    stage_tile<OP>(mystage, 64, h1[0], s, h);
+    stage_tile<OP>(mystage, 96, h1[1], s, h);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+      const int tau = wave + FUSE_WAVES * k - T3;
+      if (tau >= 0 && tau < 4) fuse_contract<OP>(stage, SR, 0, 64, tau >> 1, tau & 1, acc[k], bsum[k]);
+    }
+    __syncthreads();
+    // dh1 = W2^T dpre2, masked
+    f32x16 d1[2];
+#pragma unroll
+    for (int to = 0; to < 2; ++to) {
+      f32x16 ac = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) ac = OP::mma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], to_b<OP>(d2[kk >> 1], kk & 1), ac);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) ac[v] = ((m1[to] >> v) & 1u) ? ac[v] : 0.0f;
+      d1[to] = ac;
+    }
+    // stage 3: [dpre1 rows 0 .. 64 | zA rows 64 .. 96, rows >= |A| zero]; dW1, db1
+    stage_tile<OP>(mystage, 0, d1[0], s, h);
+    stage_tile<OP>(mystage, 32, d1[1], s, h);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const float val = (e < FAB && h == 0 && e < na) ? za[e & (FAB - 1)] : 0.0f;
+      mystage[(64 + 16 * h + e) * RS + s] = OP::store(val);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+      const int tau = wave + FUSE_WAVES * k - T3 - 4;
+      if (tau >= 0 && tau < 2) fuse_contract<OP>(stage, SR, 0, 64, tau, 0, acc[k], bsum[k]);
+    }
+    __syncthreads();
+    // dzA = W1^T dpre1: rows a = 4h + r in registers 0..3
+    f32x16 d0 = zero16();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d0 = OP::mma(w1t[(kk * 32 + s) * 2 + h], to_b<OP>(d1[kk >> 1], kk & 1), d0);
+    float dza[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float mine = d0[r], other = xor32(d0[r]);
+      dza[r] = h == 0 ? mine : other;
+      dza[4 + r] = h == 0 ? other : mine;
+    }
+#pragma unroll
+    for (int e = 0; e < FAB; ++e)
+      if (e < na) dz[L.a_idx[e] * FBLOCK] += dza[e];
+    if (valid && h == 0) {
+      for (int j = 0; j < d; ++j) a.dzin[(int64_t)j * a.n + i] = dz[j * FBLOCK];
+    }
+  }
+  // the workgroup's partial of the parameter block, each element from its owner
+  float* out = gpart + (size_t)blockIdx.x * L.n_par;
+  const int oW1 = 0, ob1 = FH * na, oW2 = ob1 + FH, ob2 = oW2 + FH * FH, oW3 = ob2 + FH, ob3 = oW3 + nb * FK * FH;
+  const int i32 = lane & 31;
+#pragma unroll
+  for (int k = 0; k < OWN; ++k) {
+    const int tau = wave + FUSE_WAVES * k;
+    if (tau >= T) continue;
+    int wo, bo, ld, ncol, m, n;
+    if (tau < T3) { wo = oW3; bo = ob3; ld = FH; ncol = FH; m = tau >> 1; n = tau & 1; }
+    else if (tau < T3 + 4) { wo = oW2; bo = ob2; ld = FH; ncol = FH; m = (tau - T3) >> 1; n = (tau - T3) & 1; }
+    else { wo = oW1; bo = ob1; ld = na; ncol = na; m = tau - T3 - 4; n = 0; }
+    const int col = 32 * n + i32;
+    if (col < ncol) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) out[wo + (32 * m + drow(v, h)) * ld + col] = acc[k][v];
+    }
+    if (n == 0) {
+      const float tot = bsum[k] + xor32(bsum[k]);
+      if (h == 0) out[bo + 32 * m + i32] = tot;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Gradient reduction (fixed order over workgroup partials) + Adam.
 // ---------------------------------------------------------------------------
 constexpr int GSPLIT = 8;  // row groups of the first reduction stage
@@ -1203,6 +1466,19 @@ size_t bwd_lds(const vgx_flow* f, int l) {
   return bwd_z_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len, op_es(f)) + sizeof(float) * 3 * (size_t)f->dim * FBLOCK;
 }
 
+template <class OP>
+size_t fuse_lds_op(const vgx_flow* f, int l) {
+  const FlowLayerDesc& Ld = f->D.l[l];
+  const int es = (int)sizeof(typename OP::S);
+  return fuse_stage_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len, es, f->dim) +
+         (size_t)FUSE_WAVES * fuse_stage_rows(f->nbm) * fuse_rs<OP>() * es;
+}
+
+size_t fuse_lds(const vgx_flow* f, int l) { return f->f32ops ? fuse_lds_op<OpF32>(f, l) : fuse_lds_op<OpBF16>(f, l); }
+
+// the backward of layers with |B| <= 4 runs fused with its weight gradients
+bool fused_backward(const vgx_flow* f) { return f->nbm <= 4; }
+
 size_t fwd_lds_es(const vgx_flow* f, int es) {
   return fwd_z_offset(f->D.fw_total, f->D.bias_total, es) + sizeof(float) * (size_t)f->dim * FWD_BLOCK;
 }
@@ -1225,43 +1501,53 @@ vgx_status pack(vgx_flow* f) {
 
 // Allow the dynamic LDS the kernels of this flow need (beyond 64 KB), once.
 template <int NB, class OP>
-vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr) {
+vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr, size_t fus) {
   // never lower a limit another live flow may rely on
-  static size_t cur_f = 0, cur_b = 0, cur_w = 0;
+  static size_t cur_f = 0, cur_b = 0, cur_w = 0, cur_u = 0;
   fwd = fwd > cur_f ? fwd : cur_f;
   bwd = bwd > cur_b ? bwd : cur_b;
   wgr = wgr > cur_w ? wgr : cur_w;
+  fus = fus > cur_u ? fus : cur_u;
   cur_f = fwd;
   cur_b = bwd;
   cur_w = wgr;
+  cur_u = fus;
+  if constexpr (NB <= 4) {
+    if (fus > 0)
+      VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwdw<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)fus));
+  }
   VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 0, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
   VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 1, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
   VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 2, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwd<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd));
-  VGX_HIP(hipFuncSetAttribute((const void*)k_flow_wgrad<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wgr));
+  if constexpr (NB > 4) {
+    VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwd<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd));
+    VGX_HIP(hipFuncSetAttribute((const void*)k_flow_wgrad<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wgr));
+  }
   return VGX_OK;
 }
 
 template <class OP>
-vgx_status set_lds_limits_nb(int nbm, size_t fwd, size_t bwd, size_t wgr) {
+vgx_status set_lds_limits_nb(int nbm, size_t fwd, size_t bwd, size_t wgr, size_t fus) {
   switch (nbm) {
-    case 1: return set_lds_limits<1, OP>(fwd, bwd, wgr);
-    case 2: return set_lds_limits<2, OP>(fwd, bwd, wgr);
-    case 4: return set_lds_limits<4, OP>(fwd, bwd, wgr);
-    default: return set_lds_limits<8, OP>(fwd, bwd, wgr);
+    case 1: return set_lds_limits<1, OP>(fwd, bwd, wgr, fus);
+    case 2: return set_lds_limits<2, OP>(fwd, bwd, wgr, fus);
+    case 4: return set_lds_limits<4, OP>(fwd, bwd, wgr, fus);
+    default: return set_lds_limits<8, OP>(fwd, bwd, wgr, fus);
   }
 }
 
 vgx_status init_lds_limits(const vgx_flow* f) {
-  size_t fwd = fwd_lds(f), bwd = 0, wgr = 0;
+  size_t fwd = fwd_lds(f), bwd = 0, wgr = 0, fus = 0;
   for (int l = 0; l < f->L; ++l) {
     const FlowLayerDesc& Ld = f->D.l[l];
     const size_t b = bwd_lds(f, l);
     bwd = b > bwd ? b : bwd;
     wgr = (size_t)Ld.n_par * 4 > wgr ? (size_t)Ld.n_par * 4 : wgr;
+    if (fused_backward(f)) fus = std::max(fus, fuse_lds(f, l));
   }
-  return f->f32ops ? set_lds_limits_nb<OpF32>(f->nbm, fwd, bwd, wgr)
-                   : set_lds_limits_nb<OpBF16>(f->nbm, fwd, bwd, wgr);
+  return f->f32ops ? set_lds_limits_nb<OpF32>(f->nbm, fwd, bwd, wgr, fus)
+                   : set_lds_limits_nb<OpBF16>(f->nbm, fwd, bwd, wgr, fus);
 }
 
 int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
@@ -1308,11 +1594,11 @@ vgx_status ensure_train(vgx_flow* f, int64_t n) {
   VGX_TRY(dev_alloc((void**)&f->lqsave, sizeof(double) * (size_t)n));
   VGX_TRY(dev_alloc((void**)&f->dz[0], sizeof(float) * (size_t)f->dim * n));
   VGX_TRY(dev_alloc((void**)&f->dz[1], sizeof(float) * (size_t)f->dim * n));
-  VGX_TRY(dev_alloc((void**)&f->scr, es * (size_t)tiles * f->srows * 32));
+  if (!fused_backward(f)) VGX_TRY(dev_alloc((void**)&f->scr, es * (size_t)tiles * f->srows * 32));
   VGX_TRY(dev_alloc((void**)&f->gpart, sizeof(float) * (size_t)f->n_par * f->grid_w));
   if (!f->gtmp) VGX_TRY(dev_alloc((void**)&f->gtmp, sizeof(float) * (size_t)f->n_par * GSPLIT));
   // rows 16..31 of the zA block are never written and must read as zero
-  VGX_HIP(hipMemsetAsync(f->scr, 0, es * (size_t)tiles * f->srows * 32, f->stream));
+  if (f->scr) VGX_HIP(hipMemsetAsync(f->scr, 0, es * (size_t)tiles * f->srows * 32, f->stream));
   f->cap_n = n;
   return VGX_OK;
 }
@@ -1352,16 +1638,36 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     b.loss = f->loss;
     b.scr = f->scr;
     b.srows = f->srows;
+    const size_t wl = (size_t)Ld.n_par * 4;
+    float* gp = f->gpart + (size_t)Ld.p_off * wgrid;
+    if (fused_backward(f)) {
+      const size_t lds = fuse_lds(f, l);
+#define F_(NB, OP)                                                                                          \
+  case NB:                                                                                                  \
+    hipLaunchKernelGGL((k_flow_bwdw<NB, OP>), dim3(wgrid), dim3(FBLOCK), lds, f->stream, f->d_desc, b,      \
+                       (const OP::S*)f->fw, (const OP::S*)f->bw, f->bias, gp);                              \
+    break;
+      if (f->f32ops) {
+        switch (f->nbm) { F_(1, OpF32) F_(2, OpF32) F_(4, OpF32) default: return VGX_EINVAL; }
+      } else {
+        switch (f->nbm) { F_(1, OpBF16) F_(2, OpBF16) F_(4, OpBF16) default: return VGX_EINVAL; }
+      }
+#undef F_
+      VGX_HIP(hipGetLastError());
+      cur ^= 1;
+      continue;
+    }
     const size_t lds = bwd_lds(f, l);
 #define B_(NB, OP)                                                                                        \
   case NB:                                                                                                \
     hipLaunchKernelGGL((k_flow_bwd<NB, OP>), dim3(bgrid), dim3(FBLOCK), lds, f->stream, f->d_desc, b,     \
                        (const OP::S*)f->fw, (const OP::S*)f->bw, f->bias);                                \
     break;
+    // |B| up to 8: backward and weight gradients as two kernels
     if (f->f32ops) {
-      switch (f->nbm) { B_(1, OpF32) B_(2, OpF32) B_(4, OpF32) B_(8, OpF32) default: return VGX_EINVAL; }
+      switch (f->nbm) { B_(8, OpF32) default: return VGX_EINVAL; }
     } else {
-      switch (f->nbm) { B_(1, OpBF16) B_(2, OpBF16) B_(4, OpBF16) B_(8, OpBF16) default: return VGX_EINVAL; }
+      switch (f->nbm) { B_(8, OpBF16) default: return VGX_EINVAL; }
     }
 #undef B_
     VGX_HIP(hipGetLastError());
@@ -1370,16 +1676,15 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     w.layer = l;
     w.scr = f->scr;
     w.srows = f->srows;
-    w.gpart = f->gpart + (size_t)Ld.p_off * wgrid;
-    const size_t wl = (size_t)Ld.n_par * 4;
+    w.gpart = gp;
 #define W_(NB, OP)                                                                                    \
   case NB:                                                                                            \
     hipLaunchKernelGGL((k_flow_wgrad<NB, OP>), dim3(wgrid), dim3(FBLOCK), wl, f->stream, f->d_desc, w); \
     break;
     if (f->f32ops) {
-      switch (f->nbm) { W_(1, OpF32) W_(2, OpF32) W_(4, OpF32) W_(8, OpF32) default: return VGX_EINVAL; }
+      switch (f->nbm) { W_(8, OpF32) default: return VGX_EINVAL; }
     } else {
-      switch (f->nbm) { W_(1, OpBF16) W_(2, OpBF16) W_(4, OpBF16) W_(8, OpBF16) default: return VGX_EINVAL; }
+      switch (f->nbm) { W_(8, OpBF16) default: return VGX_EINVAL; }
     }
 #undef W_
     VGX_HIP(hipGetLastError());
@@ -1485,7 +1790,10 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
     set_error("flow_create: expected %lld parameters, got %lld", (long long)f->n_par, (long long)n_params);
     return VGX_EINVAL;
   }
-  if (fwd_lds(f) > 160 * 1024) {
+  size_t need = fwd_lds(f);
+  if (fused_backward(f))
+    for (int l = 0; l < f->L; ++l) need = std::max(need, fuse_lds(f, l));
+  if (need > 160 * 1024) {
     delete f;
     set_error("flow_create: packed weights exceed LDS");
     return VGX_EINVAL;
@@ -1533,7 +1841,10 @@ extern "C" vgx_status flow_set_operands(vgx_flow* f, int32_t operands) {
             operands);
   const int want = operands == VGX_OPERANDS_F32 ? 1 : 0;
   if (want == f->f32ops) return VGX_OK;
-  if (fwd_lds_es(f, want ? 4 : 2) > 160 * 1024) {
+  size_t need = fwd_lds_es(f, want ? 4 : 2);
+  if (fused_backward(f))
+    for (int l = 0; l < f->L; ++l) need = std::max(need, want ? fuse_lds_op<OpF32>(f, l) : fuse_lds_op<OpBF16>(f, l));
+  if (need > 160 * 1024) {
     set_error("flow_set_operands: the FP32 weight packs of a %d-dimensional flow exceed the LDS", f->dim);
     return VGX_EINVAL;
   }
