@@ -31,7 +31,9 @@ struct Gauss : NoStage {
     R e = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const R z = ((R)x[j] - (R)prm.p[j]) * (R)prm.p[D + j];
+      // z = (x - c) k as x k - c k (one FMA; c k is loop-invariant)
+      const R k = (R)prm.p[D + j];
+      const R z = fma((R)x[j], k, -((R)prm.p[j] * k));
       e = fma(z, z, e);
     }
     return (double)((R)prm.p[2 * D] * exp(-e));

@@ -48,6 +48,8 @@ struct VegasArgs {
   int nb;
   int pstride;   // doubles per workgroup partial row
   int hcopies;   // histogram copies in LDS: 4 per wave, one per wave, or 1 (shared)
+  int narrow;    // the sample loop may run on 32-bit indices (see narrow_ok)
+  double nbD;    // nb^dim, the Jacobian's constant factor
 };
 
 // Histogram copies a workgroup keeps in LDS: one per wave when they fit in
@@ -68,16 +70,40 @@ __host__ __device__ inline int hist_copies(int D, int nb, bool lane_groups) {
 // ---------------------------------------------------------------------------
 template <int D>
 struct PhiloxSrc {
+  static constexpr bool kInterior = true;  // 0 < u N < N for every sample
   uint32_t it, sid, k0, k1;
   int64_t first;
   __device__ __forceinline__ double get(int64_t i, double (&u)[D]) const {
     philox_uniforms<D>((uint64_t)(first + i), it, sid, k0, k1, u);
     return 1.0;
   }
+  // scaled coordinates t = u N = (k + 1/2) N 2^-32 of counter (c0, c1), one
+  // FMA each (exact: k N 2^-32 has at most 40 significant bits)
+  __device__ __forceinline__ double get_t_c(uint32_t c0, uint32_t c1, double sc, double hf, double (&t)[D]) const {
+#pragma unroll
+    for (int b = 0; b < (D + 3) / 4; ++b) {
+      const u32x4 w = philox4x32_10(c0, c1, it, (sid << 8) | (uint32_t)b, k0, k1);
+      const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * b + e < D) t[4 * b + e < D ? 4 * b + e : 0] = fma((double)ww[e], sc, hf);
+    }
+    return 1.0;
+  }
+  __device__ __forceinline__ double get_t(int64_t i, double nbd, double sc, double hf, double (&t)[D]) const {
+    const uint64_t c = (uint64_t)(first + i);
+    return get_t_c((uint32_t)c, (uint32_t)(c >> 32), sc, hf, t);
+  }
+  // 32-bit sample index; the caller guarantees that the low counter word
+  // does not carry (narrow_ok)
+  __device__ __forceinline__ double get_t32(uint32_t i, double nbd, double sc, double hf, double (&t)[D]) const {
+    return get_t_c((uint32_t)first + i, (uint32_t)((uint64_t)first >> 32), sc, hf, t);
+  }
 };
 
 template <int D>
 struct PointsSrc {
+  static constexpr bool kInterior = false;  // caller points may lie on the faces
   const double* y;     // [D][n]
   const double* logq;  // [n] or null
   int64_t n;
@@ -85,6 +111,14 @@ struct PointsSrc {
 #pragma unroll
     for (int j = 0; j < D; ++j) u[j] = y[(int64_t)j * n + i];
     return logq ? exp(-logq[i]) : 1.0;
+  }
+  __device__ __forceinline__ double get_t(int64_t i, double nbd, double sc, double hf, double (&t)[D]) const {
+#pragma unroll
+    for (int j = 0; j < D; ++j) t[j] = y[(int64_t)j * n + i] * nbd;
+    return logq ? exp(-logq[i]) : 1.0;
+  }
+  __device__ __forceinline__ double get_t32(uint32_t i, double nbd, double sc, double hf, double (&t)[D]) const {
+    return get_t((int64_t)i, nbd, sc, hf, t);
   }
 };
 
@@ -139,14 +173,13 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
   Comp c1, c2;
   double p1 = 0.0, p2 = 0.0;
   int cnt = 0;
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += stride) {
-    double u[D], x[D];
+  const double nbd = (double)nb, sc = nbd * 0x1p-32, hf = nbd * 0x1p-33;
+  // one sample from its scaled coordinates and source weight
+  auto sample = [&](const double (&t)[D], double ws) {
+    double x[D];
     int idx[D];
-    const double ws = src.get(i, u);
-    double jac;
-    if constexpr (F::kStage) jac = grid_map<D>(u, se, nb, x, idx);
-    else jac = grid_map_split<D>(u, se, a.edges, nb, x, idx);  // the LDS is the limit here
+    // integrands without LDS tables: the edge pairs come from global memory
+    const double jac = grid_map_t<D, Src::kInterior, !F::kStage>(t, se, a.edges, nb, a.nbD, x, idx);
     const double w = ff.eval(x) * jac * ws;
     const double w2 = w * w;
     p1 += w;
@@ -160,6 +193,22 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
     if (HIST) {
 #pragma unroll
       for (int j = 0; j < D; ++j) atomicAdd(&hw[j * nb + idx[j]], w2);
+    }
+  };
+  if (a.narrow) {
+    // 32-bit indices (no 64-bit adds and compares in the loop)
+    const uint32_t n32 = (uint32_t)a.n, stride = gridDim.x * BLOCK;
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n32; i += stride) {
+      double t[D];
+      const double ws = src.get_t32(i, nbd, sc, hf, t);
+      sample(t, ws);
+    }
+  } else {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += stride) {
+      double t[D];
+      const double ws = src.get_t(i, nbd, sc, hf, t);
+      sample(t, ws);
     }
   }
   c1.add(p1);
@@ -583,10 +632,27 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
   }
 }
 
+// The sample loop runs on 32-bit indices when they and the low Philox
+// counter word (first + i) can neither wrap nor carry: i + grid stride stays
+// below 2^32 for i < 2^31.
+template <int D>
+bool narrow_ok(const PhiloxSrc<D>& s, int64_t n) {
+  return s.first >= 0 && (int64_t)((uint64_t)s.first & 0xFFFFFFFFu) + n <= ((int64_t)1 << 31);
+}
+template <int D>
+bool narrow_ok(const PointsSrc<D>&, int64_t n) { return n <= ((int64_t)1 << 31); }
+
+double pow_int(double b, int e) {
+  double r = 1.0;
+  for (int k = 0; k < e; ++k) r *= b;
+  return r;
+}
+
 // Launch helpers dispatching on (kind, prec, D).
 template <int D, class F, class Src, bool HIST>
 vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage)};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), narrow_ok(src, n) ? 1 : 0,
+              pow_int((double)v->nb, D)};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST, !F::kStage) + extra_lds_bytes(v);
   hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
@@ -653,7 +719,7 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
 
 template <int D, class F>
 vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, const F& f, double* u, double* g) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage)};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), 0, pow_int((double)v->nb, D)};
   PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false, !F::kStage) + extra_lds_bytes(v);
