@@ -83,11 +83,26 @@ template <int D, class F>
 __device__ __forceinline__ void run_tile(const BatchItem& it, const F& f, const double* se, double* sh, int64_t s0,
                                          int64_t s1, uint32_t iter, Comp& c1, Comp& c2) {
   double p1 = 0.0, p2 = 0.0;
+  // scaled coordinates t = u N straight from the Philox words (exact), the
+  // Jacobian's constant N^D
+  const double nbd = (double)it.nb, sc = nbd * 0x1p-32, hf = nbd * 0x1p-33;
+  double nbD = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) nbD *= nbd;
   for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-    double u[D], x[D];
+    double t[D], x[D];
     int idx[D];
-    philox_uniforms<D>((uint64_t)i, iter, it.sid, it.k0, it.k1, u);
-    const double jac = grid_map_split<D>(u, se, it.edges, it.nb, x, idx);  // the LDS is the limit here
+#pragma unroll
+    for (int b = 0; b < (D + 3) / 4; ++b) {
+      const u32x4 w4 = philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), iter, (it.sid << 8) | (uint32_t)b,
+                                     it.k0, it.k1);
+      const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * b + e < D) t[4 * b + e < D ? 4 * b + e : 0] = fma((double)ww[e], sc, hf);
+    }
+    // edge pairs from global memory: the LDS holds the histogram copies
+    const double jac = grid_map_t<D, true, true>(t, se, it.edges, it.nb, nbD, x, idx);
     const double w = f.eval(x) * jac;
     const double w2 = w * w;
     p1 += w;
