@@ -48,8 +48,8 @@ struct VegasArgs {
   int nb;
   int pstride;   // doubles per workgroup partial row
   int hcopies;   // histogram copies in LDS: 4 per wave, one per wave, or 1 (shared)
-  int narrow;    // the sample loop may run on 32-bit indices (see narrow_ok)
   double nbD;    // nb^dim, the Jacobian's constant factor
+  double sc;     // nb 2^-32: t = u nb = (word + 1/2) sc
 };
 
 // Histogram copies a workgroup keeps in LDS: one per wave when they fit in
@@ -77,8 +77,12 @@ struct PhiloxSrc {
     philox_uniforms<D>((uint64_t)(first + i), it, sid, k0, k1, u);
     return 1.0;
   }
-  // scaled coordinates t = u N = (k + 1/2) N 2^-32 of counter (c0, c1), one
-  // FMA each (exact: k N 2^-32 has at most 40 significant bits)
+  // scaled coordinates t = u N = (k + 1/2) N 2^-32 of counter (c0, c1), exact
+  // (k N 2^-32 has at most 40 significant bits): one FMA with the two
+  // constants in registers, or (LEAN, for register-bound kernels) k + 1/2
+  // (an inline constant) times the uniform scale, two instructions and no
+  // vector registers for the constants
+  template <bool LEAN>
   __device__ __forceinline__ double get_t_c(uint32_t c0, uint32_t c1, double sc, double hf, double (&t)[D]) const {
 #pragma unroll
     for (int b = 0; b < (D + 3) / 4; ++b) {
@@ -86,18 +90,23 @@ struct PhiloxSrc {
       const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (4 * b + e < D) t[4 * b + e < D ? 4 * b + e : 0] = fma((double)ww[e], sc, hf);
+        if (4 * b + e < D)
+          t[4 * b + e < D ? 4 * b + e : 0] = LEAN ? ((double)ww[e] + 0.5) * sc : fma((double)ww[e], sc, hf);
     }
     return 1.0;
   }
-  __device__ __forceinline__ double get_t(int64_t i, double nbd, double sc, double hf, double (&t)[D]) const {
-    const uint64_t c = (uint64_t)(first + i);
-    return get_t_c((uint32_t)c, (uint32_t)(c >> 32), sc, hf, t);
+  // Samples are taken in segments within which the low counter word does
+  // not carry: 32-bit indices i, counter (first + base) + i, at most 2^31
+  // per segment (so that i + grid stride cannot wrap either).
+  __host__ __device__ __forceinline__ int64_t seg_len(int64_t base, int64_t left) const {
+    const int64_t room = ((int64_t)1 << 31) - (int64_t)((uint64_t)(first + base) & 0x7FFFFFFFu);
+    return left < room ? left : room;
   }
-  // 32-bit sample index; the caller guarantees that the low counter word
-  // does not carry (narrow_ok)
-  __device__ __forceinline__ double get_t32(uint32_t i, double nbd, double sc, double hf, double (&t)[D]) const {
-    return get_t_c((uint32_t)first + i, (uint32_t)((uint64_t)first >> 32), sc, hf, t);
+  template <bool LEAN>
+  __device__ __forceinline__ double get_t_seg(int64_t base, uint32_t i, double nbd, double sc, double hf,
+                                              double (&t)[D]) const {
+    const uint64_t c = (uint64_t)(first + base);
+    return get_t_c<LEAN>((uint32_t)c + i, (uint32_t)(c >> 32), sc, hf, t);
   }
 };
 
@@ -112,13 +121,16 @@ struct PointsSrc {
     for (int j = 0; j < D; ++j) u[j] = y[(int64_t)j * n + i];
     return logq ? exp(-logq[i]) : 1.0;
   }
-  __device__ __forceinline__ double get_t(int64_t i, double nbd, double sc, double hf, double (&t)[D]) const {
+  __host__ __device__ __forceinline__ int64_t seg_len(int64_t base, int64_t left) const {
+    return left < ((int64_t)1 << 31) ? left : ((int64_t)1 << 31);
+  }
+  template <bool LEAN>
+  __device__ __forceinline__ double get_t_seg(int64_t base, uint32_t i32, double nbd, double sc, double hf,
+                                              double (&t)[D]) const {
+    const int64_t i = base + i32;
 #pragma unroll
     for (int j = 0; j < D; ++j) t[j] = y[(int64_t)j * n + i] * nbd;
     return logq ? exp(-logq[i]) : 1.0;
-  }
-  __device__ __forceinline__ double get_t32(uint32_t i, double nbd, double sc, double hf, double (&t)[D]) const {
-    return get_t((int64_t)i, nbd, sc, hf, t);
   }
 };
 
@@ -141,8 +153,11 @@ struct MinWaves { static constexpr int value = 1; };
 template <class F>
 struct MinWaves<F, std::void_t<decltype(F::kMinWaves)>> { static constexpr int value = F::kMinWaves; };
 
-template <int D, class F, class Src, bool HIST>
-__global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasArgs a, F f, Src src,
+// Caller points (flow samples) carry a density and an index into memory:
+// the integrand's occupancy bound would make those kernels spill, so they
+// take none.
+template <int D, class F, class Src, bool HIST, bool WIDE = false>
+__global__ __launch_bounds__(BLOCK, Src::kInterior ? MinWaves<F>::value : 1) void k_vegas_iter(VegasArgs a, F f, Src src,
                                                                           double* __restrict__ partials) {
   extern __shared__ __align__(16) double lds[];
   const int nb = a.nb;
@@ -172,8 +187,7 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
 
   Comp c1, c2;
   double p1 = 0.0, p2 = 0.0;
-  int cnt = 0;
-  const double nbd = (double)nb, sc = nbd * 0x1p-32, hf = nbd * 0x1p-33;
+  const double nbd = (double)nb, sc = a.sc, hf = nbd * 0x1p-33;
   // one sample from its scaled coordinates and source weight
   auto sample = [&](const double (&t)[D], double ws) {
     double x[D];
@@ -184,32 +198,39 @@ __global__ __launch_bounds__(BLOCK, MinWaves<F>::value) void k_vegas_iter(VegasA
     const double w2 = w * w;
     p1 += w;
     p2 += w2;
-    if (++cnt == CHUNK) {
-      c1.add(p1);
-      c2.add(p2);
-      p1 = p2 = 0.0;
-      cnt = 0;
-    }
     if (HIST) {
 #pragma unroll
       for (int j = 0; j < D; ++j) atomicAdd(&hw[j * nb + idx[j]], w2);
     }
   };
-  if (a.narrow) {
-    // 32-bit indices (no 64-bit adds and compares in the loop)
-    const uint32_t n32 = (uint32_t)a.n, stride = gridDim.x * BLOCK;
-    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n32; i += stride) {
+  // 32-bit sample indices: no 64-bit adds and compares in the loop.  WIDE
+  // launches (the low counter word would carry, or more than 2^31 samples)
+  // run in segments that do not; each thread adds CHUNK of its samples into
+  // the compensated sums at a time.
+  const uint32_t stride = gridDim.x * BLOCK;
+  int cnt = 0;
+  auto run = [&](int64_t base, uint32_t len) {
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < len; i += stride) {
       double t[D];
-      const double ws = src.get_t32(i, nbd, sc, hf, t);
+      // integrands with LDS tables are register-bound (occupancy)
+      const double ws = src.template get_t_seg<F::kStage>(base, i, nbd, sc, hf, t);
       sample(t, ws);
+      if (++cnt == CHUNK) {
+        c1.add(p1);
+        c2.add(p2);
+        p1 = p2 = 0.0;
+        cnt = 0;
+      }
+    }
+  };
+  if constexpr (WIDE) {
+    for (int64_t base = 0; base < a.n;) {
+      const uint32_t len = (uint32_t)src.seg_len(base, a.n - base);
+      run(base, len);
+      base += len;
     }
   } else {
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += stride) {
-      double t[D];
-      const double ws = src.get_t(i, nbd, sc, hf, t);
-      sample(t, ws);
-    }
+    run(0, (uint32_t)a.n);
   }
   c1.add(p1);
   c2.add(p2);
@@ -632,16 +653,6 @@ vgx_status prepare_params(vgx_vegas* v, const vgx_vegas_cfg* c) {
   }
 }
 
-// The sample loop runs on 32-bit indices when they and the low Philox
-// counter word (first + i) can neither wrap nor carry: i + grid stride stays
-// below 2^32 for i < 2^31.
-template <int D>
-bool narrow_ok(const PhiloxSrc<D>& s, int64_t n) {
-  return s.first >= 0 && (int64_t)((uint64_t)s.first & 0xFFFFFFFFu) + n <= ((int64_t)1 << 31);
-}
-template <int D>
-bool narrow_ok(const PointsSrc<D>&, int64_t n) { return n <= ((int64_t)1 << 31); }
-
 double pow_int(double b, int e) {
   double r = 1.0;
   for (int k = 0; k < e; ++k) r *= b;
@@ -651,12 +662,16 @@ double pow_int(double b, int e) {
 // Launch helpers dispatching on (kind, prec, D).
 template <int D, class F, class Src, bool HIST>
 vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), narrow_ok(src, n) ? 1 : 0,
-              pow_int((double)v->nb, D)};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), pow_int((double)v->nb, D),
+              v->nb * 0x1p-32};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST, !F::kStage) + extra_lds_bytes(v);
-  hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
-                     v->partials);
+  if (src.seg_len(0, n) == n)  // one segment: the common case
+    hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST, false>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
+                       v->partials);
+  else
+    hipLaunchKernelGGL((k_vegas_iter<D, F, Src, HIST, true>), dim3(grid), dim3(BLOCK), lds, v->stream, a, f, src,
+                       v->partials);
   VGX_HIP(hipGetLastError());
   return VGX_OK;
 }
@@ -719,7 +734,8 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
 
 template <int D, class F>
 vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, const F& f, double* u, double* g) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), 0, pow_int((double)v->nb, D)};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), pow_int((double)v->nb, D),
+              v->nb * 0x1p-32};
   PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false, !F::kStage) + extra_lds_bytes(v);

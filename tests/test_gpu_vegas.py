@@ -378,3 +378,34 @@ def test_result_after_every_kind_of_update(vgx):
         check(1)
     finally:
         vgx.vegas_destroy(v)
+
+
+def test_launch_beyond_32_bit_counters(vgx):
+    """An iteration of 2^32 + 1000 samples runs in segments of at most 2^31
+    samples within which the low Philox counter word does not carry (the
+    last segment has counter high word 1).  Its sums less those of an
+    iteration of 2^32 samples are the sums of samples 2^32 .. 2^32 + 999,
+    which the oracle computes from their own counters."""
+    import math
+    dim, nb = 4, 50
+    n0 = 1 << 32
+    print(f"iteration of {n0} + 1000 samples (segmented counters)", flush=True)
+    e = rand_grid(dim, nb, 5)
+    sums = []
+    for n in (n0 + 1000, n0):
+        v = make(vgx, GAUSS, dim, nb, seed=C0["seed"], params=gauss_params(dim, 0.5, 0.1))
+        try:
+            vgx.vegas_set_grid(v, e)
+            r = vgx.vegas_iterate(v, n, 3)
+            assert r["n"] == n
+            sums.append((r["s1"], r["s2"]))
+        finally:
+            vgx.vegas_destroy(v)
+    idx = np.arange(n0, n0 + 1000, dtype=np.uint64)
+    u = sample_uniforms(C0["seed"], 0, 3, idx, dim)
+    x, jac, _ = ov.vegas_map(u, e)
+    w = gauss(x, 0.5, 0.1) * jac
+    # each GPU sum is compensated, so exact to about one unit in the last place
+    for k, ref in ((0, math.fsum(w)), (1, math.fsum(w * w))):
+        tol = 4 * math.ulp(sums[0][k]) + 1e-12 * abs(ref)
+        assert abs((sums[0][k] - sums[1][k]) - ref) <= tol, (k, sums[0][k] - sums[1][k], ref)
