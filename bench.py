@@ -842,7 +842,7 @@ def main():
             "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
             "traffic": measured_traffic(n),
             "traffic_unit": "bytes/launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE scaled by a 2 GiB copy)",
-            "kernel": "k_vegas_iter<3,TTbar,PhiloxSrc<3>,true>",
+            "kernel": "k_vegas_iter<3,TTbar,PhiloxSrc<3>,true,false>",
             "kernel_avg_ms": kern_avg_s * 1e3,
             "flops_per_event": FLOPS_PER_EVENT_F32,
             "events_per_launch": n,
