@@ -550,7 +550,7 @@ __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restri
   copy16(sb, bias, D.bias_total * 4);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (FWD_BLOCK / 64) + (threadIdx.x >> 6);
+  const int wave = (threadIdx.x >> 6) * gridDim.x + blockIdx.x;
   const int nwaves = gridDim.x * (FWD_BLOCK / 64);
   const int64_t ntiles = (a.n + 63) / 64;  // tile pairs
   const int d = D.d;
@@ -632,28 +632,45 @@ __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restri
   }
 }
 
-// loss L = sum r / sum g^2, scale = -1/sum g^2 (fixed-order reduction)
-__global__ __launch_bounds__(256) void k_flow_loss(const double* __restrict__ partials, int rows, double* __restrict__ out) {
-  __shared__ double ps[4][64], pc[4][64];
-  __shared__ double sh[4];
-  const int col = threadIdx.x & 3, grp = threadIdx.x >> 2;  // 64 row groups per column
-  Comp c;
-  for (int r = grp; r < rows; r += 64) c.add(partials[r * 4 + col]);
-  ps[col][grp] = c.s;
-  pc[col][grp] = c.c;
+// loss L = sum r / sum g^2, scale = -1/sum g^2 and the ok flag from the
+// forward's partial rows [rows][4] (fixed-order compensated reduction by the
+// first 256 threads of a workgroup of at least 256; lds: 520 doubles).
+// Every thread of the workgroup must call it; all get the three values.
+__device__ __forceinline__ void loss_reduce(const double* __restrict__ partials, int rows, double* lds,
+                                            double (&out)[3]) {
+  double* ps = lds;        // [4][64]
+  double* pc = lds + 256;  // [4][64]
+  double* sh = lds + 512;  // [4]
+  if (threadIdx.x < 256) {
+    const int col = threadIdx.x & 3, grp = threadIdx.x >> 2;  // 64 row groups per column
+    Comp c;
+    for (int r = grp; r < rows; r += 64) c.add(partials[r * 4 + col]);
+    ps[col * 64 + grp] = c.s;
+    pc[col * 64 + grp] = c.c;
+  }
   __syncthreads();
   if (threadIdx.x < 4) {
     Comp t;
-    for (int g = 0; g < 64; ++g) { t.add(ps[threadIdx.x][g]); t.add(pc[threadIdx.x][g]); }
+    for (int g = 0; g < 64; ++g) { t.add(ps[threadIdx.x * 64 + g]); t.add(pc[threadIdx.x * 64 + g]); }
     sh[threadIdx.x] = t.value();
   }
   __syncthreads();
+  const double sr = sh[0] + sh[1], sg = sh[2] + sh[3];
+  const double L = sr / sg;
+  out[0] = L;
+  out[1] = -1.0 / sg;
+  out[2] = (isfinite(L) && sg > 0.0) ? 1.0 : 0.0;
+  __syncthreads();  // the scratch may be reused
+}
+
+__global__ __launch_bounds__(256) void k_flow_loss(const double* __restrict__ partials, int rows, double* __restrict__ out) {
+  __shared__ double lds[520];
+  double v[3];
+  loss_reduce(partials, rows, lds, v);
   if (threadIdx.x == 0) {
-    const double sr = sh[0] + sh[1], sg = sh[2] + sh[3];
-    const double L = sr / sg;
-    out[0] = L;
-    out[1] = -1.0 / sg;
-    out[2] = (isfinite(L) && sg > 0.0) ? 1.0 : 0.0;
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
   }
 }
 
@@ -671,6 +688,9 @@ struct BwdArgs {
   const double* loss;   // [3]: L, scale, ok
   void* scr;            // operand tiles (OP::S elements)
   int srows;            // scratch rows per tile
+  const double* partials;  // fused kernel: the forward's partial rows [prows][4], or null (loss read
+  int prows;               // from loss); with them every workgroup reduces the loss itself and
+  double* loss_out;        // workgroup 0 stores it to loss_out [3]
 };
 
 template <class OP>
@@ -968,106 +988,272 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_wgrad(const FlowDesc* __restric
 // ---------------------------------------------------------------------------
 // Fused backward and weight gradients of one layer (|B| <= 4).
 //
-// The workgroup's four waves take four 32-sample tiles at a time.  Each wave
-// runs the backward of its tile as k_flow_bwd does; the operands of the
-// weight-gradient products (deltas and activations, feature-major) go to an
-// LDS stage instead of global memory, one product at a time: [dlogit | h2],
-// then [dpre2 | h1], then [dpre1 | zA].  After each stage the four waves
-// contract the four tiles (K = 128 samples) into the weight-gradient tiles
-// they own: output tile tau of [dW3 (2 |B|) | dW2 (4) | dW1 (2)] belongs to
-// wave tau mod 4, whose accumulators persist over all the tiles of the
-// workgroup.  Each workgroup finally stores its partial of the layer's
-// parameter block (every element from its one owner: no LDS reduction), in
-// the layout k_flow_wgrad writes.
+// The workgroup's WV waves (8 where the stages fit the LDS, two per SIMD,
+// else 4) take WV 32-sample tiles at a time (a group).  Each wave runs the
+// backward of its tile as k_flow_bwd does; the operands
+// of the weight-gradient products (deltas and activations, feature-major)
+// go to an LDS stage instead of global memory, one product at a time:
+// [dlogit | h2], then [dpre2 | h1], then [dpre1 | zA].  After each stage the
+// waves contract the group's tiles (K = 32 WV samples) into the
+// weight-gradient tiles they own: output tile tau of [dW3 (2 |B|) | dW2 (4) |
+// dW1 (2)] belongs to wave tau mod WV, whose accumulators persist over all
+// the tiles of the workgroup.  Each workgroup finally stores its partial of
+// the layer's parameter block (every element from its one owner: no LDS
+// reduction), in the layout k_flow_wgrad writes.  The next group's inputs
+// are loaded while the current one is processed.  |B| is a template
+// parameter, and the layer's coordinate sets are addressed through per-lane
+// LDS pointers set up once, so the loop over groups has no branches on the
+// layer's shape and reads nothing from its descriptor.
+//
+// Activations and deltas between the products stay in operand form (eight
+// BF16 values per fragment): the ReLU, its derivative's mask and the bias
+// sums work on packed pairs.
 // ---------------------------------------------------------------------------
-constexpr int FUSE_WAVES = 4;
+constexpr int FUSE_DMAX = 8;  // |B| <= 4 holds exactly for d <= 8
 
-// rows of a stage: the largest of (32 |B|max + 64), 128 and 96
-__host__ __device__ constexpr int fuse_stage_rows(int nbm) { return 32 * nbm + 64 > 128 ? 32 * nbm + 64 : 128; }
+// rows of a tile's stage: the largest of (32 |B| + 64), 128 and 96
+__host__ __device__ constexpr int fuse_stage_rows(int nb) { return 32 * nb + 64 > 128 ? 32 * nb + 64 : 128; }
 // row stride of a stage in elements: 32 samples, + 16 bytes of padding for
 // BF16 stages (the FP32 validation stages go without, to fit the LDS)
 template <class OP>
 __host__ __device__ constexpr int fuse_rs() { return sizeof(typename OP::S) == 2 ? 40 : 32; }
 
-// LDS of the fused kernel: packs and biases | z, dz columns [2][d][FBLOCK] |
-// stage [FUSE_WAVES][rows][rs]
+// LDS of the fused kernel with bs threads: packs and biases | per-lane
+// columns [2 d + 2][bs] (z, its gradient, a zero column, a sink column) |
+// stage [bs / 64][rows][rs]
 __host__ __device__ inline size_t fuse_z_offset(int fw_len, int bw_len, int bias_len, int es) {
   return bwd_z_offset(fw_len, bw_len, bias_len, es);
 }
-__host__ __device__ inline size_t fuse_stage_offset(int fw_len, int bw_len, int bias_len, int es, int d) {
-  return fuse_z_offset(fw_len, bw_len, bias_len, es) + sizeof(float) * 2 * (size_t)d * FBLOCK;
+__host__ __device__ inline size_t fuse_stage_offset(int fw_len, int bw_len, int bias_len, int es, int d, int bs) {
+  return fuse_z_offset(fw_len, bw_len, bias_len, es) + sizeof(float) * (2 * (size_t)d + 2) * bs;
 }
 
-// one 32x32 D tile into a stage, feature-major (row = feature, column = sample)
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU, ReLU-derivative mask and element sum of an operand fragment.
 template <class OP>
-__device__ __forceinline__ void stage_tile(typename OP::S* st, int row0, const f32x16& c, int s, int h) {
+struct FragOps;
+
+template <>
+struct FragOps<OpBF16> {
+  using frag = bf16x8;
+  // a BF16 value is negative exactly when its bits are, read as a signed
+  // 16-bit integer: max with 0 on packed pairs is the ReLU (v_pk_max_i16)
+  static __device__ __forceinline__ void relu(frag& f) {
+    const s16x8 x = __builtin_elementwise_max(__builtin_bit_cast(s16x8, f), (s16x8)0);
+    f = __builtin_bit_cast(frag, x);
+  }
+  // d = (h > 0) ? d : 0 per element, for h >= 0 (a ReLU output): min(h, 1)
+  // is 1 for every non-zero h and 0 for +0, and multiplies the bits of d
+  static __device__ __forceinline__ void mask(frag& d, const frag& h) {
+    u32x4v dv = __builtin_bit_cast(u32x4v, d);
+    const u32x4v hv = __builtin_bit_cast(u32x4v, h);
+    const unsigned one2 = 0x00010001u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      unsigned r;
+      asm("v_pk_min_u16 %0, %1, %2\n\tv_pk_mul_lo_u16 %0, %3, %0" : "=&v"(r) : "v"(hv[k]), "v"(one2), "v"(dv[k]));
+      dv[k] = r;
+    }
+    d = __builtin_bit_cast(frag, dv);
+  }
+  // acc + the sum of the eight elements (v_dot2 with ones)
+  static __device__ __forceinline__ float sum(const frag& f, float acc) {
+    const u32x4v v = __builtin_bit_cast(u32x4v, f);
+    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const unsigned w = v[k];
+      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), one, acc, false);
+    }
+    return acc;
+  }
+  // (whole vectors are bit_cast, then indexed: a bit_cast of one element
+  // f[e] compiles to element 0)
+  static __device__ __forceinline__ unsigned short bits(const frag& f, int e) {
+    const u16x8 u = __builtin_bit_cast(u16x8, f);
+    return u[e];
+  }
+};
+
+template <>
+struct FragOps<OpF32> {
+  using frag = f32x8;
+  static __device__ __forceinline__ void relu(frag& f) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = fmaxf(f[e], 0.0f);
+  }
+  static __device__ __forceinline__ void mask(frag& d, const frag& h) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = h[e] > 0.0f ? d[e] : 0.0f;
+  }
+  static __device__ __forceinline__ float sum(const frag& f, float acc) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += f[e];
+    return acc;
+  }
+  static __device__ __forceinline__ float bits(const frag& f, int e) { return f[e]; }
+};
+
+// the two hidden layers of the network for the wave's 32 samples as operand
+// fragments (ReLU applied): h1b for the second product, h2b for the output;
+// za holds zeros beyond |A|
+template <class OP>
+__device__ __forceinline__ void mlp_hidden_fb(const float (&za)[FAB], const LayerLds<OP>& W, typename OP::frag (&h1b)[4],
+                                              typename OP::frag (&h2b)[4]) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  typename OP::frag bz;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) OP::set(bz, e, h == 0 ? za[e] : 0.0f);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const f32x16 p = OP::mma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
+    h1b[2 * t] = to_b<OP>(p, 0);
+    h1b[2 * t + 1] = to_b<OP>(p, 1);
+    FragOps<OP>::relu(h1b[2 * t]);
+    FragOps<OP>::relu(h1b[2 * t + 1]);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16 acc = bias_tile(W.b2 + 32 * t, h);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = OP::mma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], h1b[kk], acc);
+    h2b[2 * t] = to_b<OP>(acc, 0);
+    h2b[2 * t + 1] = to_b<OP>(acc, 1);
+    FragOps<OP>::relu(h2b[2 * t]);
+    FragOps<OP>::relu(h2b[2 * t + 1]);
+  }
+}
+
+// fragment kk of a 32-row block into a stage, feature-major (row = feature,
+// column = sample): element e holds row row0 + drow(8 (kk & 1) + e, h)
+template <class OP>
+__device__ __forceinline__ void stage_put(typename OP::S* st, int row0, const typename OP::frag& f, int half, int s,
+                                          int h) {
   constexpr int RS = fuse_rs<OP>();
 #pragma unroll
-  for (int v = 0; v < 16; ++v) st[(row0 + drow(v, h)) * RS + s] = OP::store(c[v]);
+  for (int e = 0; e < 8; ++e) st[(row0 + drow(8 * half + e, h)) * RS + s] = FragOps<OP>::bits(f, e);
 }
 
 template <class OP>
-__device__ __forceinline__ typename OP::frag stage_frag(const typename OP::S* st, int row, int kk, int h) {
+__device__ __forceinline__ typename OP::frag stage_get(const typename OP::S* st, int row, int kk, int h) {
   constexpr int RS = fuse_rs<OP>();
   return *(const typename OP::frag*)(st + row * RS + 16 * kk + 8 * h);
 }
 
-// contract the four waves' stages: A rows arow0 + 32 m, B rows brow0 + 32 n
-template <class OP>
-__device__ __forceinline__ void fuse_contract(const typename OP::S* stage, int srows, int arow0, int brow0, int m,
-                                              int n, f32x16& acc, float& bsum) {
+// contract the group's NST stages: A rows arow0 + 32 m, B rows brow0 + 32 n
+template <class OP, int NST, int SR>
+__device__ __forceinline__ void fuse_contract(const typename OP::S* stage, int arow0, int brow0, int m, int n,
+                                              f32x16& acc, float& bsum) {
   constexpr int RS = fuse_rs<OP>();
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
 #pragma unroll
-  for (int q = 0; q < FUSE_WAVES; ++q) {
-    const typename OP::S* st = stage + (size_t)q * srows * RS;
+  for (int q = 0; q < NST; ++q) {
+    const typename OP::S* st = stage + (size_t)q * SR * RS;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      const typename OP::frag af = stage_frag<OP>(st, arow0 + 32 * m + i, kk, h);
-      const typename OP::frag bf = stage_frag<OP>(st, brow0 + 32 * n + i, kk, h);
-      if (n == 0) bsum += frag_sum<OP>(af);
+      const typename OP::frag af = stage_get<OP>(st, arow0 + 32 * m + i, kk, h);
+      const typename OP::frag bf = stage_get<OP>(st, brow0 + 32 * n + i, kk, h);
+      if (n == 0) bsum = FragOps<OP>::sum(af, bsum);
       acc = OP::mma(af, bf, acc);
     }
   }
 }
 
-template <int NBM, class OP>
-__global__ __launch_bounds__(FBLOCK) void k_flow_bwdw(const FlowDesc* __restrict__ Dp, BwdArgs a,
+template <int NB, int WV, class OP>
+__global__ __launch_bounds__(64 * WV) void k_flow_bwdw(const FlowDesc* __restrict__ Dp, BwdArgs a,
                                                      const typename OP::S* __restrict__ fw,
                                                      const typename OP::S* __restrict__ bw,
                                                      const float* __restrict__ bias, float* __restrict__ gpart) {
-  static_assert(NBM <= 4, "the fused kernel holds at most four weight-gradient tiles per wave");
+  static_assert(NB >= 1 && NB <= 4, "the fused kernel holds at most four weight-gradient tiles per wave");
   using S = typename OP::S;
   using frag = typename OP::frag;
-  constexpr int SR = fuse_stage_rows(NBM);
+  using FO = FragOps<OP>;
+  constexpr int SR = fuse_stage_rows(NB);
   constexpr int RS = fuse_rs<OP>();
-  constexpr int OWN = (2 * NBM + 6 + FUSE_WAVES - 1) / FUSE_WAVES;  // output tiles per wave
+  constexpr int BS = 64 * WV;
+  constexpr int T3 = 2 * NB, T = 2 * NB + 6;
+  constexpr int OWN = (T + WV - 1) / WV;  // output tiles per wave
   extern __shared__ __align__(16) unsigned char flds[];
   const FlowDesc& D = *Dp;
   const FlowLayerDesc& L = D.l[a.layer];
+  const int d = D.d;
+  const int es = (int)sizeof(S);
+  const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = a.n;
+  const int64_t ntiles = (n + 31) / 32;
+  const int64_t ngroups = (ntiles + WV - 1) / WV;
+  // the inputs of the wave's tile of group g: coordinates z, incoming
+  // gradient, the sample's loss term; a tile past the end has no valid
+  // sample: zero deltas, nothing added.  Every load reads a valid address
+  // (coordinates j >= d repeat d - 1, samples past the end read sample 0).
+  const float* dzsrc = a.dzout ? a.dzout : a.zin;
+  const float dzs = a.dzout ? 1.0f : 0.0f;
+  float pz[FUSE_DMAX], pd[FUSE_DMAX];
+  double pr;
+  auto fetch = [&](int64_t g) {
+    const int64_t i = (g * WV + wave) * 32 + s;
+    const bool ok = g < ngroups && i < n;
+    const int64_t ic = ok ? i : 0;
+#pragma unroll
+    for (int j = 0; j < FUSE_DMAX; ++j) {
+      const int64_t jj = j < d ? j : d - 1;
+      const float zv = a.zin[jj * n + ic], dv = dzsrc[jj * n + ic];
+      pz[j] = ok ? zv : 0.5f;
+      pd[j] = ok ? dv * dzs : 0.0f;
+    }
+    const double rv = a.rsave[ic];
+    pr = ok ? rv : 0.0;
+  };
+  if (n > 0) fetch(blockIdx.x);
   S* sfw = (S*)flds;
   S* sbw = sfw + L.fw_len;
   float* sb = (float*)(sbw + L.bw_len);
-  const int d = D.d;
-  const int es = (int)sizeof(S);
-  float* z = (float*)(flds + fuse_z_offset(L.fw_len, L.bw_len, L.bias_len, es)) + threadIdx.x;
-  float* dz = z + d * FBLOCK;
-  S* stage = (S*)(flds + fuse_stage_offset(L.fw_len, L.bw_len, L.bias_len, es, d));
+  // the lane's own LDS columns, BS apart: z_j at zc[j], its gradient at
+  // zc[d + j], zero at zc[2 d], a sink for unused writes at zc[2 d + 1]
+  float* zc = (float*)(flds + fuse_z_offset(L.fw_len, L.bw_len, L.bias_len, es)) + threadIdx.x;
+  S* stage = (S*)(flds + fuse_stage_offset(L.fw_len, L.bw_len, L.bias_len, es, d, BS));
   copy16(sfw, fw + L.fw_off, L.fw_len * es);
   copy16(sbw, bw + L.bw_off, L.bw_len * es);
   copy16(sb, bias + L.bias_off, L.bias_len * 4);
+  zc[2 * d * BS] = 0.0f;
+  // per-lane pointers to the columns of the layer's coordinate sets
+  const float* zap[FAB];
+  float* dzap[FAB];
+#pragma unroll
+  for (int e = 0; e < FAB; ++e) {
+    const int ai = L.a_idx[e];
+    const bool act = e < L.na;
+    zap[e] = zc + (act ? ai : 2 * d) * BS;
+    dzap[e] = zc + (act ? d + ai : 2 * d + 1) * BS;
+  }
+  float* zbp[NB];
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) zbp[jb] = zc + L.b_idx[jb] * BS;
   __syncthreads();
   const LayerLds<OP> W = layer_lds<OP>(sfw, sb, L, L.fw_off, L.bias_off);
-  const frag* w3t = (const frag*)sbw;                         // [2][2nb][32][2]
-  const frag* w2t = (const frag*)(sbw + L.nb * 2048);         // [2][4][32][2]
-  const frag* w1t = (const frag*)(sbw + L.nb * 2048 + 4096);  // [1][4][32][2]
-  const double scale = a.loss[1];
-  const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
-  const int wave = threadIdx.x >> 6;
+  const frag* w3t = (const frag*)sbw;                       // [2][2 NB][32][2]
+  const frag* w2t = (const frag*)(sbw + NB * 2048);         // [2][4][32][2]
+  const frag* w1t = (const frag*)(sbw + NB * 2048 + 4096);  // [1][4][32][2]
+  double scale;
+  if (a.partials) {
+    // the stage is free until the first group: scratch of the loss reduction
+    double lv[3];
+    loss_reduce(a.partials, a.prows, (double*)stage, lv);
+    scale = lv[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.loss_out[0] = lv[0];
+      a.loss_out[1] = lv[1];
+      a.loss_out[2] = lv[2];
+    }
+  } else {
+    scale = a.loss[1];
+  }
   S* mystage = stage + (size_t)wave * SR * RS;
-  const int64_t ntiles = (a.n + 31) / 32;
-  const int na = L.na, nb = L.nb;
-  const int T3 = 2 * nb, T = 2 * nb + 6;
   f32x16 acc[OWN];
   float bsum[OWN];
 #pragma unroll
@@ -1075,121 +1261,115 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwdw(const FlowDesc* __restrict
     acc[k] = zero16();
     bsum[k] = 0.0f;
   }
-  for (int64_t g = blockIdx.x; g * FUSE_WAVES < ntiles; g += gridDim.x) {
-    // tiles past the end run with no valid sample: zero deltas, nothing added
-    const int64_t t = g * FUSE_WAVES + wave;
-    const int64_t i = t * 32 + s;
-    const bool valid = i < a.n;
-    for (int j = 0; j < d; ++j) {
-      z[j * FBLOCK] = valid ? a.zin[(int64_t)j * a.n + i] : 0.5f;
-      dz[j * FBLOCK] = (valid && a.dzout) ? a.dzout[(int64_t)j * a.n + i] : 0.0f;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    // the prefetched inputs into the lane's columns (coordinates j >= d
+    // write column d - 1 again, with its own value)
+#pragma unroll
+    for (int j = 0; j < FUSE_DMAX; ++j) {
+      const int jj = j < d ? j : d - 1;
+      zc[jj * BS] = pz[j];
+      zc[(d + jj) * BS] = pd[j];
     }
-    const float dlq = valid ? (float)(a.rsave[i] * scale) : 0.0f;
+    const float dlq = (float)(pr * scale);
     float za[FAB];
 #pragma unroll
-    for (int e = 0; e < FAB; ++e) za[e] = (e < na) ? z[L.a_idx[e] * FBLOCK] : 0.0f;
-    f32x16 h1[2], h2[2], lg[NBM];
-    mlp_fwd<NBM, OP>(za, na, nb, W, h1, h2, lg);
-    unsigned m1[2] = {0u, 0u}, m2[2] = {0u, 0u};
+    for (int e = 0; e < FAB; ++e) za[e] = *zap[e];
+    fetch(g + gridDim.x);  // in flight while this group is processed
+    // network forward, then bins, dQ and dlogit per transformed dim (the
+    // incoming gradient of z_j is its column before this layer's update)
+    frag h1b[4], h2b[4], dlb[2 * NB];
+    mlp_hidden_fb<OP>(za, W, h1b, h2b);
 #pragma unroll
-    for (int to = 0; to < 2; ++to)
+    for (int jb = 0; jb < NB; ++jb) {
+      f32x16 q = mlp_logits<OP>(h2b, jb, W);
+      softmax32(q);
+      float* zj = zbp[jb];
+      float* dzj = zj + d * BS;
+      int b;
+      float al, qb;
+      cdf_fwd(q, *zj, b, al, qb);
+      const float g_out = *dzj;
+      float dq[16];
+      float sdot = 0.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        m1[to] |= (h1[to][v] > 0.0f ? 1u : 0u) << v;
-        m2[to] |= (h2[to][v] > 0.0f ? 1u : 0u) << v;
+        const int k = drow(v, h);
+        dq[v] = g_out * ((k < b) ? 1.0f : ((k == b) ? al : 0.0f)) + ((k == b) ? dlq / qb : 0.0f);
+        sdot += q[v] * dq[v];
       }
-    // bins, dQ and dlogit per transformed dim (the incoming gradient of z_j
-    // is dz[j] before this layer's update)
+      sdot += xor32(sdot);
 #pragma unroll
-    for (int jb = 0; jb < NBM; ++jb) {
-      if (jb < nb) {
-        softmax32(lg[jb]);
-        const int j = L.b_idx[jb];
-        int b;
-        float al, qb;
-        cdf_fwd(lg[jb], z[j * FBLOCK], b, al, qb);
-        const float g_out = dz[j * FBLOCK];
-        float dq[16];
-        float sdot = 0.0f;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int k = drow(v, h);
-          dq[v] = g_out * ((k < b) ? 1.0f : ((k == b) ? al : 0.0f)) + ((k == b) ? dlq / qb : 0.0f);
-          sdot += lg[jb][v] * dq[v];
-        }
-        sdot += xor32(sdot);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) lg[jb][v] = lg[jb][v] * (dq[v] - sdot);  // dlogit
-        dz[j * FBLOCK] = g_out * (float)FK * qb;
-      }
+      for (int v = 0; v < 16; ++v) q[v] = q[v] * (dq[v] - sdot);  // dlogit
+      dlb[2 * jb] = to_b<OP>(q, 0);
+      dlb[2 * jb + 1] = to_b<OP>(q, 1);
+      *dzj = g_out * (float)FK * qb;
     }
-    // stage 1: [dlogit rows 0 .. 32 nb | h2 rows 32 NBM ..]; dW3, db3
+    // stage 1: [dlogit rows 0 .. 32 NB | h2 rows 32 NB .. 32 NB + 64]; dW3, db3
 #pragma unroll
-    for (int jb = 0; jb < NBM; ++jb)
-      if (jb < nb) stage_tile<OP>(mystage, 32 * jb, lg[jb], s, h);
-    stage_tile<OP>(mystage, 32 * NBM, h2[0], s, h);
-    stage_tile<OP>(mystage, 32 * NBM + 32, h2[1], s, h);
+    for (int kk = 0; kk < 2 * NB; ++kk) stage_put<OP>(mystage, 32 * (kk >> 1), dlb[kk], kk & 1, s, h);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) stage_put<OP>(mystage, 32 * NB + 32 * (kk >> 1), h2b[kk], kk & 1, s, h);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
-      const int tau = wave + FUSE_WAVES * k;
-      if (tau < T3) fuse_contract<OP>(stage, SR, 0, 32 * NBM, tau >> 1, tau & 1, acc[k], bsum[k]);
+      const int tau = wave + WV * k;
+      if (tau < T3) fuse_contract<OP, WV, SR>(stage, 0, 32 * NB, tau >> 1, tau & 1, acc[k], bsum[k]);
     }
     __syncthreads();
-    // dh2 = W3^T dlogit, masked by relu'
-    f32x16 d2[2];
+    // dh2 = W3^T dlogit, masked by relu'; stage 2: [dpre2 rows 0 .. 64 | h1 rows 64 .. 128]
+    frag d2b[4];
 #pragma unroll
     for (int to = 0; to < 2; ++to) {
       f32x16 ac = zero16();
 #pragma unroll
-      for (int kk = 0; kk < 2 * NBM; ++kk)
-        if (kk < 2 * nb) ac = OP::mma(w3t[((to * 2 * nb + kk) * 32 + s) * 2 + h], to_b<OP>(lg[kk >> 1], kk & 1), ac);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) ac[v] = ((m2[to] >> v) & 1u) ? ac[v] : 0.0f;
-      d2[to] = ac;
+      for (int kk = 0; kk < 2 * NB; ++kk) ac = OP::mma(w3t[((to * 2 * NB + kk) * 32 + s) * 2 + h], dlb[kk], ac);
+      d2b[2 * to] = to_b<OP>(ac, 0);
+      d2b[2 * to + 1] = to_b<OP>(ac, 1);
+      FO::mask(d2b[2 * to], h2b[2 * to]);
+      FO::mask(d2b[2 * to + 1], h2b[2 * to + 1]);
     }
-    // stage 2: [dpre2 rows 0 .. 64 | h1 rows 64 .. 128]; dW2, db2
-    stage_tile<OP>(mystage, 0, d2[0], s, h);
-    stage_tile<OP>(mystage, 32, d2[1], s, h);
-    stage_tile<OP>(mystage, 64, h1[0], s, h);
-    stage_tile<OP>(mystage, 96, h1[1], s, h);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      stage_put<OP>(mystage, 32 * (kk >> 1), d2b[kk], kk & 1, s, h);
+      stage_put<OP>(mystage, 64 + 32 * (kk >> 1), h1b[kk], kk & 1, s, h);
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
-      const int tau = wave + FUSE_WAVES * k - T3;
-      if (tau >= 0 && tau < 4) fuse_contract<OP>(stage, SR, 0, 64, tau >> 1, tau & 1, acc[k], bsum[k]);
+      const int tau = wave + WV * k - T3;
+      if (tau >= 0 && tau < 4) fuse_contract<OP, WV, SR>(stage, 0, 64, tau >> 1, tau & 1, acc[k], bsum[k]);
     }
     __syncthreads();
-    // dh1 = W2^T dpre2, masked
-    f32x16 d1[2];
+    // dh1 = W2^T dpre2, masked; stage 3: [dpre1 rows 0 .. 64 | zA rows 64 .. 96, rows >= |A| zero]
+    frag d1b[4];
 #pragma unroll
     for (int to = 0; to < 2; ++to) {
       f32x16 ac = zero16();
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) ac = OP::mma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], to_b<OP>(d2[kk >> 1], kk & 1), ac);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) ac[v] = ((m1[to] >> v) & 1u) ? ac[v] : 0.0f;
-      d1[to] = ac;
+      for (int kk = 0; kk < 4; ++kk) ac = OP::mma(w2t[((to * 4 + kk) * 32 + s) * 2 + h], d2b[kk], ac);
+      d1b[2 * to] = to_b<OP>(ac, 0);
+      d1b[2 * to + 1] = to_b<OP>(ac, 1);
+      FO::mask(d1b[2 * to], h1b[2 * to]);
+      FO::mask(d1b[2 * to + 1], h1b[2 * to + 1]);
     }
-    // stage 3: [dpre1 rows 0 .. 64 | zA rows 64 .. 96, rows >= |A| zero]; dW1, db1
-    stage_tile<OP>(mystage, 0, d1[0], s, h);
-    stage_tile<OP>(mystage, 32, d1[1], s, h);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) stage_put<OP>(mystage, 32 * (kk >> 1), d1b[kk], kk & 1, s, h);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const float val = (e < FAB && h == 0 && e < na) ? za[e & (FAB - 1)] : 0.0f;
+      const float val = (e < FAB && h == 0) ? za[e & (FAB - 1)] : 0.0f;
       mystage[(64 + 16 * h + e) * RS + s] = OP::store(val);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < OWN; ++k) {
-      const int tau = wave + FUSE_WAVES * k - T3 - 4;
-      if (tau >= 0 && tau < 2) fuse_contract<OP>(stage, SR, 0, 64, tau, 0, acc[k], bsum[k]);
+      const int tau = wave + WV * k - T3 - 4;
+      if (tau >= 0 && tau < 2) fuse_contract<OP, WV, SR>(stage, 0, 64, tau, 0, acc[k], bsum[k]);
     }
     __syncthreads();
     // dzA = W1^T dpre1: rows a = 4h + r in registers 0..3
     f32x16 d0 = zero16();
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) d0 = OP::mma(w1t[(kk * 32 + s) * 2 + h], to_b<OP>(d1[kk >> 1], kk & 1), d0);
+    for (int kk = 0; kk < 4; ++kk) d0 = OP::mma(w1t[(kk * 32 + s) * 2 + h], d1b[kk], d0);
     float dza[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1198,19 +1378,20 @@ __global__ __launch_bounds__(FBLOCK) void k_flow_bwdw(const FlowDesc* __restrict
       dza[4 + r] = h == 0 ? other : mine;
     }
 #pragma unroll
-    for (int e = 0; e < FAB; ++e)
-      if (e < na) dz[L.a_idx[e] * FBLOCK] += dza[e];
-    if (valid && h == 0) {
-      for (int j = 0; j < d; ++j) a.dzin[(int64_t)j * a.n + i] = dz[j * FBLOCK];
+    for (int e = 0; e < FAB; ++e) *dzap[e] += dza[e];
+    const int64_t i = (g * WV + wave) * 32 + s;
+    if (i < n && h == 0) {
+      for (int j = 0; j < d; ++j) a.dzin[(int64_t)j * n + i] = zc[(d + j) * BS];
     }
   }
   // the workgroup's partial of the parameter block, each element from its owner
   float* out = gpart + (size_t)blockIdx.x * L.n_par;
-  const int oW1 = 0, ob1 = FH * na, oW2 = ob1 + FH, ob2 = oW2 + FH * FH, oW3 = ob2 + FH, ob3 = oW3 + nb * FK * FH;
+  const int na = L.na;
+  const int oW1 = 0, ob1 = FH * na, oW2 = ob1 + FH, ob2 = oW2 + FH * FH, oW3 = ob2 + FH, ob3 = oW3 + NB * FK * FH;
   const int i32 = lane & 31;
 #pragma unroll
   for (int k = 0; k < OWN; ++k) {
-    const int tau = wave + FUSE_WAVES * k;
+    const int tau = wave + WV * k;
     if (tau >= T) continue;
     int wo, bo, ld, ncol, m, n;
     if (tau < T3) { wo = oW3; bo = ob3; ld = FH; ncol = FH; m = tau >> 1; n = tau & 1; }
@@ -1268,8 +1449,18 @@ struct AdamArgs {
   float lr, beta1, beta2, eps;
   int step;              // t >= 1
   int do_adam;
+  // with Adam: the positions of each parameter in the forward and backward
+  // packs and the bias vector (-1: none), updated with the new weight in
+  // place of a full re-pack (null: the caller re-packs)
+  const int* fw_dst;
+  const int* bw_dst;
+  const int* b_dst;
+  void* fw;
+  void* bw;
+  float* bias;
 };
 
+template <class OP>
 __global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ Dp, AdamArgs a) {
   const FlowDesc& D = *Dp;
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1290,7 +1481,14 @@ __global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ 
   a.v[p] = v;
   const float mh = m / (1.0f - powf(a.beta1, (float)a.step));
   const float vh = v / (1.0f - powf(a.beta2, (float)a.step));
-  a.master[p] -= a.lr * mh / (sqrtf(vh) + a.eps);
+  const float w = a.master[p] - a.lr * mh / (sqrtf(vh) + a.eps);
+  a.master[p] = w;
+  if (a.fw_dst) {
+    const int kf = a.fw_dst[p], kb = a.bw_dst[p], kc = a.b_dst[p];
+    if (kf >= 0) ((typename OP::S*)a.fw)[kf] = OP::store(w);
+    if (kb >= 0) ((typename OP::S*)a.bw)[kb] = OP::store(w);
+    if (kc >= 0) a.bias[kc] = w;
+  }
 }
 
 // master FP32 weights -> permuted operand packs (OP::S) and FP32 bias pack
@@ -1335,6 +1533,9 @@ struct vgx_flow {
   int* fw_src = nullptr;
   int* bw_src = nullptr;
   int* b_src = nullptr;
+  int* fw_dst = nullptr;  // inverse of fw_src per parameter (-1: none); null if a parameter
+  int* bw_dst = nullptr;  // appears twice in one pack
+  int* b_dst = nullptr;
   double* loss = nullptr;       // [3]
   double* partials = nullptr;   // [max grid][4]
   int step = 0;
@@ -1467,14 +1668,61 @@ size_t bwd_lds(const vgx_flow* f, int l) {
 }
 
 template <class OP>
-size_t fuse_lds_op(const vgx_flow* f, int l) {
+size_t fuse_lds_wv(const vgx_flow* f, int l, int wv) {
   const FlowLayerDesc& Ld = f->D.l[l];
   const int es = (int)sizeof(typename OP::S);
-  return fuse_stage_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len, es, f->dim) +
-         (size_t)FUSE_WAVES * fuse_stage_rows(f->nbm) * fuse_rs<OP>() * es;
+  return fuse_stage_offset(Ld.fw_len, Ld.bw_len, Ld.bias_len, es, f->dim, 64 * wv) +
+         (size_t)wv * fuse_stage_rows(Ld.nb) * fuse_rs<OP>() * es;
 }
 
+// waves of the fused workgroup of layer l: eight (two per SIMD, so that one
+// wave's waits overlap the other's work) for BF16 operands and |B| <= 2
+// where their stages fit the LDS, else four
+template <class OP>
+int fuse_waves(const vgx_flow* f, int l) {
+  return (sizeof(typename OP::S) == 2 && f->D.l[l].nb <= 2 && fuse_lds_wv<OP>(f, l, 8) <= 160 * 1024) ? 8 : 4;
+}
+
+template <class OP>
+size_t fuse_lds_op(const vgx_flow* f, int l) { return fuse_lds_wv<OP>(f, l, fuse_waves<OP>(f, l)); }
+
 size_t fuse_lds(const vgx_flow* f, int l) { return f->f32ops ? fuse_lds_op<OpF32>(f, l) : fuse_lds_op<OpBF16>(f, l); }
+
+// the fused kernel of a layer with |B| = nb and wv waves
+template <class OP>
+const void* fuse_kernel(int nb, int wv) {
+  if (wv == 8) {
+    if constexpr (sizeof(typename OP::S) == 2) {
+      switch (nb) {
+        case 1: return (const void*)k_flow_bwdw<1, 8, OP>;
+        case 2: return (const void*)k_flow_bwdw<2, 8, OP>;
+        default: return nullptr;
+      }
+    }
+    return nullptr;
+  }
+  switch (nb) {
+    case 1: return (const void*)k_flow_bwdw<1, 4, OP>;
+    case 2: return (const void*)k_flow_bwdw<2, 4, OP>;
+    case 3: return (const void*)k_flow_bwdw<3, 4, OP>;
+    case 4: return (const void*)k_flow_bwdw<4, 4, OP>;
+    default: return nullptr;
+  }
+}
+
+// allow every fused kernel the whole LDS of a CU (a launch still asks only
+// for what its layer needs), once per process
+template <class OP>
+vgx_status fuse_allow_lds() {
+  static bool done = false;
+  if (done) return VGX_OK;
+  for (int nb = 1; nb <= 4; ++nb)
+    for (int wv = 4; wv <= 8; wv += 4)
+      if (const void* k = fuse_kernel<OP>(nb, wv))
+        VGX_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  done = true;
+  return VGX_OK;
+}
 
 // the backward of layers with |B| <= 4 runs fused with its weight gradients
 bool fused_backward(const vgx_flow* f) { return f->nbm <= 4; }
@@ -1512,11 +1760,7 @@ vgx_status set_lds_limits(size_t fwd, size_t bwd, size_t wgr, size_t fus) {
   cur_b = bwd;
   cur_w = wgr;
   cur_u = fus;
-  if constexpr (NB <= 4) {
-    if (fus > 0)
-      VGX_HIP(hipFuncSetAttribute((const void*)k_flow_bwdw<NB, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)fus));
-  }
+  if (fus > 0) VGX_TRY(fuse_allow_lds<OP>());
   VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 0, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
   VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 1, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
   VGX_HIP(hipFuncSetAttribute((const void*)k_flow_fwd<NB, 2, OP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd));
@@ -1550,10 +1794,12 @@ vgx_status init_lds_limits(const vgx_flow* f) {
                    : set_lds_limits_nb<OpBF16>(f->nbm, fwd, bwd, wgr, fus);
 }
 
+// forward grid: tile pairs go round-robin over the workgroups (wave w of
+// workgroup b takes pairs w gridDim + b, ...), so a batch of fewer than
+// FWD_BLOCK / 64 pairs per CU still spreads over every CU
 int fwd_grid(const vgx_flow* f, int64_t n, int per_cu = 2) {
   const int64_t tiles = (n + 63) / 64;  // the forward kernels take 64-sample tile pairs
-  const int64_t waves_per_wg = FWD_BLOCK / 64;
-  int64_t g = (tiles + waves_per_wg - 1) / waves_per_wg;
+  int64_t g = tiles;
   const int64_t cap = (int64_t)device_cus() * per_cu;
   if (g > cap) g = cap;
   return (int)(g < 1 ? 1 : g);
@@ -1619,8 +1865,11 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
   a.rsave = f->rsave;
   a.partials = f->partials;
   VGX_TRY(launch_fwd<1>(f, grid, a, f->stream));
-  hipLaunchKernelGGL(k_flow_loss, dim3(1), dim3(256), 0, f->stream, f->partials, grid, f->loss);
-  VGX_HIP(hipGetLastError());
+  // the fused backward of the last layer reduces the loss itself
+  if (!fused_backward(f)) {
+    hipLaunchKernelGGL(k_flow_loss, dim3(1), dim3(256), 0, f->stream, f->partials, grid, f->loss);
+    VGX_HIP(hipGetLastError());
+  }
   const int wgrid = f->grid_w;
   // backward: two resident workgroups per CU (the layer's packs in LDS)
   const int64_t btiles = (n + 31) / 32;
@@ -1638,19 +1887,36 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
     b.loss = f->loss;
     b.scr = f->scr;
     b.srows = f->srows;
+    b.partials = l == f->L - 1 ? f->partials : nullptr;
+    b.prows = grid;
+    b.loss_out = f->loss;
     const size_t wl = (size_t)Ld.n_par * 4;
     float* gp = f->gpart + (size_t)Ld.p_off * wgrid;
     if (fused_backward(f)) {
       const size_t lds = fuse_lds(f, l);
-#define F_(NB, OP)                                                                                          \
-  case NB:                                                                                                  \
-    hipLaunchKernelGGL((k_flow_bwdw<NB, OP>), dim3(wgrid), dim3(FBLOCK), lds, f->stream, f->d_desc, b,      \
-                       (const OP::S*)f->fw, (const OP::S*)f->bw, f->bias, gp);                              \
-    break;
+      const int wv = f->f32ops ? fuse_waves<OpF32>(f, l) : fuse_waves<OpBF16>(f, l);
+#define F_(NB, WV, OP)                                                                                    \
+  hipLaunchKernelGGL((k_flow_bwdw<NB, WV, OP>), dim3(wgrid), dim3(64 * WV), lds, f->stream, f->d_desc, b, \
+                     (const OP::S*)f->fw, (const OP::S*)f->bw, f->bias, gp)
+      const int key = 10 * Ld.nb + wv;
       if (f->f32ops) {
-        switch (f->nbm) { F_(1, OpF32) F_(2, OpF32) F_(4, OpF32) default: return VGX_EINVAL; }
+        switch (Ld.nb) {
+          case 1: F_(1, 4, OpF32); break;
+          case 2: F_(2, 4, OpF32); break;
+          case 3: F_(3, 4, OpF32); break;
+          case 4: F_(4, 4, OpF32); break;
+          default: return VGX_EINVAL;
+        }
       } else {
-        switch (f->nbm) { F_(1, OpBF16) F_(2, OpBF16) F_(4, OpBF16) default: return VGX_EINVAL; }
+        switch (key) {
+          case 14: F_(1, 4, OpBF16); break;
+          case 18: F_(1, 8, OpBF16); break;
+          case 24: F_(2, 4, OpBF16); break;
+          case 28: F_(2, 8, OpBF16); break;
+          case 34: F_(3, 4, OpBF16); break;
+          case 44: F_(4, 4, OpBF16); break;
+          default: return VGX_EINVAL;
+        }
       }
 #undef F_
       VGX_HIP(hipGetLastError());
@@ -1715,9 +1981,21 @@ vgx_status reduce_adam(vgx_flow* f, const float* grad_in, float* grad_out, float
   a.eps = 1e-8f;
   a.do_adam = adam ? 1 : 0;
   if (adam) a.step = ++f->step;
-  hipLaunchKernelGGL(k_flow_adam, dim3((unsigned)((f->n_par + 255) / 256)), dim3(256), 0, f->stream, f->d_desc, a);
+  if (adam && f->fw_dst) {
+    a.fw_dst = f->fw_dst;
+    a.bw_dst = f->bw_dst;
+    a.b_dst = f->b_dst;
+    a.fw = f->fw;
+    a.bw = f->bw;
+    a.bias = f->bias;
+  }
+  const dim3 grid((unsigned)((f->n_par + 255) / 256));
+  if (f->f32ops)
+    hipLaunchKernelGGL(k_flow_adam<OpF32>, grid, dim3(256), 0, f->stream, f->d_desc, a);
+  else
+    hipLaunchKernelGGL(k_flow_adam<OpBF16>, grid, dim3(256), 0, f->stream, f->d_desc, a);
   VGX_HIP(hipGetLastError());
-  if (adam) VGX_TRY(pack(f));
+  if (adam && !f->fw_dst) VGX_TRY(pack(f));
   return VGX_OK;
 }
 
@@ -1798,6 +2076,21 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
     set_error("flow_create: packed weights exceed LDS");
     return VGX_EINVAL;
   }
+  // each parameter's position in the packs: Adam writes the new weight
+  // there directly (only if no parameter appears twice in one pack)
+  std::vector<int> fwd(f->n_par, -1), bwd(f->n_par, -1), bd(f->n_par, -1);
+  bool inv_ok = true;
+  auto invert = [&](const std::vector<int>& src, std::vector<int>& dst) {
+    for (size_t k = 0; k < src.size(); ++k) {
+      const int q = src[k];
+      if (q < 0) continue;
+      if (q >= f->n_par || dst[q] >= 0) inv_ok = false;
+      else dst[q] = (int)k;
+    }
+  };
+  invert(fws, fwd);
+  invert(bws, bwd);
+  invert(bs, bd);
   do {
     if ((s = dev_alloc((void**)&f->master, sizeof(float) * f->n_par)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->m, sizeof(float) * f->n_par)) != VGX_OK) break;
@@ -1809,6 +2102,11 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
     if ((s = dev_alloc((void**)&f->fw_src, 4 * fws.size())) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->bw_src, 4 * bws.size())) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->b_src, 4 * bs.size())) != VGX_OK) break;
+    if (inv_ok) {
+      if ((s = dev_alloc((void**)&f->fw_dst, 4 * (size_t)f->n_par)) != VGX_OK) break;
+      if ((s = dev_alloc((void**)&f->bw_dst, 4 * (size_t)f->n_par)) != VGX_OK) break;
+      if ((s = dev_alloc((void**)&f->b_dst, 4 * (size_t)f->n_par)) != VGX_OK) break;
+    }
     if ((s = dev_alloc((void**)&f->loss, sizeof(double) * 4)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->d_desc, sizeof(FlowDesc))) != VGX_OK) break;
     if ((s = dev_alloc((void**)&f->partials, sizeof(double) * 4 * (size_t)device_cus() * 2)) != VGX_OK) break;
@@ -1821,6 +2119,11 @@ extern "C" vgx_status flow_create(int32_t dim, int32_t n_layers, int32_t n_bins,
   if (e == hipSuccess) e = hipMemcpyAsync(f->fw_src, fws.data(), 4 * fws.size(), hipMemcpyHostToDevice, f->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(f->bw_src, bws.data(), 4 * bws.size(), hipMemcpyHostToDevice, f->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(f->b_src, bs.data(), 4 * bs.size(), hipMemcpyHostToDevice, f->stream);
+  if (inv_ok) {
+    if (e == hipSuccess) e = hipMemcpyAsync(f->fw_dst, fwd.data(), 4 * fwd.size(), hipMemcpyHostToDevice, f->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->bw_dst, bwd.data(), 4 * bwd.size(), hipMemcpyHostToDevice, f->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->b_dst, bd.data(), 4 * bd.size(), hipMemcpyHostToDevice, f->stream);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(f->d_desc, &f->D, sizeof(FlowDesc), hipMemcpyHostToDevice, f->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);  // host vectors die at return
   if (e != hipSuccess) { s = hip_fail(e, "flow_create copies", __FILE__, __LINE__); flow_destroy(f); return s; }
@@ -1843,7 +2146,8 @@ extern "C" vgx_status flow_set_operands(vgx_flow* f, int32_t operands) {
   if (want == f->f32ops) return VGX_OK;
   size_t need = fwd_lds_es(f, want ? 4 : 2);
   if (fused_backward(f))
-    for (int l = 0; l < f->L; ++l) need = std::max(need, want ? fuse_lds_op<OpF32>(f, l) : fuse_lds_op<OpBF16>(f, l));
+    for (int l = 0; l < f->L; ++l)
+      need = std::max(need, want ? fuse_lds_op<OpF32>(f, l) : fuse_lds_op<OpBF16>(f, l));
   if (need > 160 * 1024) {
     set_error("flow_set_operands: the FP32 weight packs of a %d-dimensional flow exceed the LDS", f->dim);
     return VGX_EINVAL;
@@ -1953,6 +2257,7 @@ extern "C" void flow_destroy(vgx_flow* f) {
   hipFree(f->master); hipFree(f->m); hipFree(f->v); hipFree(f->grad);
   hipFree(f->fw); hipFree(f->bw); hipFree(f->bias);
   hipFree(f->fw_src); hipFree(f->bw_src); hipFree(f->b_src);
+  hipFree(f->fw_dst); hipFree(f->bw_dst); hipFree(f->b_dst);
   hipFree(f->loss); hipFree(f->partials); hipFree(f->d_desc);
   hipFree(f->zsave); hipFree(f->rsave); hipFree(f->lqsave); hipFree(f->dz[0]); hipFree(f->dz[1]); hipFree(f->scr); hipFree(f->gpart);
   hipFree(f->gtmp);
