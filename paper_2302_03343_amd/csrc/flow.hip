@@ -633,40 +633,65 @@ __global__ __launch_bounds__(FWD_BLOCK) void k_flow_fwd(const FlowDesc* __restri
 }
 
 // loss L = sum r / sum g^2, scale = -1/sum g^2 and the ok flag from the
-// forward's partial rows [rows][4] (fixed-order compensated reduction by the
-// first 256 threads of a workgroup of at least 256; lds: 520 doubles).
-// Every thread of the workgroup must call it; all get the three values.
-__device__ __forceinline__ void loss_reduce(const double* __restrict__ partials, int rows, double* lds,
+// forward's partial rows [rows][4], by one wave (every lane gets them):
+// lane l sums rows l, l + 64, ... (compensated), then the lanes combine in a
+// fixed butterfly order and lane 0's totals are broadcast.  The loads of the
+// first 512 rows are issued apart (loss_load), so that other work can run
+// while they are in flight.
+struct LossRows {
+  double v[8][4];
+};
+
+__device__ __forceinline__ void loss_load(const double* __restrict__ partials, int rows, int r0, LossRows& lr) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = r0 + 64 * k + lane;
+#pragma unroll
+    for (int col = 0; col < 4; ++col) lr.v[k][col] = r < rows ? partials[r * 4 + col] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void loss_finish(const double* __restrict__ partials, int rows, LossRows& lr,
                                             double (&out)[3]) {
-  double* ps = lds;        // [4][64]
-  double* pc = lds + 256;  // [4][64]
-  double* sh = lds + 512;  // [4]
-  if (threadIdx.x < 256) {
-    const int col = threadIdx.x & 3, grp = threadIdx.x >> 2;  // 64 row groups per column
-    Comp c;
-    for (int r = grp; r < rows; r += 64) c.add(partials[r * 4 + col]);
-    ps[col * 64 + grp] = c.s;
-    pc[col * 64 + grp] = c.c;
+  const int lane = threadIdx.x & 63;
+  Comp c[4];
+  for (int r0 = 0; r0 < rows; r0 += 8 * 64) {
+    if (r0 > 0) loss_load(partials, rows, r0, lr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (r0 + 64 * k + lane < rows) {
+#pragma unroll
+        for (int col = 0; col < 4; ++col) c[col].add(lr.v[k][col]);
+      }
   }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    Comp t;
-    for (int g = 0; g < 64; ++g) { t.add(ps[threadIdx.x * 64 + g]); t.add(pc[threadIdx.x * 64 + g]); }
-    sh[threadIdx.x] = t.value();
+  double tot[4];
+#pragma unroll
+  for (int col = 0; col < 4; ++col) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double os = __shfl_xor(c[col].s, off, 64), oc = __shfl_xor(c[col].c, off, 64);
+      c[col].add(os);
+      c[col].add(oc);
+    }
+    tot[col] = __shfl(c[col].value(), 0, 64);
   }
-  __syncthreads();
-  const double sr = sh[0] + sh[1], sg = sh[2] + sh[3];
+  const double sr = tot[0] + tot[1], sg = tot[2] + tot[3];
   const double L = sr / sg;
   out[0] = L;
   out[1] = -1.0 / sg;
   out[2] = (isfinite(L) && sg > 0.0) ? 1.0 : 0.0;
-  __syncthreads();  // the scratch may be reused
 }
 
-__global__ __launch_bounds__(256) void k_flow_loss(const double* __restrict__ partials, int rows, double* __restrict__ out) {
-  __shared__ double lds[520];
+__device__ __forceinline__ void loss_reduce(const double* __restrict__ partials, int rows, double (&out)[3]) {
+  LossRows lr;
+  loss_load(partials, rows, 0, lr);
+  loss_finish(partials, rows, lr, out);
+}
+
+__global__ __launch_bounds__(64) void k_flow_loss(const double* __restrict__ partials, int rows, double* __restrict__ out) {
   double v[3];
-  loss_reduce(partials, rows, lds, v);
+  loss_reduce(partials, rows, v);
   if (threadIdx.x == 0) {
     out[0] = v[0];
     out[1] = v[1];
@@ -1209,6 +1234,11 @@ __global__ __launch_bounds__(64 * WV) void k_flow_bwdw(const FlowDesc* __restric
     const double rv = a.rsave[ic];
     pr = ok ? rv : 0.0;
   };
+  // the loss scale: reduced by every wave from the forward's partial rows
+  // (first launch of a step; workgroup 0 stores the loss), else read; the
+  // rows' loads are in flight while the packs are copied
+  LossRows lrows;
+  if (a.partials) loss_load(a.partials, a.prows, 0, lrows);
   if (n > 0) fetch(blockIdx.x);
   S* sfw = (S*)flds;
   S* sbw = sfw + L.fw_len;
@@ -1234,16 +1264,10 @@ __global__ __launch_bounds__(64 * WV) void k_flow_bwdw(const FlowDesc* __restric
   float* zbp[NB];
 #pragma unroll
   for (int jb = 0; jb < NB; ++jb) zbp[jb] = zc + L.b_idx[jb] * BS;
-  __syncthreads();
-  const LayerLds<OP> W = layer_lds<OP>(sfw, sb, L, L.fw_off, L.bias_off);
-  const frag* w3t = (const frag*)sbw;                       // [2][2 NB][32][2]
-  const frag* w2t = (const frag*)(sbw + NB * 2048);         // [2][4][32][2]
-  const frag* w1t = (const frag*)(sbw + NB * 2048 + 4096);  // [1][4][32][2]
   double scale;
   if (a.partials) {
-    // the stage is free until the first group: scratch of the loss reduction
     double lv[3];
-    loss_reduce(a.partials, a.prows, (double*)stage, lv);
+    loss_finish(a.partials, a.prows, lrows, lv);
     scale = lv[1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.loss_out[0] = lv[0];
@@ -1253,6 +1277,11 @@ __global__ __launch_bounds__(64 * WV) void k_flow_bwdw(const FlowDesc* __restric
   } else {
     scale = a.loss[1];
   }
+  __syncthreads();
+  const LayerLds<OP> W = layer_lds<OP>(sfw, sb, L, L.fw_off, L.bias_off);
+  const frag* w3t = (const frag*)sbw;                       // [2][2 NB][32][2]
+  const frag* w2t = (const frag*)(sbw + NB * 2048);         // [2][4][32][2]
+  const frag* w1t = (const frag*)(sbw + NB * 2048 + 4096);  // [1][4][32][2]
   S* mystage = stage + (size_t)wave * SR * RS;
   f32x16 acc[OWN];
   float bsum[OWN];
@@ -1412,35 +1441,13 @@ __global__ __launch_bounds__(64 * WV) void k_flow_bwdw(const FlowDesc* __restric
 // ---------------------------------------------------------------------------
 // Gradient reduction (fixed order over workgroup partials) + Adam.
 // ---------------------------------------------------------------------------
-constexpr int GSPLIT = 8;  // row groups of the first reduction stage
+constexpr int GSPLIT = 8;  // row groups (waves) of the gradient reduction
 
-// First stage: row group blockIdx.y sums the workgroup partial rows
-// r = y, y + GSPLIT, ... of every parameter (compensated, fixed order).
-__global__ __launch_bounds__(256) void k_flow_gsum(const FlowDesc* __restrict__ Dp, int64_t n_par, int rows,
-                                                  const float* __restrict__ gpart, float* __restrict__ gtmp) {
-  const FlowDesc& D = *Dp;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n_par) return;
-  int l = 0;
-  while (l + 1 < D.L && p >= D.l[l + 1].p_off) ++l;
-  const int q = (int)(p - D.l[l].p_off);
-  const int np = D.l[l].n_par;
-  const float* base = gpart + (size_t)D.l[l].p_off * rows;
-  float acc = 0.0f, c = 0.0f;
-  for (int r = blockIdx.y; r < rows; r += GSPLIT) {
-    const float y = base[(size_t)r * np + q] - c;
-    const float t = acc + y;
-    c = (t - acc) - y;
-    acc = t;
-  }
-  gtmp[(size_t)blockIdx.y * n_par + p] = acc;
-}
 
 struct AdamArgs {
   int64_t n_par;
   int rows;              // workgroup partial rows per layer
-  const float* gpart;    // first-stage sums [GSPLIT][n_par]
-  const float* grad_in;  // alternative: a full gradient (flow_adam)
+  const float* grad_in;  // a full gradient (flow_adam), or null: the step's partial rows
   float* grad_out;       // reduced gradient (nullable)
   float* master;
   float* m;
@@ -1460,18 +1467,10 @@ struct AdamArgs {
   float* bias;
 };
 
+// Adam for parameter p with gradient g; with the pack positions, the new
+// weight also goes into the packs
 template <class OP>
-__global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ Dp, AdamArgs a) {
-  const FlowDesc& D = *Dp;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= a.n_par) return;
-  float g;
-  if (a.grad_in) {
-    g = a.grad_in[p];
-  } else {
-    g = 0.0f;
-    for (int r = 0; r < GSPLIT; ++r) g += a.gpart[(size_t)r * a.n_par + p];  // fixed order
-  }
+__device__ __forceinline__ void adam_update(const AdamArgs& a, int64_t p, float g) {
   if (a.grad_out) a.grad_out[p] = g;
   if (!a.do_adam) return;
   if (a.loss && a.loss[2] == 0.0) return;  // non-finite loss: leave the weights
@@ -1489,6 +1488,62 @@ __global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ 
     if (kb >= 0) ((typename OP::S*)a.bw)[kb] = OP::store(w);
     if (kc >= 0) a.bias[kc] = w;
   }
+}
+
+// Adam with a caller's full gradient
+template <class OP>
+__global__ __launch_bounds__(256) void k_flow_adam(const FlowDesc* __restrict__ Dp, AdamArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.n_par) return;
+  adam_update<OP>(a, p, a.grad_in[p]);
+}
+
+// The gradient of a training step from the workgroup partial rows, then
+// Adam: a workgroup of 64 GSPLIT threads takes 64 parameters; wave w sums
+// rows w, w + GSPLIT, ... of its lane's parameter (compensated, in row
+// order, eight loads in flight), and the GSPLIT waves' sums are added in
+// wave order (a fixed order throughout).
+template <class OP>
+__global__ __launch_bounds__(64 * GSPLIT) void k_flow_gadam(const FlowDesc* __restrict__ Dp, AdamArgs a,
+                                                           const float* __restrict__ gpart) {
+  __shared__ float part[GSPLIT][64];
+  const FlowDesc& D = *Dp;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  float acc = 0.0f;
+  if (p < a.n_par) {
+    int l = 0;
+    while (l + 1 < D.L && p >= D.l[l + 1].p_off) ++l;
+    const int q = (int)(p - D.l[l].p_off);
+    const int np = D.l[l].n_par;
+    const int rows = a.rows;
+    const float* base = gpart + (size_t)D.l[l].p_off * rows;
+    float c = 0.0f;
+    for (int r0 = w; r0 < rows; r0 += 8 * GSPLIT) {
+      float v[8];  // eight rows' loads in flight, then added in row order
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = r0 + k * GSPLIT;
+        v[k] = r < rows ? base[(size_t)r * np + q] : 0.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (r0 + k * GSPLIT < rows) {
+          const float y = v[k] - c;
+          const float t = acc + y;
+          c = (t - acc) - y;
+          acc = t;
+        }
+      }
+    }
+  }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w != 0 || p >= a.n_par) return;
+  float g = 0.0f;
+#pragma unroll
+  for (int r = 0; r < GSPLIT; ++r) g += part[r][lane];  // fixed order
+  adam_update<OP>(a, p, g);
 }
 
 // master FP32 weights -> permuted operand packs (OP::S) and FP32 bias pack
@@ -1547,7 +1602,6 @@ struct vgx_flow {
   float* dz[2] = {nullptr, nullptr};  // [d][n]
   void* scr = nullptr;          // operand tiles [tiles][srows][32] of OP::S
   float* gpart = nullptr;       // [n_par * grid_w]
-  float* gtmp = nullptr;        // [GSPLIT][n_par]
   int grid_w = 0;
   int srows = 0;
   double* pinned = nullptr;
@@ -1842,7 +1896,6 @@ vgx_status ensure_train(vgx_flow* f, int64_t n) {
   VGX_TRY(dev_alloc((void**)&f->dz[1], sizeof(float) * (size_t)f->dim * n));
   if (!fused_backward(f)) VGX_TRY(dev_alloc((void**)&f->scr, es * (size_t)tiles * f->srows * 32));
   VGX_TRY(dev_alloc((void**)&f->gpart, sizeof(float) * (size_t)f->n_par * f->grid_w));
-  if (!f->gtmp) VGX_TRY(dev_alloc((void**)&f->gtmp, sizeof(float) * (size_t)f->n_par * GSPLIT));
   // rows 16..31 of the zA block are never written and must read as zero
   if (f->scr) VGX_HIP(hipMemsetAsync(f->scr, 0, es * (size_t)tiles * f->srows * 32, f->stream));
   f->cap_n = n;
@@ -1867,7 +1920,7 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
   VGX_TRY(launch_fwd<1>(f, grid, a, f->stream));
   // the fused backward of the last layer reduces the loss itself
   if (!fused_backward(f)) {
-    hipLaunchKernelGGL(k_flow_loss, dim3(1), dim3(256), 0, f->stream, f->partials, grid, f->loss);
+    hipLaunchKernelGGL(k_flow_loss, dim3(1), dim3(64), 0, f->stream, f->partials, grid, f->loss);
     VGX_HIP(hipGetLastError());
   }
   const int wgrid = f->grid_w;
@@ -1960,15 +2013,9 @@ vgx_status loss_grad_enqueue(vgx_flow* f, int64_t n, const double* y, const doub
 }
 
 vgx_status reduce_adam(vgx_flow* f, const float* grad_in, float* grad_out, float lr, bool adam, const double* loss) {
-  if (!grad_in) {
-    hipLaunchKernelGGL(k_flow_gsum, dim3((unsigned)((f->n_par + 255) / 256), GSPLIT), dim3(256), 0, f->stream,
-                       f->d_desc, f->n_par, f->grid_w, f->gpart, f->gtmp);
-    VGX_HIP(hipGetLastError());
-  }
   AdamArgs a{};
   a.n_par = f->n_par;
   a.rows = f->grid_w;
-  a.gpart = f->gtmp;
   a.grad_in = grad_in;
   a.grad_out = grad_out;
   a.master = f->master;
@@ -1989,11 +2036,20 @@ vgx_status reduce_adam(vgx_flow* f, const float* grad_in, float* grad_out, float
     a.bw = f->bw;
     a.bias = f->bias;
   }
-  const dim3 grid((unsigned)((f->n_par + 255) / 256));
-  if (f->f32ops)
-    hipLaunchKernelGGL(k_flow_adam<OpF32>, grid, dim3(256), 0, f->stream, f->d_desc, a);
-  else
-    hipLaunchKernelGGL(k_flow_adam<OpBF16>, grid, dim3(256), 0, f->stream, f->d_desc, a);
+  if (grad_in) {
+    const dim3 grid((unsigned)((f->n_par + 255) / 256));
+    if (f->f32ops)
+      hipLaunchKernelGGL(k_flow_adam<OpF32>, grid, dim3(256), 0, f->stream, f->d_desc, a);
+    else
+      hipLaunchKernelGGL(k_flow_adam<OpBF16>, grid, dim3(256), 0, f->stream, f->d_desc, a);
+  } else {
+    // the workgroup partials of the training step, reduced and applied at once
+    const dim3 grid((unsigned)((f->n_par + 63) / 64));
+    if (f->f32ops)
+      hipLaunchKernelGGL(k_flow_gadam<OpF32>, grid, dim3(64 * GSPLIT), 0, f->stream, f->d_desc, a, f->gpart);
+    else
+      hipLaunchKernelGGL(k_flow_gadam<OpBF16>, grid, dim3(64 * GSPLIT), 0, f->stream, f->d_desc, a, f->gpart);
+  }
   VGX_HIP(hipGetLastError());
   if (adam && !f->fw_dst) VGX_TRY(pack(f));
   return VGX_OK;
@@ -2260,7 +2316,7 @@ extern "C" void flow_destroy(vgx_flow* f) {
   hipFree(f->fw_dst); hipFree(f->bw_dst); hipFree(f->b_dst);
   hipFree(f->loss); hipFree(f->partials); hipFree(f->d_desc);
   hipFree(f->zsave); hipFree(f->rsave); hipFree(f->lqsave); hipFree(f->dz[0]); hipFree(f->dz[1]); hipFree(f->scr); hipFree(f->gpart);
-  hipFree(f->gtmp);
+
   if (f->pinned) hipHostFree(f->pinned);
   delete f;
 }
