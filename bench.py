@@ -377,6 +377,12 @@ def flow_pipeline(vgx, kind, dim, params, pdf, n_iter, warm_iters, steps, batch,
         e1.record()
         e1.synchronize()
         out["flow_ns_per_event"] = e0.elapsed_time(e1) * 1e6 / n_flow
+        # the same in one pass (flow_vegas_iterate: no points in memory)
+        e0.record()
+        vgx.flow_vegas_iterate(f, v, n_flow, seed, 6, 1, allow_fallback=True)
+        e1.record()
+        e1.synchronize()
+        out["flow_fused_ns_per_event"] = e0.elapsed_time(e1) * 1e6 / n_flow
         # the identity-initialised flow draws the VEGAS map's own points: one
         # fused iteration on the grid the flow was trained on measures it (a
         # fresh context, so the pipeline's combination is untouched)

@@ -550,6 +550,21 @@ vgx_status flow_set_operands(vgx_flow* f, int32_t operands);
 vgx_status flow_sample(vgx_flow* f, int64_t n, uint64_t seed, uint32_t stream_id, int32_t iteration,
                        double* y_dev, double* logq_dev, void* stream);
 
+/* Draw n points from the flow and add their importance-sampling estimate to
+ * the VEGAS context, in one pass with no points in memory (sync).  Thesis:
+ * MC chapter, eq. mc_est_is with the proposal p = q times the grid's density
+ * (as vegas_iterate_points): w = f(G(y)) J_G(y) / q(y).  The points are
+ * those flow_sample(f, n, seed, stream_id, iteration) draws, so the estimate
+ * equals vegas_iterate_points on them up to the order of the sums.  Needs
+ * the flow's dimension equal to the context's (2..8), BF16 operands, and the
+ * flow's weights and the integrand's tables together within the LDS of a CU
+ * (VGX_EINVAL otherwise).  Runs on the context's stream after the work
+ * enqueued on the flow's stream; records and judges the estimate as
+ * vegas_iterate_points does with logq (VGX_EFALLBACK, VGX_ENUMERIC); out_host
+ * may be NULL. */
+vgx_status flow_vegas_iterate(vgx_flow* f, vgx_vegas* v, int64_t n, uint64_t seed, uint32_t stream_id,
+                              int32_t iteration, vgx_iter_result* out_host);
+
 /* Density direction (async): y_dev [dim][n] -> u_dev [dim][n] (may be NULL),
  * logq_dev [n]. */
 vgx_status flow_density(vgx_flow* f, int64_t n, const double* y_dev, double* u_dev, double* logq_dev,

@@ -31,6 +31,7 @@
 #include "singletop.h"
 #include "ttbar_dyn.h"
 #include "vegas_internal.h"
+#include "flow_internal.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -253,6 +254,89 @@ __global__ __launch_bounds__(BLOCK, Src::kInterior ? MinWaves<F>::value : 1) voi
       for (int c = 1; c < a.hcopies; ++c) h += sh[c * D * nb + k];  // copy order
       row[4 + k] = h;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fused flow-sampling iteration: the importance-sampling estimate with the
+// coupling flow as the proposal density q.  Each wave draws a 64-sample tile
+// pair from the flow as flow_sample draws it (Philox u, the coupling layers
+// in the sampling direction: y and log q in the lane of each sample), maps
+// y through the VEGAS grid and weights f(x) J(y) / q(y) into compensated S1
+// and S2, as the iteration kernel does with caller points and their log q;
+// nothing per sample goes to HBM.  LDS: edges [D][nb+1] | integrand tables |
+// flow packs | biases | per-lane columns [d][FI_BLOCK].
+// ---------------------------------------------------------------------------
+struct FlowIterArgs {
+  const FlowDesc* desc;
+  const void* fw;
+  const float* bias;
+  int flow_off;  // byte offset of the flow's part of the LDS (16-byte aligned)
+  uint32_t it, sid, k0, k1;
+};
+
+constexpr int FI_BLOCK = 512;  // eight waves share one LDS copy of the weights and tables
+
+template <int D, class F, class OP>
+__global__ __launch_bounds__(FI_BLOCK) void k_flow_iter(VegasArgs a, F f, FlowIterArgs fa,
+                                                        double* __restrict__ partials) {
+  using S = typename OP::S;
+  extern __shared__ __align__(16) double lds[];
+  const int nb = a.nb;
+  double* se = lds;
+  float* extra = (float*)(lds + lds_table_offset(D, nb, false, !F::kStage));
+  unsigned char* fl = (unsigned char*)lds + fa.flow_off;
+  const FlowDesc& FD = *fa.desc;
+  S* sfw = (S*)fl;
+  float* sb = (float*)(fl + (size_t)FD.fw_total * sizeof(S));
+  float* z = (float*)(fl + fwd_z_offset(FD.fw_total, FD.bias_total, (int)sizeof(S))) + threadIdx.x;
+  for (int k = threadIdx.x; k < D * (nb + 1); k += FI_BLOCK) se[k] = a.edges[k];
+  F ff = f;
+  if constexpr (F::kStage) ff.stage(extra);
+  copy16(sfw, fa.fw, FD.fw_total * (int)sizeof(S));
+  copy16(sb, fa.bias, FD.bias_total * 4);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = (threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+  const int nwaves = gridDim.x * (FI_BLOCK / 64);
+  const int64_t npairs = (a.n + 63) / 64;
+  const double nbd = (double)nb;
+  Comp c1, c2;
+  double p1 = 0.0, p2 = 0.0;
+  int cnt = 0;
+  for (int64_t t = wave; t < npairs; t += nwaves) {
+    const int64_t i = t * 64 + lane;  // the lane's own sample; every lane runs the layers
+    const bool valid = i < a.n;
+    flow_draw<FI_BLOCK>(z, D, i, fa.it, fa.sid, fa.k0, fa.k1);
+    const double lq = flow_layers<true, OP, FI_BLOCK>(FD, sfw, sb, z, i, valid, nullptr, a.n);
+    if (valid) {
+      double tt[D], x[D];
+      int idx[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) tt[j] = (double)z[j * FI_BLOCK] * nbd;
+      const double jac = grid_map_t<D, false, !F::kStage>(tt, se, a.edges, nb, a.nbD, x, idx);
+      const double w = ff.eval(x) * jac * exp(-lq);
+      p1 += w;
+      p2 += w * w;
+      if (++cnt == CHUNK) {
+        c1.add(p1);
+        c2.add(p2);
+        p1 = p2 = 0.0;
+        cnt = 0;
+      }
+    }
+  }
+  c1.add(p1);
+  c2.add(p2);
+  __shared__ double red[4][FI_BLOCK / 64];
+  const double v0 = wave_sum(c1.s), v1 = wave_sum(c1.c), v2 = wave_sum(c2.s), v3 = wave_sum(c2.c);
+  const int wv = threadIdx.x >> 6;
+  if (lane == 0) { red[0][wv] = v0; red[1][wv] = v1; red[2][wv] = v2; red[3][wv] = v3; }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int k = 0; k < FI_BLOCK / 64; ++k) s += red[threadIdx.x][k];
+    partials[(size_t)blockIdx.x * a.pstride + threadIdx.x] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -850,6 +934,94 @@ vgx_status launch_points_iter(vgx_vegas* v, int64_t n, const double* y, const do
   return VGX_EINVAL;
 }
 
+// The fused flow-sampling iteration (k_flow_iter) for integrand F; sets the
+// grid (the partial rows to reduce).
+template <int D, class F>
+vgx_status launch_flow_iter_f(vgx_vegas* v, const FlowView& fv, int64_t n, FlowIterArgs fa, const F& f, int* grid) {
+  VegasArgs a{n, v->edges, v->nb, v->pstride, 1, pow_int((double)v->nb, D), v->nb * 0x1p-32};
+  const size_t base = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false, !F::kStage) + extra_lds_bytes(v);
+  const size_t off = (base + 15) & ~(size_t)15;
+  const size_t lds = off + fwd_z_offset(fv.fw_total, fv.bias_total, 2) + sizeof(float) * (size_t)D * FI_BLOCK;
+  VGX_CHECK(lds <= 160 * 1024, "flow_vegas_iterate: the flow's weights and the integrand's tables need %zu bytes of LDS",
+            lds);
+  fa.flow_off = (int)off;
+  const void* k = reinterpret_cast<const void*>(&k_flow_iter<D, F, OpBF16>);
+  static size_t allowed = 0;  // per instantiation: the dynamic LDS allowed so far (never lowered)
+  if (lds > allowed) {
+    VGX_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    allowed = lds;
+  }
+  // one workgroup per CU (the LDS), at most one tile pair per wave and round
+  const int64_t pairs = (n + 63) / 64;
+  int64_t g = device_cus();
+  if (g > v->max_wg) g = v->max_wg;
+  if (g * (FI_BLOCK / 64) > pairs) g = (pairs + FI_BLOCK / 64 - 1) / (FI_BLOCK / 64);
+  *grid = (int)(g < 1 ? 1 : g);
+  hipLaunchKernelGGL((k_flow_iter<D, F, OpBF16>), dim3(*grid), dim3(FI_BLOCK), lds, v->stream, a, f, fa, v->partials);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+template <int D>
+vgx_status launch_flow_iter_d(vgx_vegas* v, const FlowView& fv, int64_t n, const FlowIterArgs& fa, int* grid) {
+  if constexpr (D == 3) {
+    if (v->kind == VGX_TTBAR) {
+      if (v->tt_dyn) {
+        TTbarDyn f{};
+        f.c = v->ttd;
+        return launch_flow_iter_f<3, TTbarDyn>(v, fv, n, fa, f, grid);
+      }
+      TTbar f{};
+      f.c = v->tt;
+      return launch_flow_iter_f<3, TTbar>(v, fv, n, fa, f, grid);
+    }
+    if (v->kind == VGX_DRELLYAN) {
+      DrellYan f{};
+      f.c = v->dy;
+      return launch_flow_iter_f<3, DrellYan>(v, fv, n, fa, f, grid);
+    }
+    if (v->kind == VGX_SINGLETOP) {
+      SingleTop f{};
+      f.c = v->st;
+      return launch_flow_iter_f<3, SingleTop>(v, fv, n, fa, f, grid);
+    }
+  }
+#define VGX_FLOW_KIND(T)                                                       \
+  do {                                                                         \
+    if (v->prec == VGX_F64) {                                                  \
+      T<D, double> f{};                                                        \
+      f.prm = v->prm;                                                          \
+      return launch_flow_iter_f<D, T<D, double>>(v, fv, n, fa, f, grid);       \
+    } else {                                                                   \
+      T<D, float> f{};                                                         \
+      f.prm = v->prm;                                                          \
+      return launch_flow_iter_f<D, T<D, float>>(v, fv, n, fa, f, grid);        \
+    }                                                                          \
+  } while (0)
+  switch (v->kind) {
+    case VGX_GAUSS: VGX_FLOW_KIND(Gauss);
+    case VGX_GENZ_OSC: VGX_FLOW_KIND(GenzOsc);
+    case VGX_GENZ_PEAK: VGX_FLOW_KIND(GenzPeak);
+  }
+#undef VGX_FLOW_KIND
+  set_error("flow_vegas_iterate: integrand kind %d needs a different dimension", v->kind);
+  return VGX_EINVAL;
+}
+
+vgx_status launch_flow_iter(vgx_vegas* v, const FlowView& fv, int64_t n, const FlowIterArgs& fa, int* grid) {
+  switch (v->dim) {
+    case 2: return launch_flow_iter_d<2>(v, fv, n, fa, grid);
+    case 3: return launch_flow_iter_d<3>(v, fv, n, fa, grid);
+    case 4: return launch_flow_iter_d<4>(v, fv, n, fa, grid);
+    case 5: return launch_flow_iter_d<5>(v, fv, n, fa, grid);
+    case 6: return launch_flow_iter_d<6>(v, fv, n, fa, grid);
+    case 7: return launch_flow_iter_d<7>(v, fv, n, fa, grid);
+    case 8: return launch_flow_iter_d<8>(v, fv, n, fa, grid);
+  }
+  set_error("flow_vegas_iterate: dimension %d (the fused iteration takes 2..8)", v->dim);
+  return VGX_EINVAL;
+}
+
 vgx_status launch_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t it, double* u, double* g) {
 #define CALL(D) launch_sample_d<D>(v, first, n, it, u, g)
   VGX_DIM_SWITCH(v->dim, CALL)
@@ -1085,6 +1257,28 @@ extern "C" vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double
   v->comb_fresh = false;
   const int k = v->n_rec++;
   return read_record(v, k, out, logq ? REC_PROPOSAL : REC_POINTS);
+}
+
+extern "C" vgx_status flow_vegas_iterate(vgx_flow* f, vgx_vegas* v, int64_t n, uint64_t seed, uint32_t stream_id,
+                                         int32_t iteration, vgx_iter_result* out) {
+  VGX_CHECK(f && v, "flow_vegas_iterate: null flow or context");
+  VGX_CHECK(n >= 2, "flow_vegas_iterate: need n >= 2");
+  VGX_CHECK(stream_id < (1u << 23), "flow_vegas_iterate: stream_id >= 2^23");
+  const FlowView fv = flow_view(f);
+  VGX_CHECK(fv.dim == v->dim, "flow_vegas_iterate: flow dimension %d, context dimension %d", fv.dim, v->dim);
+  VGX_CHECK(!fv.f32ops, "flow_vegas_iterate: the flow runs FP32 validation operands (the fused iteration takes BF16)");
+  if (v->n_rec >= MAX_RECORDS) { set_error("flow_vegas_iterate: too many stored estimates"); return VGX_ESTATE; }
+  FlowIterArgs fa{fv.desc, fv.fw, fv.bias, 0, (uint32_t)iteration, stream_id | (1u << 23), (uint32_t)seed,
+                  (uint32_t)(seed >> 32)};
+  VGX_TRY(flow_order_before(f, v->stream));
+  VGX_TRY(timed_begin(v));
+  int grid = 0;
+  VGX_TRY(launch_flow_iter(v, fv, n, fa, &grid));
+  VGX_TRY(timed_end(v));
+  VGX_TRY(launch_reduce(v, grid, 4, n));
+  v->comb_fresh = false;
+  const int k = v->n_rec++;
+  return read_record(v, k, out, REC_PROPOSAL);
 }
 
 extern "C" void* vegas_stream(vgx_vegas* v) { return v ? (void*)v->stream : nullptr; }

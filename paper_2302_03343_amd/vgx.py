@@ -155,6 +155,7 @@ _optional("flow_adam", _S, _vp, _vp, _f32)
 _optional("flow_get_params", _S, _vp, C.POINTER(_f32), _i64, C.POINTER(_i64))
 _optional("flow_set_params", _S, _vp, C.POINTER(_f32), _i64)
 _optional("flow_set_operands", _S, _vp, _i32)
+_optional("flow_vegas_iterate", _S, _vp, _vp, _i64, _u64, _u32, _i32, C.POINTER(IterResult))
 _optional("flow_destroy", None, _vp)
 
 EXPORTED = sorted(_c)
@@ -613,6 +614,18 @@ def flow_sample(f, n, seed, stream_id, iteration, y, logq, stream=None):
     dim, _ = flow_shape(f)
     _check(_c["flow_sample"](f, n, seed, stream_id, iteration, _dptr(y, torch.float64, dim * n, "y"),
                              _dptr(logq, torch.float64, n, "logq"), _stream(stream)), "flow_sample")
+
+
+def flow_vegas_iterate(f, v, n, seed, stream_id, iteration, allow_numeric=False, allow_fallback=False):
+    """n points from the flow weighted into the VEGAS context's estimate in
+    one pass (the points flow_sample would draw; no points in memory)."""
+    r = IterResult()
+    st = _c["flow_vegas_iterate"](f, v, n, seed, stream_id, iteration, C.byref(r))
+    if not ((allow_numeric and st == VGX_ENUMERIC) or (allow_fallback and st == VGX_EFALLBACK)):
+        _check(st, "flow_vegas_iterate")
+    d = r.as_dict()
+    d["fallback"] = st == VGX_EFALLBACK
+    return d
 
 
 def flow_density(f, y, logq, u=None, stream=None):
