@@ -521,76 +521,6 @@ __host__ __device__ inline size_t fuse_stage_offset(int fw_len, int bw_len, int 
   return fuse_z_offset(fw_len, bw_len, bias_len, es) + sizeof(float) * (2 * (size_t)d + 2) * bs;
 }
 
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-// ReLU, ReLU-derivative mask and element sum of an operand fragment.
-template <class OP>
-struct FragOps;
-
-template <>
-struct FragOps<OpBF16> {
-  using frag = bf16x8;
-  // a BF16 value is negative exactly when its bits are, read as a signed
-  // 16-bit integer: max with 0 on packed pairs is the ReLU (v_pk_max_i16)
-  static __device__ __forceinline__ void relu(frag& f) {
-    const s16x8 x = __builtin_elementwise_max(__builtin_bit_cast(s16x8, f), (s16x8)0);
-    f = __builtin_bit_cast(frag, x);
-  }
-  // d = (h > 0) ? d : 0 per element, for h >= 0 (a ReLU output): min(h, 1)
-  // is 1 for every non-zero h and 0 for +0, and multiplies the bits of d
-  static __device__ __forceinline__ void mask(frag& d, const frag& h) {
-    u32x4v dv = __builtin_bit_cast(u32x4v, d);
-    const u32x4v hv = __builtin_bit_cast(u32x4v, h);
-    const unsigned one2 = 0x00010001u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      unsigned r;
-      asm("v_pk_min_u16 %0, %1, %2\n\tv_pk_mul_lo_u16 %0, %3, %0" : "=&v"(r) : "v"(hv[k]), "v"(one2), "v"(dv[k]));
-      dv[k] = r;
-    }
-    d = __builtin_bit_cast(frag, dv);
-  }
-  // acc + the sum of the eight elements (v_dot2 with ones)
-  static __device__ __forceinline__ float sum(const frag& f, float acc) {
-    const u32x4v v = __builtin_bit_cast(u32x4v, f);
-    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const unsigned w = v[k];
-      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), one, acc, false);
-    }
-    return acc;
-  }
-  // (whole vectors are bit_cast, then indexed: a bit_cast of one element
-  // f[e] compiles to element 0)
-  static __device__ __forceinline__ unsigned short bits(const frag& f, int e) {
-    const u16x8 u = __builtin_bit_cast(u16x8, f);
-    return u[e];
-  }
-};
-
-template <>
-struct FragOps<OpF32> {
-  using frag = f32x8;
-  static __device__ __forceinline__ void relu(frag& f) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) f[e] = fmaxf(f[e], 0.0f);
-  }
-  static __device__ __forceinline__ void mask(frag& d, const frag& h) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = h[e] > 0.0f ? d[e] : 0.0f;
-  }
-  static __device__ __forceinline__ float sum(const frag& f, float acc) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) acc += f[e];
-    return acc;
-  }
-  static __device__ __forceinline__ float bits(const frag& f, int e) { return f[e]; }
-};
-
 // the two hidden layers of the network for the wave's 32 samples as operand
 // fragments (ReLU applied): h1b for the second product, h2b for the output;
 // za holds zeros beyond |A|

@@ -47,6 +47,76 @@ struct OpF32 {
   static __device__ __forceinline__ S store(float x) { return x; }
 };
 
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU, ReLU-derivative mask and element sum of an operand fragment.
+template <class OP>
+struct FragOps;
+
+template <>
+struct FragOps<OpBF16> {
+  using frag = bf16x8;
+  // a BF16 value is negative exactly when its bits are, read as a signed
+  // 16-bit integer: max with 0 on packed pairs is the ReLU (v_pk_max_i16)
+  static __device__ __forceinline__ void relu(frag& f) {
+    const s16x8 x = __builtin_elementwise_max(__builtin_bit_cast(s16x8, f), (s16x8)0);
+    f = __builtin_bit_cast(frag, x);
+  }
+  // d = (h > 0) ? d : 0 per element, for h >= 0 (a ReLU output): min(h, 1)
+  // is 1 for every non-zero h and 0 for +0, and multiplies the bits of d
+  static __device__ __forceinline__ void mask(frag& d, const frag& h) {
+    u32x4v dv = __builtin_bit_cast(u32x4v, d);
+    const u32x4v hv = __builtin_bit_cast(u32x4v, h);
+    const unsigned one2 = 0x00010001u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      unsigned r;
+      asm("v_pk_min_u16 %0, %1, %2\n\tv_pk_mul_lo_u16 %0, %3, %0" : "=&v"(r) : "v"(hv[k]), "v"(one2), "v"(dv[k]));
+      dv[k] = r;
+    }
+    d = __builtin_bit_cast(frag, dv);
+  }
+  // acc + the sum of the eight elements (v_dot2 with ones)
+  static __device__ __forceinline__ float sum(const frag& f, float acc) {
+    const u32x4v v = __builtin_bit_cast(u32x4v, f);
+    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const unsigned w = v[k];
+      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), one, acc, false);
+    }
+    return acc;
+  }
+  // (whole vectors are bit_cast, then indexed: a bit_cast of one element
+  // f[e] compiles to element 0)
+  static __device__ __forceinline__ unsigned short bits(const frag& f, int e) {
+    const u16x8 u = __builtin_bit_cast(u16x8, f);
+    return u[e];
+  }
+};
+
+template <>
+struct FragOps<OpF32> {
+  using frag = f32x8;
+  static __device__ __forceinline__ void relu(frag& f) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = fmaxf(f[e], 0.0f);
+  }
+  static __device__ __forceinline__ void mask(frag& d, const frag& h) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = h[e] > 0.0f ? d[e] : 0.0f;
+  }
+  static __device__ __forceinline__ float sum(const frag& f, float acc) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += f[e];
+    return acc;
+  }
+  static __device__ __forceinline__ float bits(const frag& f, int e) { return f[e]; }
+};
+
 constexpr int FH = 64;       // hidden width
 constexpr int FK = 32;       // bins
 constexpr int FL_MAX = 8;    // layers
@@ -211,21 +281,21 @@ __device__ __forceinline__ void mlp_hidden(const float (&za)[FAB], int na, const
   typename OP::frag h1b[4];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    f32x16 h1 = OP::mma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
-#pragma unroll
-    for (int v = 0; v < 16; ++v) h1[v] = fmaxf(h1[v], 0.0f);
-    h1b[2 * t] = to_b<OP>(h1, 0);
-    h1b[2 * t + 1] = to_b<OP>(h1, 1);
+    const f32x16 p = OP::mma(W.w1p[(t * 32 + i) * 2 + h], bz, bias_tile(W.b1 + 32 * t, h));
+    h1b[2 * t] = to_b<OP>(p, 0);
+    h1b[2 * t + 1] = to_b<OP>(p, 1);
+    FragOps<OP>::relu(h1b[2 * t]);
+    FragOps<OP>::relu(h1b[2 * t + 1]);
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     f32x16 acc = bias_tile(W.b2 + 32 * t, h);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) acc = OP::mma(W.w2p[((t * 4 + kk) * 32 + i) * 2 + h], h1b[kk], acc);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v], 0.0f);
     h2b[2 * t] = to_b<OP>(acc, 0);
     h2b[2 * t + 1] = to_b<OP>(acc, 1);
+    FragOps<OP>::relu(h2b[2 * t]);
+    FragOps<OP>::relu(h2b[2 * t + 1]);
   }
 }
 
@@ -241,17 +311,23 @@ __device__ __forceinline__ f32x16 mlp_logits(const typename OP::frag (&h2b)[4], 
 
 // in place: exponentials of the 32 logits of one B dim less their maximum
 // (16 here, 16 in lane^32), unnormalised; returns their sum
+// e^(x - m) as 2^(x log2 e + nml) with nml = -m log2 e, on the hardware
+// exp2 (v_exp_f32, relative error ~1e-7): the scale is folded into one FMA;
+// the rounding of nml is common to all bins of a sample and cancels in the
+// softmax's normalisation.
+constexpr float FLOG2E = 1.44269504088896341f;
+__device__ __forceinline__ float exp_shifted(float x, float nml) { return __builtin_amdgcn_exp2f(fmaf(x, FLOG2E, nml)); }
+
 __device__ __forceinline__ float softexp32(f32x16& q) {
   float m = q[0];
 #pragma unroll
   for (int v = 1; v < 16; ++v) m = fmaxf(m, q[v]);
   m = fmaxf(m, xor32(m));
-  // exp via the hardware exp2 (v_exp_f32): arguments are <= 0 and the
-  // relative error (~1e-7) is far below the BF16 noise of the logits
+  const float nml = -m * FLOG2E;
   float s = 0.0f;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    q[v] = __expf(q[v] - m);
+    q[v] = exp_shifted(q[v], nml);
     s += q[v];
   }
   return s + xor32(s);
@@ -401,13 +477,12 @@ __device__ __forceinline__ float softexp_own(f32x16& lo, f32x16& hi) {
   float m = fmaxf(lo[0], hi[0]);
 #pragma unroll
   for (int v = 1; v < 16; ++v) m = fmaxf(m, fmaxf(lo[v], hi[v]));
-  // exp via the hardware exp2 (v_exp_f32): arguments are <= 0 and the
-  // relative error (~1e-7) is far below the BF16 noise of the logits
+  const float nml = -m * FLOG2E;
   float s = 0.0f;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    lo[v] = __expf(lo[v] - m);
-    hi[v] = __expf(hi[v] - m);
+    lo[v] = exp_shifted(lo[v], nml);
+    hi[v] = exp_shifted(hi[v], nml);
   }
   // bin-order sum in groups of four
 #pragma unroll
