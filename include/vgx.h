@@ -30,6 +30,22 @@
  *   - The library runs on the device current at the call (hipSetDevice);
  *     a context must be used on the device it was created on.
  *   - Calls on one context are not thread-safe; distinct contexts are.
+ *
+ * Environment
+ *   - VGX_TRACE=<file> ("-": standard error): every estimate a synchronous
+ *     call reads back (vegas_iterate, vegas_iterate_points,
+ *     flow_vegas_iterate) is appended as one JSON line: the record, the
+ *     combination after it, chi^2/dof, and an FNV-1a hash of the grid it was
+ *     sampled on.
+ *   - VGX_FAIL_ALLOC=k: the k-th device or pinned-host allocation counted
+ *     from the variable's last change fails with VGX_ENOMEM (for tests of
+ *     the error paths; stream-ordered scratch allocations are not counted).
+ *
+ * Checkpoint and resume: an iteration depends only on its grid and its
+ * Philox counters, so saving the grid (vegas_get_grid) and the records
+ * (vegas_results), and continuing with the same iteration indices on a
+ * context given that grid (vegas_set_grid), reproduces an uninterrupted
+ * run's records bit for bit.
  */
 #ifndef VGX_H
 #define VGX_H

@@ -2,6 +2,10 @@
 // device properties.
 #include "common.h"
 
+#include <mutex>
+#include <stdlib.h>
+#include <string>
+
 namespace vgx {
 
 static thread_local char g_err[512] = "";
@@ -18,8 +22,31 @@ vgx_status hip_fail(hipError_t e, const char* what, const char* file, int line) 
   return (e == hipErrorOutOfMemory) ? VGX_ENOMEM : VGX_EDEVICE;
 }
 
+// Failure injection for tests of the error paths: with VGX_FAIL_ALLOC=k in
+// the environment, the k-th allocation (device or pinned host) counted from
+// the last change of that variable fails with VGX_ENOMEM.
+static bool injected_failure() {
+  static std::mutex mu;
+  static std::string last;
+  static long count = 0;
+  const char* v = getenv("VGX_FAIL_ALLOC");
+  std::lock_guard<std::mutex> lock(mu);
+  const std::string cur = v ? v : "";
+  if (cur != last) {
+    last = cur;
+    count = 0;
+  }
+  if (cur.empty()) return false;
+  const long k = strtol(cur.c_str(), nullptr, 10);
+  return k > 0 && ++count == k;
+}
+
 vgx_status dev_alloc(void** p, size_t bytes) {
   *p = nullptr;
+  if (injected_failure()) {
+    set_error("hipMalloc(%zu): failure injected by VGX_FAIL_ALLOC", bytes);
+    return VGX_ENOMEM;
+  }
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
@@ -33,6 +60,10 @@ vgx_status dev_alloc(void** p, size_t bytes) {
 
 vgx_status host_alloc(void** p, size_t bytes) {
   *p = nullptr;
+  if (injected_failure()) {
+    set_error("hipHostMalloc(%zu): failure injected by VGX_FAIL_ALLOC", bytes);
+    return VGX_ENOMEM;
+  }
   hipError_t e = hipHostMalloc(p, bytes ? bytes : 16, hipHostMallocDefault);
   if (e != hipSuccess) {
     *p = nullptr;

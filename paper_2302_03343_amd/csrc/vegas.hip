@@ -1048,6 +1048,37 @@ enum RecordKind { REC_PLAIN = 0, REC_POINTS = 1, REC_PROPOSAL = 2 };
 // Plain VEGAS judges a proposal: a finite proposal estimate whose variance
 // per sample, n var(E), exceeds that of the latest plain iteration read
 // back returns VGX_EFALLBACK (the estimate is unbiased and stays recorded).
+// With VGX_TRACE set to a file name ("-": standard error), every estimate
+// read back is appended there as one JSON line: the record, the combination
+// after it, and an FNV-1a hash of the grid it was sampled on.
+void trace_record(vgx_vegas* v, int k, const IterRecord* h, const Combined* hc, RecordKind kind) {
+  const char* path = getenv("VGX_TRACE");
+  if (!path || !*path) return;
+  const size_t ne = (size_t)v->dim * (v->nb + 1);
+  double* g = (double*)((char*)v->pinned + sizeof(IterRecord) * MAX_RECORDS + sizeof(Combined));
+  uint64_t hash = 14695981039346656037ull;
+  if (hipMemcpyAsync(g, v->edges, sizeof(double) * ne, hipMemcpyDeviceToHost, v->stream) == hipSuccess &&
+      hipStreamSynchronize(v->stream) == hipSuccess) {
+    const unsigned char* b = (const unsigned char*)g;
+    for (size_t i = 0; i < sizeof(double) * ne; ++i) hash = (hash ^ b[i]) * 1099511628211ull;
+  } else {
+    (void)hipGetLastError();
+    hash = 0;
+  }
+  static const char* kinds[] = {"plain", "points", "proposal"};
+  const bool err = strcmp(path, "-") == 0;
+  FILE* fp = err ? stderr : fopen(path, "a");
+  if (!fp) return;
+  fprintf(fp,
+          "{\"context\": \"%p\", \"record\": %d, \"kind\": \"%s\", \"n\": %lld, \"mean\": %.17g, \"var\": %.17g, "
+          "\"finite\": %d, \"combined_mean\": %.17g, \"combined_sigma\": %.17g, \"chi2_dof\": %.17g, "
+          "\"records_used\": %d, \"grid_fnv1a\": \"%016llx\"}\n",
+          (void*)v, k, kinds[kind], (long long)h->n, h->mean, h->var, (int)h->finite, hc->mean, hc->sigma, hc->chi2_dof,
+          (int)hc->n_used, (unsigned long long)hash);
+  if (err) fflush(fp);
+  else fclose(fp);
+}
+
 vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out, RecordKind kind) {
   IterRecord* h = (IterRecord*)v->pinned;
   Combined* hc = (Combined*)((char*)v->pinned + sizeof(IterRecord) * MAX_RECORDS);
@@ -1055,6 +1086,7 @@ vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out, RecordKind kin
   VGX_HIP(hipMemcpyAsync(hc, v->comb, sizeof(Combined), hipMemcpyDeviceToHost, v->stream));
   VGX_HIP(hipStreamSynchronize(v->stream));
   v->comb_fresh = true;
+  trace_record(v, k, h, hc, kind);
   if (out) {
     out->mean = h->mean;
     out->var = h->var;
