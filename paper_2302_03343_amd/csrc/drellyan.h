@@ -46,6 +46,10 @@ struct DrellYan {
     P.c = c.pdf;
     P.stage(lds);
   }
+  __device__ void layout(float* lds) {
+    P.c = c.pdf;
+    P.layout(lds);
+  }
 
   __device__ __forceinline__ double eval(const double (&x)[3]) const {
     const double ltau = c.Llo - x[0] * c.Lr;     // ln(1/tau)

@@ -88,13 +88,19 @@ struct PdfRows {
   float* sa;        // LDS ln x knots [nxs]
   float4* cw;       // LDS per cell: knot_cell_data
 
-  __device__ void stage(float* lds) {
-    float* Fs = lds;
+  // the tables' places in an LDS block of pdf_rows_lds_floats(nxs) floats
+  __device__ void layout(float* lds) {
     F = (const float4*)lds;
+    nq4 = (c.nxs + 3) >> 2;
+    sa = lds + nq4 * 4 * 4 * TT_NF;
+    cw = (float4*)(sa + ((c.nxs + 3) & ~3));
+  }
+
+  // layout and fill the tables (every thread of the workgroup)
+  __device__ void stage(float* lds) {
+    layout(lds);
+    float* Fs = lds;
     const int nxs = c.nxs;
-    nq4 = (nxs + 3) >> 2;
-    sa = Fs + nq4 * 4 * 4 * TT_NF;
-    cw = (float4*)(sa + ((nxs + 3) & ~3));
     const int nr = c.n_rows;
     const int tot = nq4 * 4 * TT_NF * 4;
     const double* lx = c.lx + c.ix0;

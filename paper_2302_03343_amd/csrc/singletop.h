@@ -40,6 +40,10 @@ struct SingleTop {
     P.c = c.pdf;
     P.stage(lds);
   }
+  __device__ void layout(float* lds) {
+    P.c = c.pdf;
+    P.layout(lds);
+  }
 
   __device__ __forceinline__ double eval(const double (&x)[3]) const {
     const double v = x[0] * c.L0;                  // ln(s_hat/m_t^2)

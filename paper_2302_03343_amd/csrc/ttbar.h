@@ -50,6 +50,10 @@ struct TTbar {
     P.c = c.pdf;
     P.stage(lds);
   }
+  __device__ void layout(float* lds) {
+    P.c = c.pdf;
+    P.layout(lds);
+  }
 
   __device__ __forceinline__ double eval(const double (&x)[3]) const {
     // kinematics in FP64 (a handful of operations), then FP32

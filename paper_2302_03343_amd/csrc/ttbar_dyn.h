@@ -99,20 +99,27 @@ struct TTbarDyn {
   float* sal;       // ln Q^2 knots of the alpha_s subgrid [a_nq]
   float* sav;       // alpha_s values [a_nq]
 
-  __device__ void stage(float* lds) {
+  // the tables' places in an LDS block of ttdyn_lds_floats floats
+  __device__ void layout(float* lds) {
     const int nxs = c.nxs, R = c.R;
     nq4 = (nxs + 3) >> 2;
     F = (const float4*)lds;
+    sa = lds + R * nq4 * 4 * 12;
+    cwa = (const float4*)(sa + ((nxs + 3) & ~3));
+    sb = (float*)(cwa + nxs);
+    cwb = (const float4*)(sb + ((R + 3) & ~3));
+    sal = (float*)(cwb + R);
+    sav = sal + c.a_nq;
+  }
+
+  // layout and fill the tables (every thread of the workgroup)
+  __device__ void stage(float* lds) {
+    layout(lds);
+    const int nxs = c.nxs, R = c.R;
     float* Fs = lds;
     const int plane = nq4 * 4 * 12;  // floats per staged row
-    sa = Fs + R * plane;
-    float4* wa = (float4*)(sa + ((nxs + 3) & ~3));
-    sb = (float*)(wa + nxs);
-    float4* wb = (float4*)(sb + ((R + 3) & ~3));
-    sal = (float*)(wb + R);
-    sav = sal + c.a_nq;
-    cwa = wa;
-    cwb = wb;
+    float4* wa = const_cast<float4*>(cwa);
+    float4* wb = const_cast<float4*>(cwb);
     const int tot = R * plane;
     for (int k = threadIdx.x; k < tot; k += blockDim.x) {
       const int f = k % 12;

@@ -51,6 +51,10 @@ struct VegasArgs {
   int hcopies;   // histogram copies in LDS: 4 per wave, one per wave, or 1 (shared)
   double nbD;    // nb^dim, the Jacobian's constant factor
   double sc;     // nb 2^-32: t = u nb = (word + 1/2) sc
+  // the integrand's LDS tables as staged once for the context (copied by
+  // each workgroup), or null (each workgroup stages them itself)
+  const float* tables;
+  int table_bytes;  // a multiple of 16
 };
 
 // Histogram copies a workgroup keeps in LDS: one per wave when they fit in
@@ -143,6 +147,33 @@ __host__ __device__ inline int lds_table_offset(int D, int nb, bool hist, bool l
 }
 
 // ---------------------------------------------------------------------------
+// Integrand tables in LDS.  An integrand that stages tables (PDF rows, knots,
+// per-cell Hermite inputs) computes them from the PDF grid with scattered
+// loads and index arithmetic; k_stage_tables does that once per context, in
+// one workgroup, and stores the LDS block as it stands, so that each
+// workgroup of a launch only copies it (16-byte loads, all in flight): the
+// same LDS contents, bit for bit.
+// ---------------------------------------------------------------------------
+template <class F>
+__global__ __launch_bounds__(BLOCK) void k_stage_tables(F f, float* __restrict__ out, int bytes) {
+  extern __shared__ __align__(16) float tl[];
+  F ff = f;
+  ff.stage(tl);
+  __syncthreads();
+  copy16(out, tl, bytes);
+}
+
+template <class F>
+__device__ __forceinline__ void stage_tables(F& ff, float* extra, const VegasArgs& a) {
+  if (a.tables) {
+    ff.layout(extra);
+    copy16(extra, a.tables, a.table_bytes);
+  } else {
+    ff.stage(extra);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused iteration kernel.
 // LDS: edges [D][nb+1] | histogram [D][nb] (HIST) | integrand staging.
 // Partial row per workgroup: [S1.s, S1.c, S2.s, S2.c, hist[D][nb]].
@@ -170,7 +201,7 @@ __global__ __launch_bounds__(BLOCK, Src::kInterior ? MinWaves<F>::value : 1) voi
   if (HIST)
     for (int k = threadIdx.x; k < a.hcopies * D * nb; k += BLOCK) sh[k] = 0.0;
   F ff = f;
-  if constexpr (F::kStage) ff.stage(extra);
+  if constexpr (F::kStage) stage_tables(ff, extra, a);
   __syncthreads();
   // The epilogue rebuilds the thread index from the wave index (uniform, so
   // a scalar register) and the lane (mbcnt), so that no vector register has
@@ -291,7 +322,7 @@ __global__ __launch_bounds__(FI_BLOCK) void k_flow_iter(VegasArgs a, F f, FlowIt
   float* z = (float*)(fl + fwd_z_offset(FD.fw_total, FD.bias_total, (int)sizeof(S))) + threadIdx.x;
   for (int k = threadIdx.x; k < D * (nb + 1); k += FI_BLOCK) se[k] = a.edges[k];
   F ff = f;
-  if constexpr (F::kStage) ff.stage(extra);
+  if constexpr (F::kStage) stage_tables(ff, extra, a);
   copy16(sfw, fa.fw, FD.fw_total * (int)sizeof(S));
   copy16(sb, fa.bias, FD.bias_total * 4);
   __syncthreads();
@@ -420,7 +451,7 @@ __global__ __launch_bounds__(BLOCK) void k_vegas_sample(VegasArgs a, F f, Philox
   float* extra = (float*)(lds + lds_table_offset(D, nb, false, !F::kStage));
   for (int k = threadIdx.x; k < D * (nb + 1); k += BLOCK) se[k] = a.edges[k];
   F ff = f;
-  if constexpr (F::kStage) ff.stage(extra);
+  if constexpr (F::kStage) stage_tables(ff, extra, a);
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += stride) {
@@ -444,13 +475,15 @@ namespace {
 
 bool uses_pdf(int kind) { return kind == VGX_TTBAR || kind == VGX_DRELLYAN || kind == VGX_SINGLETOP; }
 
+// Bytes of the integrand's LDS tables, a multiple of 16 (they are copied in
+// 16-byte pieces).
 size_t extra_lds_bytes(const vgx_vegas* v) {
-  if (v->kind == VGX_TTBAR && v->tt_dyn)
-    return sizeof(float) * (size_t)ttdyn_lds_floats(v->ttd.nxs, v->ttd.R, v->ttd.a_nq);
-  if (v->kind == VGX_TTBAR) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->tt.pdf.nxs);
-  if (v->kind == VGX_DRELLYAN) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->dy.pdf.nxs);
-  if (v->kind == VGX_SINGLETOP) return sizeof(float) * (size_t)pdf_rows_lds_floats(v->st.pdf.nxs);
-  return 0;
+  size_t floats = 0;
+  if (v->kind == VGX_TTBAR && v->tt_dyn) floats = (size_t)ttdyn_lds_floats(v->ttd.nxs, v->ttd.R, v->ttd.a_nq);
+  else if (v->kind == VGX_TTBAR) floats = (size_t)pdf_rows_lds_floats(v->tt.pdf.nxs);
+  else if (v->kind == VGX_DRELLYAN) floats = (size_t)pdf_rows_lds_floats(v->dy.pdf.nxs);
+  else if (v->kind == VGX_SINGLETOP) floats = (size_t)pdf_rows_lds_floats(v->st.pdf.nxs);
+  return (sizeof(float) * floats + 15) & ~(size_t)15;
 }
 
 // Resident workgroups per CU of a hadronic integrand's iteration kernel (its
@@ -470,6 +503,41 @@ int hadronic_blocks_per_cu(const vgx_vegas* v) {
     occ = 4;
   }
   return occ > 8 ? 8 : occ;
+}
+
+template <class F>
+vgx_status stage_tables_once(vgx_vegas* v, const F& f) {
+  const int bytes = v->table_bytes;
+  if (bytes > 65536)
+    VGX_HIP(hipFuncSetAttribute((const void*)k_stage_tables<F>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  hipLaunchKernelGGL((k_stage_tables<F>), dim3(1), dim3(BLOCK), (size_t)bytes, v->stream, f, v->tables, bytes);
+  VGX_HIP(hipGetLastError());
+  return VGX_OK;
+}
+
+// The hadronic integrands' LDS tables, staged once into v->tables.
+vgx_status build_tables(vgx_vegas* v) {
+  if (!uses_pdf(v->kind)) return VGX_OK;
+  v->table_bytes = (int)extra_lds_bytes(v);
+  VGX_TRY(dev_alloc((void**)&v->tables, (size_t)v->table_bytes));
+  if (v->kind == VGX_TTBAR && v->tt_dyn) {
+    TTbarDyn f{};
+    f.c = v->ttd;
+    return stage_tables_once(v, f);
+  }
+  if (v->kind == VGX_TTBAR) {
+    TTbar f{};
+    f.c = v->tt;
+    return stage_tables_once(v, f);
+  }
+  if (v->kind == VGX_DRELLYAN) {
+    DrellYan f{};
+    f.c = v->dy;
+    return stage_tables_once(v, f);
+  }
+  SingleTop f{};
+  f.c = v->st;
+  return stage_tables_once(v, f);
 }
 
 int grid_for(const vgx_vegas* v, int64_t n) {
@@ -747,7 +815,7 @@ double pow_int(double b, int e) {
 template <int D, class F, class Src, bool HIST>
 vgx_status launch_iter_f(vgx_vegas* v, int64_t n, const F& f, const Src& src) {
   VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), pow_int((double)v->nb, D),
-              v->nb * 0x1p-32};
+              v->nb * 0x1p-32, v->tables, v->table_bytes};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, HIST, !F::kStage) + extra_lds_bytes(v);
   if (src.seg_len(0, n) == n)  // one segment: the common case
@@ -819,7 +887,7 @@ vgx_status launch_iter_d(vgx_vegas* v, int64_t n, const Src& src) {
 template <int D, class F>
 vgx_status launch_sample_f(vgx_vegas* v, int64_t first, int64_t n, int32_t it, const F& f, double* u, double* g) {
   VegasArgs a{n, v->edges, v->nb, v->pstride, hist_copies(D, v->nb, !F::kStage), pow_int((double)v->nb, D),
-              v->nb * 0x1p-32};
+              v->nb * 0x1p-32, v->tables, v->table_bytes};
   PhiloxSrc<D> src{(uint32_t)it, v->stream_id, (uint32_t)v->seed, (uint32_t)(v->seed >> 32), first};
   const int grid = grid_for(v, n);
   const size_t lds = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false, !F::kStage) + extra_lds_bytes(v);
@@ -938,7 +1006,8 @@ vgx_status launch_points_iter(vgx_vegas* v, int64_t n, const double* y, const do
 // grid (the partial rows to reduce).
 template <int D, class F>
 vgx_status launch_flow_iter_f(vgx_vegas* v, const FlowView& fv, int64_t n, FlowIterArgs fa, const F& f, int* grid) {
-  VegasArgs a{n, v->edges, v->nb, v->pstride, 1, pow_int((double)v->nb, D), v->nb * 0x1p-32};
+  VegasArgs a{n, v->edges, v->nb, v->pstride, 1, pow_int((double)v->nb, D), v->nb * 0x1p-32, v->tables,
+              v->table_bytes};
   const size_t base = sizeof(double) * (size_t)lds_table_offset(D, v->nb, false, !F::kStage) + extra_lds_bytes(v);
   const size_t off = (base + 15) & ~(size_t)15;
   const size_t lds = off + fwd_z_offset(fv.fw_total, fv.bias_total, 2) + sizeof(float) * (size_t)D * FI_BLOCK;
@@ -1143,6 +1212,7 @@ extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_veg
     if ((s = dev_alloc((void**)&v->rec, sizeof(IterRecord) * MAX_RECORDS)) != VGX_OK) break;
     if ((s = dev_alloc((void**)&v->comb, sizeof(Combined))) != VGX_OK) break;
     if ((s = host_alloc(&v->pinned, sizeof(IterRecord) * MAX_RECORDS + sizeof(Combined) + sizeof(double) * ne)) != VGX_OK) break;
+    if ((s = build_tables(v)) != VGX_OK) break;
   } while (0);
   if (s != VGX_OK) { vegas_destroy(v); return s; }
   double* h = (double*)v->pinned;
@@ -1351,6 +1421,7 @@ extern "C" void vegas_destroy(vgx_vegas* v) {
   hipFree(v->edges);
   hipFree(v->hist);
   hipFree(v->partials);
+  hipFree(v->tables);
   hipFree(v->rec);
   hipFree(v->comb);
   if (v->pinned) hipHostFree(v->pinned);

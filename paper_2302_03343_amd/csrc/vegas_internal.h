@@ -304,6 +304,8 @@ struct vgx_vegas {
   double* edges = nullptr;          // [dim][nb+1]
   double* hist = nullptr;           // [dim][nb]
   double* partials = nullptr;       // [max_wg][pstride]
+  float* tables = nullptr;          // the integrand's LDS tables, staged once (hadronic kinds)
+  int table_bytes = 0;
   vgx::IterRecord* rec = nullptr;   // [MAX_RECORDS]
   vgx::Combined* comb = nullptr;
   void* pinned = nullptr;           // host readback (IterRecord + Combined + grid)
