@@ -799,7 +799,10 @@ def main():
         vgx.vegas_refine(v)
         it += 1
     torch.cuda.synchronize()
-    vgx.vegas_set_timing(v, True)
+    # the kernel's own duration from HIP events around ten of the timed
+    # launches, spread evenly (each event pair delays the next launch by a
+    # few microseconds)
+    vgx.vegas_set_timing(v, True, every=max(1, args.steps // 10))
     t0 = time.perf_counter()
     # GPU-resident loop: estimates, combination and refinement stay on the
     # device; the host reads the combined result once after the loop

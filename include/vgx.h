@@ -352,12 +352,15 @@ void* vegas_stream(vgx_vegas* v);
 /* Dimension and bins per dimension of a context (either may be NULL). */
 vgx_status vegas_shape(const vgx_vegas* v, int32_t* dim, int32_t* n_bins);
 
-/* Kernel timing (for measurement): when enabled, HIP events on the
- * context's stream bracket every fused sampling kernel (recording does not
+/* Kernel timing (for measurement): every = 0 turns it off; every = k >= 1
+ * brackets one fused sampling kernel in k (the first after the call, then
+ * every k-th) with HIP events on the context's stream (recording does not
  * synchronise; the events carry no system-scope fence, so they add no cache
- * write-back); vegas_kernel_time (sync) returns the summed milliseconds and
- * the number of launches since timing was enabled. */
-vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable);
+ * write-back, but each record still delays the next launch by a few
+ * microseconds, which k > 1 spreads over k launches); vegas_kernel_time
+ * (sync) returns the summed milliseconds and the number of launches timed
+ * since timing was enabled. */
+vgx_status vegas_set_timing(vgx_vegas* v, int32_t every);
 vgx_status vegas_kernel_time(vgx_vegas* v, double* ms_host, int64_t* launches_host);
 
 void vegas_destroy(vgx_vegas* v);

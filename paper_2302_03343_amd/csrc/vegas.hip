@@ -972,8 +972,11 @@ vgx_status timed_flush(vgx_vegas* v) {
   return VGX_OK;
 }
 
+// Whether the launch about to be enqueued is one of the timed ones.
+bool timed_now(const vgx_vegas* v) { return v->timing && v->t_seen % v->t_every == 0; }
+
 vgx_status timed_begin(vgx_vegas* v) {
-  if (!v->timing) return VGX_OK;
+  if (!timed_now(v)) return VGX_OK;
   if (v->t_pending == vgx_vegas::kTimerPairs) VGX_TRY(timed_flush(v));
   VGX_HIP(hipEventRecord(v->ev[2 * v->t_pending], v->stream));
   return VGX_OK;
@@ -981,8 +984,11 @@ vgx_status timed_begin(vgx_vegas* v) {
 
 vgx_status timed_end(vgx_vegas* v) {
   if (!v->timing) return VGX_OK;
-  VGX_HIP(hipEventRecord(v->ev[2 * v->t_pending + 1], v->stream));
-  v->t_pending += 1;
+  if (timed_now(v)) {
+    VGX_HIP(hipEventRecord(v->ev[2 * v->t_pending + 1], v->stream));
+    v->t_pending += 1;
+  }
+  v->t_seen += 1;
   return VGX_OK;
 }
 
@@ -1392,8 +1398,10 @@ extern "C" vgx_status vegas_shape(const vgx_vegas* v, int32_t* dim, int32_t* n_b
   return VGX_OK;
 }
 
-extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
+extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t every) {
   VGX_CHECK(v, "vegas_set_timing: null context");
+  VGX_CHECK(every >= 0, "vegas_set_timing: every must be >= 0");
+  const int enable = every > 0;
   if (enable && !v->ev[0]) {
     // the events only time: no system-scope fence (cache write-back and
     // invalidation) at each record, which would slow the work they bracket
@@ -1401,6 +1409,8 @@ extern "C" vgx_status vegas_set_timing(vgx_vegas* v, int32_t enable) {
       VGX_HIP(hipEventCreateWithFlags(&v->ev[k], hipEventDisableSystemFence));
   }
   v->timing = enable != 0;
+  v->t_every = enable ? every : 1;
+  v->t_seen = 0;
   v->t_pending = 0;
   v->t_ms = 0.0;
   v->t_launches = 0;

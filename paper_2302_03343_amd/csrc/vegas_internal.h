@@ -317,6 +317,8 @@ struct vgx_vegas {
   // (and summed) only when asked for, so timing does not synchronise
   static constexpr int kTimerPairs = 256;
   bool timing = false;
+  int t_every = 1;                  // time one launch in t_every
+  int64_t t_seen = 0;               // launches since timing was enabled
   hipEvent_t ev[2 * kTimerPairs] = {};
   int t_pending = 0;
   double t_ms = 0.0;

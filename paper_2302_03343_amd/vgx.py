@@ -532,8 +532,9 @@ def vegas_stream(v):
     return _c["vegas_stream"](v)
 
 
-def vegas_set_timing(v, enable=True):
-    _check(_c["vegas_set_timing"](v, 1 if enable else 0), "vegas_set_timing")
+def vegas_set_timing(v, enable=True, every=1):
+    """Time one fused kernel in `every` (enable=False: off)."""
+    _check(_c["vegas_set_timing"](v, int(every) if enable else 0), "vegas_set_timing")
 
 
 def vegas_kernel_time(v):

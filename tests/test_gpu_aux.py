@@ -133,3 +133,24 @@ def test_injected_allocation_failures_return_enomem_and_leak_nothing(vgx, c1_gri
             destroy(make())  # works again
     finally:
         vgx.pdf_destroy(pdf)
+
+
+def test_kernel_timing_samples_one_launch_in_k(vgx):
+    """vegas_set_timing(every=k) brackets launches 0, k, 2k, ... after the
+    call; vegas_kernel_time returns their count and summed duration."""
+    v = _gauss_ctx(vgx, seed=3)
+    try:
+        for every, n_launch, timed in ((1, 7, 7), (3, 10, 4), (4, 8, 2)):
+            vgx.vegas_set_timing(v, True, every=every)
+            for it in range(n_launch):
+                vgx.vegas_iterate_async(v, 200_000, it)
+            ms, launches = vgx.vegas_kernel_time(v)
+            print(f"  every={every}: {launches} timed launches, {ms / max(launches, 1):.4f} ms each", flush=True)
+            assert launches == timed and ms > 0.0
+        vgx.vegas_set_timing(v, False)
+        vgx.vegas_iterate_async(v, 1000, 99)
+        assert vgx.vegas_kernel_time(v)[1] == 0
+        with pytest.raises(vgx.VgxError):
+            vgx._check(vgx._c["vegas_set_timing"](v, -1), "vegas_set_timing")
+    finally:
+        vgx.vegas_destroy(v)
