@@ -268,7 +268,11 @@ typedef struct {
   int32_t prec;             /* VGX_F64 or VGX_F32 integrand arithmetic          */
   const double* params;     /* host, integrand parameters (see the kinds)       */
   int32_t n_params;
-  const vgx_pdf* pdf;       /* hadronic kinds only; must outlive the context    */
+  const vgx_pdf* pdf;       /* hadronic kinds only; must outlive the context.
+                               The LDS tables the integrand reads (PDF rows,
+                               knots, alpha_s) are taken from it once, at
+                               creation: a later pdf_set_alphas leaves an
+                               existing context as it was.                      */
 } vgx_vegas_cfg;
 
 typedef struct {
