@@ -235,3 +235,33 @@ def test_dynamic_scale_needs_alphas(vgx, c1_grid):
             vgx.vegas_create(vgx.TTBAR, 3, 50, 1.5, 1, 0, vgx.F32, np.concatenate([PARAMS, [2.0]]), pdf=pdf)
     finally:
         vgx.pdf_destroy(pdf)
+
+
+def test_dynamic_scale_context_keeps_its_tables(vgx, c1_grid):
+    """A context takes the PDF rows and the alpha_s table into its staged
+    tables once, at creation: replacing the PDF's alpha_s table afterwards
+    leaves its iterations bit for bit as they were, while a context created
+    after the change sees the new table."""
+    from synth import synthetic_alphas
+    print("ttbar mode 2: tables taken at creation", flush=True)
+    table = synthetic_alphas(c1_grid)
+    pdf = vgx.pdf_create(c1_grid.x_knots, c1_grid.q2_knots, c1_grid.xf)
+    params = np.concatenate([PARAMS, [2.0]])
+    mk = lambda: vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], C2["seed"], 0, vgx.F32, params, pdf=pdf)
+    v = w = None
+    try:
+        vgx.pdf_set_alphas(pdf, table.q2_knots, table.values)
+        v = mk()
+        r0 = vgx.vegas_iterate(v, 100_000, 0)
+        vgx.pdf_set_alphas(pdf, table.q2_knots, [1.1 * np.asarray(a) for a in table.values])
+        r1 = vgx.vegas_iterate(v, 100_000, 0)
+        w = mk()
+        r2 = vgx.vegas_iterate(w, 100_000, 0)
+        assert r1["s1"] == r0["s1"] and r1["s2"] == r0["s2"]
+        # |M|^2 goes as alpha_s^2: the new context's estimate moves by about 1.21
+        assert r2["mean"] == pytest.approx(1.21 * r0["mean"], rel=1e-4)
+    finally:
+        for c in (v, w):
+            if c is not None:
+                vgx.vegas_destroy(c)
+        vgx.pdf_destroy(pdf)
