@@ -71,6 +71,37 @@ def test_per_event_integrand(vgx, pdf_ctx, c1_grid, grid_kind, mode):
         vgx.vegas_destroy(v)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("sqrt_s,m_top", [(2000.0, 172.5), (7000.0, 173.0), (100000.0, 173.0)])
+def test_per_event_integrand_other_energies(vgx, pdf_ctx, c1_grid, sqrt_s, m_top, mode):
+    """Other collider energies and top masses move the smallest reachable
+    momentum fraction tau0 = 4 m^2/s, hence how many x nodes the context
+    stages (about 30 at 2 TeV, 130 at 100 TeV) and the size of the tables
+    every workgroup copies; per event against the oracle."""
+    import torch
+    print(f"ttbar per-event at sqrt_s={sqrt_s} m_t={m_top}, mode {mode}", flush=True)
+    params = np.array([sqrt_s, m_top, C2["alpha_s"], C2["gev2_to_pb"], float(mode)])
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], 5, 0, vgx.F32, params, pdf=pdf_ctx)
+    try:
+        n = 40_000
+        g = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.vegas_sample(v, 0, n, 2, g=g)
+        got = g.cpu().numpy()
+    finally:
+        vgx.vegas_destroy(v)
+    u = sample_uniforms(5, 0, 2, np.arange(n, dtype=np.uint64), 3)
+    x, jac, _ = ov.vegas_map(u, ov.uniform_grid(3, C2["n_bins"]))
+    ref = ttbar.integrand(x, c1_grid, sqrt_s, m_top, C2["alpha_s"], C2["gev2_to_pb"]) * jac
+    k = ttbar.phase_space(x, sqrt_s, m_top)
+    xk = c1_grid.x_knots
+    keep = np.ones(n, dtype=bool)
+    for xv in (k["x1"], k["x2"]):
+        i = np.clip(np.searchsorted(xk, xv), 1, len(xk) - 1)
+        keep &= np.minimum(np.abs(xv - xk[i - 1]), np.abs(xv - xk[i])) / xv >= 1e-6
+    assert keep.sum() > 0.999 * n
+    check_events(got, ref, keep, f"ttbar sqrt_s={sqrt_s} mode {mode}")
+
+
 def test_iteration_sums(vgx, pdf_ctx, c1_grid):
     print("ttbar one iteration 2e5", flush=True)
     v = make(vgx, pdf_ctx)
