@@ -259,6 +259,42 @@ def test_dynamic_scale_iteration_and_quadrature(vgx, pdf_ctx, c1_grid):
     assert res["sigma"] / res["mean"] < 2e-3
 
 
+@pytest.mark.parametrize("sqrt_s", [7000.0, 100000.0])
+def test_dynamic_scale_per_event_other_energies(vgx, pdf_ctx, c1_grid, sqrt_s):
+    """The per-event scale spans [m_t^2, s/4]: other energies change how many
+    Q^2 rows the context stages (about 10 at 7 TeV, 30 at 100 TeV) besides the
+    x nodes; per event against the oracle."""
+    import torch
+    from synth import synthetic_alphas
+    print(f"ttbar mode 2 per-event at sqrt_s={sqrt_s}", flush=True)
+    table = synthetic_alphas(c1_grid)
+    vgx.pdf_set_alphas(pdf_ctx, table.q2_knots, table.values)
+    params = np.array([sqrt_s, C2["m_top"], C2["alpha_s"], C2["gev2_to_pb"], 2.0])
+    v = vgx.vegas_create(vgx.TTBAR, 3, C2["n_bins"], C2["alpha"], 4, 0, vgx.F32, params, pdf=pdf_ctx)
+    try:
+        n = 40_000
+        g = torch.empty(n, dtype=torch.float64, device="cuda")
+        vgx.vegas_sample(v, 0, n, 3, g=g)
+        got = g.cpu().numpy()
+    finally:
+        vgx.vegas_destroy(v)
+    u = sample_uniforms(4, 0, 3, np.arange(n, dtype=np.uint64), 3)
+    x, jac, _ = ov.vegas_map(u, ov.uniform_grid(3, C2["n_bins"]))
+    ref = ttbar.integrand_dynamic(x, c1_grid, table, sqrt_s, C2["m_top"], C2["gev2_to_pb"]) * jac
+    k = ttbar.phase_space(x, sqrt_s, C2["m_top"])
+    xk = c1_grid.x_knots
+    qk = np.concatenate(c1_grid.q2_knots)
+    keep = np.ones(n, dtype=bool)
+    for xv in (k["x1"], k["x2"]):
+        i = np.clip(np.searchsorted(xk, xv), 1, len(xk) - 1)
+        keep &= np.minimum(np.abs(xv - xk[i - 1]), np.abs(xv - xk[i])) / xv >= 1e-6
+    mu2 = k["shat"] / 4
+    i = np.clip(np.searchsorted(qk, mu2), 1, len(qk) - 1)
+    keep &= np.minimum(np.abs(mu2 - qk[i - 1]), np.abs(mu2 - qk[i])) / mu2 >= 1e-6
+    assert keep.sum() > 0.999 * n
+    check_events(got, ref, keep, f"ttbar mode 2 sqrt_s={sqrt_s}")
+
+
 def test_dynamic_scale_needs_alphas(vgx, c1_grid):
     pdf = vgx.pdf_create(c1_grid.x_knots, c1_grid.q2_knots, c1_grid.xf)
     try:
