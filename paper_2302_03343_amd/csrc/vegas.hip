@@ -12,11 +12,13 @@
 // (1978), which the thesis cites but does not print.
 //
 // MI355X design
-//   * one fused kernel per iteration, grid-stride over 64-bit sample indices,
-//     no per-sample buffers: uniforms are regenerated from the counter;
+//   * one fused kernel per iteration, grid-stride over the sample indices
+//     (32-bit within segments whose counters do not carry), no per-sample
+//     buffers: uniforms are regenerated from the counter;
 //   * the grid edges (d x (N+1) FP64) and the per-workgroup histogram
-//     (d x N FP64, LDS atomics) live in LDS; integrand tables (t tbar PDF
-//     rows) are staged there too;
+//     (d x N FP64, LDS atomics) live in LDS; integrand tables (the PDF rows
+//     of the hadronic integrands) too, staged once per context and copied
+//     by every workgroup;
 //   * S1, S2 are FP64 sums compensated per 16-sample chunk (Neumaier), wave
 //     reduced with cross-lane shuffles and written as per-workgroup partials;
 //     a second kernel reduces the partials in a fixed order (no float
