@@ -471,6 +471,10 @@ extern "C" vgx_status batch_iterate(vgx_batch* b, int32_t iteration, vgx_iter_re
   int* krec = batch_krec(b->pinned_state);
   for (int k = 0; k < b->count; ++k) {
     if (b->ctx[k]->n_rec >= MAX_RECORDS) { set_error("batch_iterate: context %d has too many records", k); return VGX_ESTATE; }
+    if (b->ctx[k]->pend_k >= 0) {  // a record left pending on the context's own stream
+      VGX_TRY(vegas_flush_pending(b->ctx[k]));
+      VGX_HIP(hipStreamSynchronize(b->ctx[k]->stream));
+    }
     krec[k] = b->ctx[k]->n_rec;
   }
   b->pinned_state->tile_counter = 0;

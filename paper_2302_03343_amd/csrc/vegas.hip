@@ -379,7 +379,9 @@ __global__ __launch_bounds__(FI_BLOCK) void k_flow_iter(VegasArgs a, F f, FlowIt
 // RMAXR); the groups are then merged in a fixed order: across the 8 groups
 // of a wave by shuffles, then across the 16 waves through LDS.  Workgroup 0
 // (which owns S1 and S2) turns (S1, S2, n) into the iteration record and
-// updates the combination.
+// updates the combination, or, with defer set, stores only S1 and S2 in the
+// record: the record is then completed by the next refinement, in a
+// workgroup of its own beside the dimensions' workgroups, or by k_finalize.
 // ---------------------------------------------------------------------------
 constexpr int RBLOCK = 1024;
 constexpr int RCOLS = 8;
@@ -389,7 +391,8 @@ constexpr int RMAXROWS = RGROUPS * RMAXR;
 
 __global__ __launch_bounds__(RBLOCK) void k_reduce(const double* __restrict__ partials, int rows, int pstride,
                                                    int ncols, double* __restrict__ hist_out, int64_t n,
-                                                   IterRecord* __restrict__ rec, int k_rec, Combined* __restrict__ comb) {
+                                                   IterRecord* __restrict__ rec, int k_rec, Combined* __restrict__ comb,
+                                                   int defer) {
   __shared__ double ss[RBLOCK / 64][RCOLS], sc[RBLOCK / 64][RCOLS];
   __shared__ double tot[RCOLS];
   const int cl = threadIdx.x % RCOLS, grp = threadIdx.x / RCOLS;
@@ -432,13 +435,32 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const double* __restrict__ pa
     if (col >= 4 && col < ncols) hist_out[col - 4] = v;
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < 64)
-    finalize_record(tot[0] + tot[1], tot[2] + tot[3], n, rec, k_rec, comb);
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    if (!defer) {
+      finalize_record(tot[0] + tot[1], tot[2] + tot[3], n, rec, k_rec, comb);
+    } else if (threadIdx.x == 0) {
+      rec[k_rec].s1 = tot[0] + tot[1];
+      rec[k_rec].s2 = tot[2] + tot[3];
+    }
+  }
 }
 
+// Refinement, one workgroup per dimension; with k_pend >= 0 the grid has one
+// more workgroup, which completes the deferred record k_pend of n_pend
+// samples from the S1 and S2 stored in it (the refinement does not read it).
 __global__ __launch_bounds__(64) void k_refine(double* __restrict__ edges, const double* __restrict__ hist, int nb,
-                                               double alpha) {
+                                               double alpha, IterRecord* __restrict__ rec, int k_pend, int64_t n_pend,
+                                               Combined* __restrict__ comb) {
+  if (k_pend >= 0 && blockIdx.x == gridDim.x - 1) {
+    finalize_record(rec[k_pend].s1, rec[k_pend].s2, n_pend, rec, k_pend, comb);
+    return;
+  }
   refine_dim(edges + (size_t)blockIdx.x * (nb + 1), hist + (size_t)blockIdx.x * nb, nb, alpha);
+}
+
+__global__ __launch_bounds__(64) void k_finalize(IterRecord* __restrict__ rec, int k, int64_t n,
+                                                 Combined* __restrict__ comb) {
+  finalize_record(rec[k].s1, rec[k].s2, n, rec, k, comb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1107,12 +1129,20 @@ vgx_status launch_sample(vgx_vegas* v, int64_t first, int64_t n, int32_t it, dou
   return VGX_EINVAL;
 }
 
-vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n) {
+// Reduce the partial rows into the histogram and record n_rec.  With defer,
+// the record keeps only S1 and S2 until vegas_refine or vegas_flush_pending
+// completes it (the context notes it as pending).
+vgx_status launch_reduce(vgx_vegas* v, int rows, int ncols, int64_t n, bool defer = false) {
   VGX_CHECK(rows >= 1 && rows <= RMAXROWS, "reduce: %d partial rows (1..%d)", rows, RMAXROWS);
+  VGX_CHECK(v->pend_k < 0, "reduce: record %d is still pending", v->pend_k);
   const int blocks = (ncols + RCOLS - 1) / RCOLS;
   hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(RBLOCK), 0, v->stream, v->partials, rows, v->pstride, ncols,
-                     v->hist, n, v->rec, v->n_rec, v->comb);
+                     v->hist, n, v->rec, v->n_rec, v->comb, defer ? 1 : 0);
   VGX_HIP(hipGetLastError());
+  if (defer) {
+    v->pend_k = v->n_rec;
+    v->pend_n = n;
+  }
   return VGX_OK;
 }
 
@@ -1187,6 +1217,14 @@ vgx_status read_record(vgx_vegas* v, int k, vgx_iter_result* out, RecordKind kin
 
 }  // namespace
 
+vgx_status vegas_flush_pending(vgx_vegas* v) {
+  if (v->pend_k < 0) return VGX_OK;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, v->stream, v->rec, v->pend_k, v->pend_n, v->comb);
+  VGX_HIP(hipGetLastError());
+  v->pend_k = -1;
+  return VGX_OK;
+}
+
 extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_vegas** out) {
   VGX_CHECK(c && out, "vegas_create: null argument");
   *out = nullptr;
@@ -1235,27 +1273,28 @@ extern "C" vgx_status vegas_create(const vgx_vegas_cfg* c, void* stream, vgx_veg
   return VGX_OK;
 }
 
-static vgx_status iterate_enqueue(vgx_vegas* v, int64_t n, int32_t iteration) {
+static vgx_status iterate_enqueue(vgx_vegas* v, int64_t n, int32_t iteration, bool defer) {
   VGX_CHECK(v, "vegas_iterate: null context");
   VGX_CHECK(n >= 2, "vegas_iterate: need n >= 2 samples");
   if (v->n_rec >= MAX_RECORDS) { set_error("vegas_iterate: more than %d stored estimates", MAX_RECORDS); return VGX_ESTATE; }
+  VGX_TRY(vegas_flush_pending(v));
   VGX_TRY(timed_begin(v));
   VGX_TRY(launch_philox_iter(v, n, iteration));
   VGX_TRY(timed_end(v));
-  VGX_TRY(launch_reduce(v, grid_for(v, n), v->pstride, n));
+  VGX_TRY(launch_reduce(v, grid_for(v, n), v->pstride, n, defer));
   v->have_hist = true;
   return VGX_OK;
 }
 
 extern "C" vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, vgx_iter_result* out) {
-  VGX_TRY(iterate_enqueue(v, n, iteration));
+  VGX_TRY(iterate_enqueue(v, n, iteration, false));
   v->comb_fresh = false;
   const int k = v->n_rec++;
   return read_record(v, k, out, REC_PLAIN);
 }
 
 extern "C" vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration) {
-  VGX_TRY(iterate_enqueue(v, n, iteration));
+  VGX_TRY(iterate_enqueue(v, n, iteration, true));
   v->comb_fresh = false;
   v->n_rec++;
   return VGX_OK;
@@ -1264,8 +1303,11 @@ extern "C" vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t itera
 extern "C" vgx_status vegas_refine(vgx_vegas* v) {
   VGX_CHECK(v, "vegas_refine: null context");
   if (!v->have_hist) { set_error("vegas_refine: no histogram (run vegas_iterate first)"); return VGX_ESTATE; }
-  hipLaunchKernelGGL(k_refine, dim3(v->dim), dim3(64), 0, v->stream, v->edges, v->hist, v->nb, v->alpha);
+  const int kp = v->pend_k;
+  hipLaunchKernelGGL(k_refine, dim3(v->dim + (kp >= 0 ? 1 : 0)), dim3(64), 0, v->stream, v->edges, v->hist, v->nb,
+                     v->alpha, v->rec, kp, v->pend_n, v->comb);
   VGX_HIP(hipGetLastError());
+  v->pend_k = -1;
   return VGX_OK;
 }
 
@@ -1279,6 +1321,7 @@ extern "C" vgx_status vegas_result(vgx_vegas* v, double* mean, double* sigma, do
     if (n_used) *n_used = 0;
     return VGX_OK;
   }
+  VGX_TRY(vegas_flush_pending(v));
   if (!v->comb_fresh) {
     VGX_HIP(hipMemcpyAsync(h, v->comb, sizeof(Combined), hipMemcpyDeviceToHost, v->stream));
     VGX_HIP(hipStreamSynchronize(v->stream));
@@ -1295,6 +1338,7 @@ extern "C" vgx_status vegas_results(vgx_vegas* v, vgx_iter_result* out, int32_t 
   VGX_CHECK(v && count && (cap == 0 || out), "vegas_results: bad argument");
   const int m = v->n_rec < cap ? v->n_rec : cap;
   IterRecord* h = (IterRecord*)v->pinned;
+  VGX_TRY(vegas_flush_pending(v));
   if (m > 0) {
     VGX_HIP(hipMemcpyAsync(h, v->rec, sizeof(IterRecord) * m, hipMemcpyDeviceToHost, v->stream));
     VGX_HIP(hipStreamSynchronize(v->stream));
@@ -1312,6 +1356,7 @@ extern "C" vgx_status vegas_results(vgx_vegas* v, vgx_iter_result* out, int32_t 
 
 extern "C" vgx_status vegas_reset_results(vgx_vegas* v) {
   VGX_CHECK(v, "vegas_reset_results: null context");
+  v->pend_k = -1;  // a record still pending is discarded with the rest
   v->n_rec = 0;
   v->comb_fresh = false;
   VGX_HIP(hipMemsetAsync(v->comb, 0, sizeof(Combined), v->stream));
@@ -1360,6 +1405,7 @@ extern "C" vgx_status vegas_iterate_points(vgx_vegas* v, int64_t n, const double
   VGX_CHECK(v, "vegas_iterate_points: null context");
   VGX_CHECK(n >= 2 && y, "vegas_iterate_points: need n >= 2 and points");
   if (v->n_rec >= MAX_RECORDS) { set_error("vegas_iterate_points: too many stored estimates"); return VGX_ESTATE; }
+  VGX_TRY(vegas_flush_pending(v));
   VGX_TRY(timed_begin(v));
   VGX_TRY(launch_points_iter(v, n, y, logq));
   VGX_TRY(timed_end(v));
@@ -1380,6 +1426,7 @@ extern "C" vgx_status flow_vegas_iterate(vgx_flow* f, vgx_vegas* v, int64_t n, u
   if (v->n_rec >= MAX_RECORDS) { set_error("flow_vegas_iterate: too many stored estimates"); return VGX_ESTATE; }
   FlowIterArgs fa{fv.desc, fv.fw, fv.bias, 0, (uint32_t)iteration, stream_id | (1u << 23), (uint32_t)seed,
                   (uint32_t)(seed >> 32)};
+  VGX_TRY(vegas_flush_pending(v));
   VGX_TRY(flow_order_before(f, v->stream));
   VGX_TRY(timed_begin(v));
   int grid = 0;

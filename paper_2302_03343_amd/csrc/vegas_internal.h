@@ -152,7 +152,18 @@ __device__ __forceinline__ Comp wave_merge(Comp a) {
 // the records (lane l takes l, l+64, ...) so that the cost per iteration does
 // not grow with the number of stored estimates; lane 0 writes the results.
 __device__ inline void finalize_record(double s1, double s2, int64_t n, IterRecord* rec, int k_rec, Combined* comb) {
+  // no contraction into FMAs, so that every kernel that inlines this gives the same bits
+#pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
+  // this lane's first stored record (k = lane), read before record k_rec is
+  // written so that the read overlaps the caller's
+  double mean0 = 0.0, var0 = 0.0;
+  bool fin0 = false;
+  if (lane < k_rec) {
+    mean0 = rec[lane].mean;
+    var0 = rec[lane].var;
+    fin0 = rec[lane].finite;
+  }
   IterRecord r;
   r.s1 = s1;
   r.s2 = s2;
@@ -167,6 +178,7 @@ __device__ inline void finalize_record(double s1, double s2, int64_t n, IterReco
   // the store lane 0 has just issued
   auto mean_var = [&](int k, double& mean, double& var) -> bool {
     if (k == k_rec) { mean = r.mean; var = r.var; return r.finite; }
+    if (k == lane) { mean = mean0; var = var0; return fin0; }
     mean = rec[k].mean;
     var = rec[k].var;
     return rec[k].finite;
@@ -311,6 +323,8 @@ struct vgx_vegas {
   void* pinned = nullptr;           // host readback (IterRecord + Combined + grid)
   int n_rec = 0;
   bool comb_fresh = false;           // the host copy of the combination (in pinned) is current
+  int pend_k = -1;                  // record holding only S1, S2 until the next refinement completes it (< 0: none)
+  int64_t pend_n = 0;               // its sample count
   double judge_var = -1.0;          // n var(E) of the latest plain iteration read back (< 0: none)
   bool have_hist = false;
   // kernel timing: event pairs recorded around the fused kernel, read back
@@ -324,3 +338,8 @@ struct vgx_vegas {
   double t_ms = 0.0;
   int64_t t_launches = 0;
 };
+
+// Completes a record that vegas_iterate_async left pending (enqueued on the
+// context's stream; nothing when none is pending).  Every path that reads
+// the records or the combination, or adds a record, calls it first.
+vgx_status vegas_flush_pending(vgx_vegas* v);

@@ -154,3 +154,82 @@ def test_kernel_timing_samples_one_launch_in_k(vgx):
             vgx._check(vgx._c["vegas_set_timing"](v, -1), "vegas_set_timing")
     finally:
         vgx.vegas_destroy(v)
+
+
+def test_deferred_records_match_synchronous_iterations(vgx):
+    """vegas_iterate_async leaves its record holding S1 and S2 only; the next
+    refinement completes it in a workgroup of its own, and every other call
+    that reads or adds records completes it first.  A context driven through
+    each of those routes must hold, bit for bit, the records, combination
+    and grid of one driven by vegas_iterate."""
+    import torch
+    print("deferred records: async routes against synchronous iterations", flush=True)
+    n = 150_001
+    a, b = _gauss_ctx(vgx, seed=21), _gauss_ctx(vgx, seed=21)
+    ba = bb = None
+
+    def same(where, grids=True):
+        ra, rb = vgx.vegas_results(a), vgx.vegas_results(b)
+        assert len(ra) == len(rb), where
+        for k, (x, y) in enumerate(zip(ra, rb)):
+            for key in ("mean", "var", "s1", "s2", "n"):
+                assert x[key] == y[key], (where, k, key, x[key], y[key])
+        ca, cb = vgx.vegas_result(a), vgx.vegas_result(b)
+        assert ca == cb, (where, ca, cb)
+        if grids:
+            assert np.array_equal(vgx.vegas_get_grid(a, 4, 50), vgx.vegas_get_grid(b, 4, 50)), where
+
+    try:
+        # completed by the refinement's extra workgroup
+        vgx.vegas_iterate(a, n, 0); vgx.vegas_refine(a)
+        vgx.vegas_iterate_async(b, n, 0); vgx.vegas_refine(b)
+        same("refine")
+        # completed by the next iteration (no refinement in between)
+        vgx.vegas_iterate(a, n, 1)
+        vgx.vegas_iterate_async(b, n, 1)
+        vgx.vegas_iterate(a, n, 2); vgx.vegas_refine(a)
+        vgx.vegas_iterate_async(b, n, 2); vgx.vegas_refine(b)
+        same("next iteration")
+        # completed by the readbacks
+        vgx.vegas_iterate(a, n, 3)
+        vgx.vegas_iterate_async(b, n, 3)
+        assert vgx.vegas_result(a) == vgx.vegas_result(b)
+        vgx.vegas_iterate(a, n, 4)
+        vgx.vegas_iterate_async(b, n, 4)
+        same("results")
+        # completed before caller points are estimated
+        y = torch.rand((4, 100_003), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+        vgx.vegas_iterate(a, n, 5)
+        vgx.vegas_iterate_async(b, n, 5)
+        pa = vgx.vegas_iterate_points(a, y)
+        pb = vgx.vegas_iterate_points(b, y)
+        assert pa["mean"] == pb["mean"] and pa["var"] == pb["var"]
+        same("points")
+        # completed before a batched iteration of the context
+        vgx.vegas_iterate(a, n, 6)
+        vgx.vegas_iterate_async(b, n, 6)
+        ba = vgx.batch_create([a], [n])
+        bb = vgx.batch_create([b], [n])
+        assert vgx.batch_iterate(ba, 7, 1) == vgx.batch_iterate(bb, 7, 1)
+        # the batch refines too, from histograms summed by LDS atomics in an
+        # order that varies from run to run: its grids agree only to rounding
+        same("batch", grids=False)
+        ga, gb = vgx.vegas_get_grid(a, 4, 50), vgx.vegas_get_grid(b, 4, 50)
+        assert np.allclose(ga, gb, rtol=0, atol=1e-12)
+        vgx.vegas_set_grid(b, ga)
+        # a pending record is discarded with the others
+        vgx.vegas_iterate(a, n, 8)
+        vgx.vegas_iterate_async(b, n, 8)
+        vgx.vegas_reset_results(a)
+        vgx.vegas_reset_results(b)
+        assert len(vgx.vegas_results(b)) == 0 and vgx.vegas_result(b)["n_used"] == 0
+        vgx.vegas_iterate(a, n, 9); vgx.vegas_refine(a)
+        vgx.vegas_iterate_async(b, n, 9); vgx.vegas_refine(b)
+        same("reset")
+        assert len(vgx.vegas_results(b)) == 1
+    finally:
+        for bt in (ba, bb):
+            if bt is not None:
+                vgx.batch_destroy(bt)
+        vgx.vegas_destroy(a)
+        vgx.vegas_destroy(b)
