@@ -301,7 +301,12 @@ vgx_status vegas_create(const vgx_vegas_cfg* cfg, void* stream, vgx_vegas** out)
 vgx_status vegas_iterate(vgx_vegas* v, int64_t n, int32_t iteration, vgx_iter_result* out_host);
 
 /* Same as vegas_iterate but async: the result stays on the device (read it
- * with vegas_results).  Lets a caller queue many iterations back to back. */
+ * with vegas_results).  Lets a caller queue many iterations back to back.
+ * The estimate and the combination are completed later on the context's
+ * stream: by the next vegas_refine (beside the refinement, in the same
+ * launch), or else first thing in the next call that reads or adds
+ * estimates (vegas_result(s), any iterate, batch_iterate); the values are
+ * bit-identical to vegas_iterate's.  vegas_reset_results discards it. */
 vgx_status vegas_iterate_async(vgx_vegas* v, int64_t n, int32_t iteration);
 
 /* Refine the grid from the last iteration's histogram (async).  Thesis:
